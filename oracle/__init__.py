@@ -1,0 +1,153 @@
+"""FP64 CPU oracle of the Gaussian blend (binning, forward, backward).
+
+TEST INFRASTRUCTURE ONLY: the test suite, the smoke check and the benchmark's CPU-baseline leg
+may call this; the GPU library never does. It shares no code with the GPU library. The C source
+(``gsoracle.c``) states what it computes and which reading of the paper it takes.
+
+Inputs may be FP32 arrays (they are promoted exactly to FP64) or FP64 arrays (finite
+differences). Outputs are FP64.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "gsoracle.c")
+_LIB_PATH = os.path.join(_HERE, "libgsoracle.so")
+TILE = 16
+
+_lib = None
+
+
+def build(force: bool = False) -> str:
+    """Compile the oracle with gcc (plain FP64: no fast-math, no FMA contraction)."""
+    if force or not os.path.exists(_LIB_PATH) or os.path.getmtime(_LIB_PATH) < os.path.getmtime(_SRC):
+        tmp = _LIB_PATH + f".tmp{os.getpid()}"
+        subprocess.check_call(["gcc", "-O2", "-std=c11", "-fopenmp", "-fno-fast-math",
+                               "-ffp-contract=off", "-fPIC", "-shared", _SRC, "-o", tmp, "-lm"])
+        os.replace(tmp, _LIB_PATH)
+    return _LIB_PATH
+
+
+def _load():
+    global _lib
+    if _lib is None:
+        lib = ctypes.CDLL(build())
+        P = ctypes.c_void_p
+        i64, i32 = ctypes.c_int64, ctypes.c_int32
+        lib.orc_bin_count.argtypes = [P, P, i64, i32, i32]
+        lib.orc_bin_count.restype = i64
+        lib.orc_bin.argtypes = [P, P, P, i64, i32, i32, i64, P, P]
+        lib.orc_bin.restype = i64
+        lib.orc_forward.argtypes = [i32, i32, P, P, P, P, P, P, P, P, P, P, P, P]
+        lib.orc_forward.restype = None
+        lib.orc_backward.argtypes = [i32, i32, P, P, P, P, P, P, P, i64, P, P, P, P, P]
+        lib.orc_backward.restype = None
+        lib.orc_threads.restype = ctypes.c_int
+        lib.orc_set_threads.argtypes = [ctypes.c_int]
+        _lib = lib
+    return _lib
+
+
+def _f64(a) -> np.ndarray:
+    return np.ascontiguousarray(a, dtype=np.float64)
+
+
+def _ptr(a: np.ndarray):
+    return a.ctypes.data_as(ctypes.c_void_p)
+
+
+def threads() -> int:
+    return int(_load().orc_threads())
+
+
+def set_threads(n: int) -> None:
+    _load().orc_set_threads(int(n))
+
+
+def grid(W: int, H: int) -> tuple[int, int]:
+    return (W + TILE - 1) // TILE, (H + TILE - 1) // TILE
+
+
+def bin_tiles(means2d, radii, depths, W: int, H: int) -> tuple[np.ndarray, np.ndarray]:
+    """(point_list u32[P], ranges u32[n_tiles][2]) sorted by (tile, depth, index)."""
+    lib = _load()
+    m, d = _f64(means2d), _f64(depths)
+    r = np.ascontiguousarray(radii, dtype=np.int32)
+    n = r.shape[0]
+    total = lib.orc_bin_count(_ptr(m), _ptr(r), n, W, H)
+    gx, gy = grid(W, H)
+    point_list = np.zeros(max(total, 1), np.uint32)
+    ranges = np.zeros((gx * gy, 2), np.uint32)
+    got = lib.orc_bin(_ptr(m), _ptr(r), _ptr(d), n, W, H, total, _ptr(point_list), _ptr(ranges))
+    assert got == total
+    return point_list[:total], ranges
+
+
+def forward(W: int, H: int, ranges, point_list, means2d, conics, opacity, colors,
+            bg=(0.0, 0.0, 0.0)) -> dict[str, np.ndarray]:
+    """image f64[3][H][W], final_T f64[H][W], last_contrib i32[H][W], n_eval i32[H][W],
+    margin f64[H][W]."""
+    lib = _load()
+    rg = np.ascontiguousarray(ranges, dtype=np.uint32)
+    pl = np.ascontiguousarray(point_list, dtype=np.uint32)
+    if pl.size == 0:
+        pl = np.zeros(1, np.uint32)
+    m, c, o, col, b = _f64(means2d), _f64(conics), _f64(opacity), _f64(colors), _f64(bg)
+    image = np.empty((3, H, W), np.float64)
+    final_T = np.empty((H, W), np.float64)
+    last = np.empty((H, W), np.int32)
+    n_eval = np.empty((H, W), np.int32)
+    margin = np.empty((H, W), np.float64)
+    lib.orc_forward(W, H, _ptr(rg), _ptr(pl), _ptr(m), _ptr(c), _ptr(o), _ptr(col), _ptr(b),
+                    _ptr(image), _ptr(final_T), _ptr(last), _ptr(n_eval), _ptr(margin))
+    return {"image": image, "final_T": final_T, "last_contrib": last, "n_eval": n_eval,
+            "margin": margin}
+
+
+def backward(W: int, H: int, ranges, point_list, means2d, conics, opacity, colors, dL_dimage,
+             bg=(0.0, 0.0, 0.0)) -> dict[str, np.ndarray]:
+    """Gradients of L = sum(dL_dimage * image): dmeans2d [N][2], dconics [N][3] (A, B, C),
+    dopacity [N], dcolors [N][3]."""
+    lib = _load()
+    rg = np.ascontiguousarray(ranges, dtype=np.uint32)
+    pl = np.ascontiguousarray(point_list, dtype=np.uint32)
+    if pl.size == 0:
+        pl = np.zeros(1, np.uint32)
+    m, c, o, col, b = _f64(means2d), _f64(conics), _f64(opacity), _f64(colors), _f64(bg)
+    g = _f64(dL_dimage)
+    n = o.shape[0]
+    out = {"dmeans2d": np.empty((n, 2)), "dconics": np.empty((n, 3)),
+           "dopacity": np.empty(n), "dcolors": np.empty((n, 3))}
+    lib.orc_backward(W, H, _ptr(rg), _ptr(pl), _ptr(m), _ptr(c), _ptr(o), _ptr(col), _ptr(b), n,
+                     _ptr(g), _ptr(out["dmeans2d"]), _ptr(out["dconics"]), _ptr(out["dopacity"]),
+                     _ptr(out["dcolors"]))
+    return out
+
+
+def render(scene: dict, bg=(0.0, 0.0, 0.0)) -> dict[str, np.ndarray]:
+    """bin + forward of a scene dict (see ``gsinputs``)."""
+    W, H = scene["width"], scene["height"]
+    pl, rg = bin_tiles(scene["means2d"], scene["radii"], scene["depths"], W, H)
+    out = forward(W, H, rg, pl, scene["means2d"], scene["conics"], scene["opacity"],
+                  scene["colors"], bg)
+    out["point_list"], out["ranges"] = pl, rg
+    return out
+
+
+def work_counts(fwd: dict, ranges) -> dict[str, int]:
+    """E = per-pixel evaluations until stop (sum over pixels); F = entries a tile must fetch
+    (max over its pixels of the stop position, summed over tiles); P = pairs."""
+    n_eval = fwd["n_eval"]
+    H, W = n_eval.shape
+    gx, gy = grid(W, H)
+    pad = np.zeros((gy * TILE, gx * TILE), np.int64)
+    pad[:H, :W] = n_eval
+    F = int(pad.reshape(gy, TILE, gx, TILE).max(axis=(1, 3)).sum())
+    rg = np.asarray(ranges, np.int64)
+    return {"E": int(n_eval.astype(np.int64).sum()), "F": F,
+            "P": int((rg[:, 1] - rg[:, 0]).sum())}

@@ -1,0 +1,307 @@
+/*
+ * FP64 CPU oracle for tile-based front-to-back blending of projected 2D Gaussians.
+ *
+ * TEST INFRASTRUCTURE ONLY. This file is the plain, slow, obviously-correct definition that the
+ * GPU library is checked against. It shares no code, header, table or constant generator with the
+ * GPU library, and nothing in the product path may link or call it: only the test suite, the
+ * smoke check and the benchmark's CPU-baseline leg do.
+ *
+ * What it computes (GEMM-GS, DAC'26, arXiv 2604.02120):
+ *   - orc_bin_*      duplication with tile|depth keys and depth sort (§2.1(b)-(c)), tile ranges.
+ *   - orc_forward    volume rendering, Eq. (volume-render), with the per-pixel loop of Alg. 1:
+ *                    exponent of Eq. (power), alpha of Eq. (alpha), 1/255 alpha-skipping and
+ *                    early termination.
+ *   - orc_backward   gradient of L = sum_p g_p . C_p with respect to the stored 2D means,
+ *                    conic scalars (A, B, C), opacities and colours, derived by the product rule
+ *                    from Eq. (volume-render) and Eq. (alpha) (the paper has no backward pass).
+ *
+ * The GEMM form of the paper (Eq. (power rewritten)) is an exact algebraic identity, so the plain
+ * definition above is also the oracle of the GEMM path; it is deliberately not used here.
+ *
+ * Readings of points where the paper is silent or self-contradictory (each also listed in the
+ * design notes of the repository):
+ *   - alpha-skip is "alpha < 1/255" (Alg. 1 writes "<="), thresholds are the FP32 constants
+ *     1/255, 1e-4 and 0.99 promoted exactly to FP64;
+ *   - early termination tests T' = T (1 - alpha) < 1e-4 BEFORE blending; the Gaussian that trips
+ *     it is not blended and T keeps its previous value (Alg. 1 updates T before the test and
+ *     checks "T <= 0", which contradicts Eq. (volume-render));
+ *   - alpha = min(0.99, o exp(min(power, 0)));
+ *   - pixel (px, py) sits at integer coordinates;
+ *   - a Gaussian with radius r > 0 covers tiles tx in [floor((x - r)/16), floor((x + r + 15)/16))
+ *     (same for y), clamped to the grid; r = 0 means "not rendered";
+ *   - the list of a tile is ordered by depth, ties broken by the Gaussian's index;
+ *   - last_contrib is the 1-based position, within the tile's list, of the last blended
+ *     Gaussian (0 = none);
+ *   - derivatives are taken with respect to the stored scalars (A, B, C) (full -dx dy for B) and
+ *     pixel-space means; a clamp that is active (o G >= 0.99, or power > 0) passes no gradient.
+ *
+ * Numerics: plain double arithmetic, built with -ffp-contract=off and without fast-math.
+ * Threads: OpenMP over tiles (results do not depend on the thread count, except the summation
+ * order of the backward's atomic FP64 adds).
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+#define ORC_TILE 16
+
+/* FP32 thresholds promoted exactly to FP64. */
+static double tau_cull(void) { return (double)(1.0f / 255.0f); }
+static double t_stop(void) { return (double)1e-4f; }
+static double alpha_max(void) { return (double)0.99f; }
+
+int orc_threads(void) {
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
+}
+
+void orc_set_threads(int n) {
+#ifdef _OPENMP
+    if (n > 0) omp_set_num_threads(n);
+#else
+    (void)n;
+#endif
+}
+
+static int64_t clamp_i64(int64_t v, int64_t lo, int64_t hi) { return v < lo ? lo : (v > hi ? hi : v); }
+
+/* Tiles covered by Gaussian i: [tx0, tx1) x [ty0, ty1); empty when r <= 0.
+ * The arithmetic is exact in FP64 for the FP32 means and integer radii this library accepts. */
+static void tile_rect(double x, double y, int32_t r, int64_t gx, int64_t gy,
+                      int64_t *tx0, int64_t *tx1, int64_t *ty0, int64_t *ty1) {
+    if (r <= 0) { *tx0 = *tx1 = *ty0 = *ty1 = 0; return; }
+    *tx0 = clamp_i64((int64_t)floor((x - r) / ORC_TILE), 0, gx);
+    *tx1 = clamp_i64((int64_t)floor((x + r + ORC_TILE - 1) / ORC_TILE), 0, gx);
+    *ty0 = clamp_i64((int64_t)floor((y - r) / ORC_TILE), 0, gy);
+    *ty1 = clamp_i64((int64_t)floor((y + r + ORC_TILE - 1) / ORC_TILE), 0, gy);
+}
+
+/* Number of (tile, Gaussian) pairs. */
+int64_t orc_bin_count(const double *means2d, const int32_t *radii, int64_t n, int32_t W, int32_t H) {
+    int64_t gx = (W + ORC_TILE - 1) / ORC_TILE, gy = (H + ORC_TILE - 1) / ORC_TILE, total = 0;
+    for (int64_t i = 0; i < n; ++i) {
+        int64_t a, b, c, d;
+        tile_rect(means2d[2 * i], means2d[2 * i + 1], radii[i], gx, gy, &a, &b, &c, &d);
+        total += (b - a) * (d - c);
+    }
+    return total;
+}
+
+typedef struct { int64_t tile; double depth; int64_t idx; } orc_pair;
+
+static int pair_less(const void *pa, const void *pb) {
+    const orc_pair *a = (const orc_pair *)pa, *b = (const orc_pair *)pb;
+    if (a->tile != b->tile) return a->tile < b->tile ? -1 : 1;
+    if (a->depth != b->depth) return a->depth < b->depth ? -1 : 1;
+    if (a->idx != b->idx) return a->idx < b->idx ? -1 : 1;
+    return 0;
+}
+
+/* Duplicate, sort by (tile, depth, index), extract ranges.
+ * point_list: u32[capacity]; ranges: u32[gx*gy][2] as [start, end), [0, 0) when empty.
+ * Returns the pair count, or -1 if it exceeds capacity (nothing written then). */
+int64_t orc_bin(const double *means2d, const int32_t *radii, const double *depths, int64_t n,
+                int32_t W, int32_t H, int64_t capacity, uint32_t *point_list, uint32_t *ranges) {
+    int64_t gx = (W + ORC_TILE - 1) / ORC_TILE, gy = (H + ORC_TILE - 1) / ORC_TILE;
+    int64_t total = orc_bin_count(means2d, radii, n, W, H);
+    if (total > capacity) return -1;
+    orc_pair *pairs = (orc_pair *)malloc(sizeof(orc_pair) * (size_t)(total > 0 ? total : 1));
+    int64_t k = 0;
+    for (int64_t i = 0; i < n; ++i) {
+        int64_t tx0, tx1, ty0, ty1;
+        tile_rect(means2d[2 * i], means2d[2 * i + 1], radii[i], gx, gy, &tx0, &tx1, &ty0, &ty1);
+        for (int64_t ty = ty0; ty < ty1; ++ty)
+            for (int64_t tx = tx0; tx < tx1; ++tx) {
+                pairs[k].tile = ty * gx + tx;
+                pairs[k].depth = depths[i];
+                pairs[k].idx = i;
+                ++k;
+            }
+    }
+    qsort(pairs, (size_t)total, sizeof(orc_pair), pair_less);
+    memset(ranges, 0, sizeof(uint32_t) * 2 * (size_t)(gx * gy));
+    for (int64_t p = 0; p < total; ++p) {
+        point_list[p] = (uint32_t)pairs[p].idx;
+        int64_t t = pairs[p].tile;
+        if (p == 0 || pairs[p - 1].tile != t) ranges[2 * t] = (uint32_t)p;
+        if (p == total - 1 || pairs[p + 1].tile != t) ranges[2 * t + 1] = (uint32_t)(p + 1);
+    }
+    free(pairs);
+    return total;
+}
+
+/* Exponent of Eq. (power): -1/2 A dx^2 - B dx dy - 1/2 C dy^2, dx = x_g - x_p, dy = y_g - y_p. */
+static double gauss_power(const double *conic, double dx, double dy) {
+    return -0.5 * (conic[0] * dx * dx + conic[2] * dy * dy) - conic[1] * dx * dy;
+}
+
+static double rel_margin(double v, double thr) { return fabs(v - thr) / thr; }
+
+/* Forward blend of every pixel. image is planar [3][H][W]; final_T and last_contrib are [H][W].
+ * n_eval (optional): list entries examined per pixel, including the one that stops it.
+ * margin (optional): smallest relative distance of any alpha-skip or stop decision to its
+ * threshold, per pixel (decisions this close can flip under rounding). */
+void orc_forward(int32_t W, int32_t H, const uint32_t *ranges, const uint32_t *point_list,
+                 const double *means2d, const double *conics, const double *opacity,
+                 const double *colors, const double *bg, double *image, double *final_T,
+                 int32_t *last_contrib, int32_t *n_eval, double *margin) {
+    const int64_t gx = (W + ORC_TILE - 1) / ORC_TILE, gy = (H + ORC_TILE - 1) / ORC_TILE;
+    const int64_t HW = (int64_t)H * W;
+    const double tau = tau_cull(), tstop = t_stop(), amax = alpha_max();
+#pragma omp parallel for schedule(dynamic, 4)
+    for (int64_t t = 0; t < gx * gy; ++t) {
+        const int64_t tx = t % gx, ty = t / gx;
+        const uint32_t start = ranges[2 * t], end = ranges[2 * t + 1];
+        for (int64_t py = ty * ORC_TILE; py < (ty + 1) * ORC_TILE && py < H; ++py) {
+            for (int64_t px = tx * ORC_TILE; px < (tx + 1) * ORC_TILE && px < W; ++px) {
+                double T = 1.0, acc[3] = {0.0, 0.0, 0.0}, mmin = INFINITY;
+                int32_t last = 0, evals = 0;
+                for (uint32_t n = start; n < end; ++n) {
+                    const int64_t i = point_list[n];
+                    ++evals;
+                    const double dx = means2d[2 * i] - (double)px, dy = means2d[2 * i + 1] - (double)py;
+                    const double power = gauss_power(&conics[3 * i], dx, dy);
+                    double alpha = opacity[i] * exp(power < 0.0 ? power : 0.0);
+                    if (alpha > amax) alpha = amax;
+                    const double m1 = rel_margin(alpha, tau);
+                    if (m1 < mmin) mmin = m1;
+                    if (alpha < tau) continue;
+                    const double Tn = T * (1.0 - alpha);
+                    const double m2 = rel_margin(Tn, tstop);
+                    if (m2 < mmin) mmin = m2;
+                    if (Tn < tstop) break;
+                    for (int c = 0; c < 3; ++c) acc[c] += alpha * T * colors[3 * i + c];
+                    T = Tn;
+                    last = (int32_t)(n - start + 1);
+                }
+                const int64_t p = py * W + px;
+                for (int c = 0; c < 3; ++c) image[c * HW + p] = acc[c] + T * bg[c];
+                final_T[p] = T;
+                last_contrib[p] = last;
+                if (n_eval) n_eval[p] = evals;
+                if (margin) margin[p] = mmin;
+            }
+        }
+    }
+}
+
+/* Largest tile list length (scratch size for the backward). */
+static int64_t max_list(const uint32_t *ranges, int64_t n_tiles) {
+    int64_t m = 0;
+    for (int64_t t = 0; t < n_tiles; ++t)
+        if ((int64_t)ranges[2 * t + 1] - ranges[2 * t] > m) m = (int64_t)ranges[2 * t + 1] - ranges[2 * t];
+    return m;
+}
+
+/* Gradient of L = sum over pixels and channels of dL_dimage * image.
+ * Outputs are overwritten: dmeans2d [N][2], dconics [N][3] (d/dA, d/dB, d/dC), dopacity [N],
+ * dcolors [N][3]. The forward is recomputed in order, keeping every contributor's T. */
+void orc_backward(int32_t W, int32_t H, const uint32_t *ranges, const uint32_t *point_list,
+                  const double *means2d, const double *conics, const double *opacity,
+                  const double *colors, const double *bg, int64_t n, const double *dL_dimage,
+                  double *dmeans2d, double *dconics, double *dopacity, double *dcolors) {
+    const int64_t gx = (W + ORC_TILE - 1) / ORC_TILE, gy = (H + ORC_TILE - 1) / ORC_TILE;
+    const int64_t HW = (int64_t)H * W;
+    const double tau = tau_cull(), tstop = t_stop(), amax = alpha_max();
+    memset(dmeans2d, 0, sizeof(double) * 2 * (size_t)n);
+    memset(dconics, 0, sizeof(double) * 3 * (size_t)n);
+    memset(dopacity, 0, sizeof(double) * (size_t)n);
+    memset(dcolors, 0, sizeof(double) * 3 * (size_t)n);
+    const int64_t cap = max_list(ranges, gx * gy) + 1;
+#pragma omp parallel
+    {
+        /* per-contributor record of the in-order pass */
+        int64_t *c_idx = (int64_t *)malloc(sizeof(int64_t) * (size_t)cap);
+        double *c_alpha = (double *)malloc(sizeof(double) * (size_t)cap);
+        double *c_T = (double *)malloc(sizeof(double) * (size_t)cap);
+        double *c_G = (double *)malloc(sizeof(double) * (size_t)cap);
+        double *c_dx = (double *)malloc(sizeof(double) * (size_t)cap);
+        double *c_dy = (double *)malloc(sizeof(double) * (size_t)cap);
+        int *c_aclamp = (int *)malloc(sizeof(int) * (size_t)cap);
+        int *c_pclamp = (int *)malloc(sizeof(int) * (size_t)cap);
+#pragma omp for schedule(dynamic, 4)
+        for (int64_t t = 0; t < gx * gy; ++t) {
+            const int64_t tx = t % gx, ty = t / gx;
+            const uint32_t start = ranges[2 * t], end = ranges[2 * t + 1];
+            for (int64_t py = ty * ORC_TILE; py < (ty + 1) * ORC_TILE && py < H; ++py) {
+                for (int64_t px = tx * ORC_TILE; px < (tx + 1) * ORC_TILE && px < W; ++px) {
+                    const int64_t p = py * W + px;
+                    double g[3];
+                    for (int c = 0; c < 3; ++c) g[c] = dL_dimage[c * HW + p];
+                    /* in-order pass: the contributors and the T in front of each */
+                    double T = 1.0;
+                    int64_t k = 0;
+                    for (uint32_t m = start; m < end; ++m) {
+                        const int64_t i = point_list[m];
+                        const double dx = means2d[2 * i] - (double)px, dy = means2d[2 * i + 1] - (double)py;
+                        const double power = gauss_power(&conics[3 * i], dx, dy);
+                        const int pclamp = power > 0.0;
+                        const double G = exp(pclamp ? 0.0 : power);
+                        double alpha = opacity[i] * G;
+                        const int aclamp = alpha >= amax;
+                        if (aclamp) alpha = amax;
+                        if (alpha < tau) continue;
+                        const double Tn = T * (1.0 - alpha);
+                        if (Tn < tstop) break;
+                        c_idx[k] = i; c_alpha[k] = alpha; c_T[k] = T; c_G[k] = G;
+                        c_dx[k] = dx; c_dy[k] = dy; c_aclamp[k] = aclamp; c_pclamp[k] = pclamp;
+                        ++k;
+                        T = Tn;
+                    }
+                    const double T_final = T;
+                    double bg_g = 0.0;
+                    for (int c = 0; c < 3; ++c) bg_g += bg[c] * g[c];
+                    /* reverse pass: behind[c] = sum over later contributors of alpha_k T_k c_k */
+                    double behind[3] = {0.0, 0.0, 0.0};
+                    for (int64_t j = k - 1; j >= 0; --j) {
+                        const int64_t i = c_idx[j];
+                        const double a = c_alpha[j], Tj = c_T[j];
+                        /* dC/dalpha_j = T_j c_j - (behind_j + T_final bg) / (1 - alpha_j) */
+                        double dL_da = 0.0;
+                        for (int c = 0; c < 3; ++c)
+                            dL_da += g[c] * (Tj * colors[3 * i + c] - behind[c] / (1.0 - a));
+                        dL_da -= T_final * bg_g / (1.0 - a);
+                        for (int c = 0; c < 3; ++c) {
+                            const double dc = a * Tj * g[c];
+#pragma omp atomic
+                            dcolors[3 * i + c] += dc;
+                        }
+                        if (!c_aclamp[j]) {
+                            const double G = c_G[j];
+                            const double d_o = G * dL_da;
+#pragma omp atomic
+                            dopacity[i] += d_o;
+                            if (!c_pclamp[j]) {
+                                const double dP = opacity[i] * G * dL_da;
+                                const double dx = c_dx[j], dy = c_dy[j];
+                                const double A = conics[3 * i], B = conics[3 * i + 1], C = conics[3 * i + 2];
+                                const double gA = -0.5 * dx * dx * dP, gB = -dx * dy * dP, gC = -0.5 * dy * dy * dP;
+                                const double gx_ = -(A * dx + B * dy) * dP, gy_ = -(B * dx + C * dy) * dP;
+#pragma omp atomic
+                                dconics[3 * i] += gA;
+#pragma omp atomic
+                                dconics[3 * i + 1] += gB;
+#pragma omp atomic
+                                dconics[3 * i + 2] += gC;
+#pragma omp atomic
+                                dmeans2d[2 * i] += gx_;
+#pragma omp atomic
+                                dmeans2d[2 * i + 1] += gy_;
+                            }
+                        }
+                        for (int c = 0; c < 3; ++c) behind[c] += a * Tj * colors[3 * i + c];
+                    }
+                }
+            }
+        }
+        free(c_idx); free(c_alpha); free(c_T); free(c_G); free(c_dx); free(c_dy);
+        free(c_aclamp); free(c_pclamp);
+    }
+}
