@@ -1,0 +1,151 @@
+/*
+ * gsblend — tile-based front-to-back blending of depth-sorted projected 2D Gaussians on
+ * AMD Instinct MI355X (gfx950), with the exponent evaluated either per pixel in FP32 (the
+ * classic form) or as a GEMM on the matrix cores (GEMM-GS, DAC'26, arXiv 2604.02120).
+ *
+ * Conventions shared by every call
+ * --------------------------------
+ *  - Array pointers are DEVICE pointers to contiguous, caller-owned memory (e.g. PyTorch tensors);
+ *    `bg` is a HOST pointer to 3 floats. Nothing here allocates or frees device memory and no call
+ *    synchronises: work is enqueued on `stream` (a hipStream_t; NULL = the default stream).
+ *  - Arguments are validated on the host before anything is enqueued; a call that returns an
+ *    error has enqueued nothing and written nothing. The message of the last error of the calling
+ *    thread is returned by gsb_last_error().
+ *  - Screen tiles are 16x16 pixels; the grid is gx = ceil(W/16) by gy = ceil(H/16) tiles, tile
+ *    index t = ty * gx + tx. Pixel (px, py) sits at integer coordinates. Images are planar
+ *    [3][H][W] FP32; per-pixel maps are [H][W].
+ *  - Gaussian attributes (the data fetched per Gaussian in Alg. 1 of the paper):
+ *      means2d  f32[n][2]  projected centre (x, y), pixels
+ *      conics   f32[n][3]  (A, B, C) of the inverse 2D covariance [[A, B], [B, C]], Eq. (alpha)
+ *      opacity  f32[n]     o in [0, 1]
+ *      colors   f32[n][3]  RGB
+ *      depths   f32[n]     view depth > 0
+ *      radii    i32[n]     screen radius in pixels; 0 = not rendered
+ *    Inputs must be finite, conics positive definite, n < 2^32, |x|, |y| < 2^24. Inputs outside
+ *    that contract give unspecified values but never an out-of-bounds access.
+ *  - Thresholds (FP32): a Gaussian is skipped for a pixel when alpha < 1/255; a pixel stops at the
+ *    first Gaussian whose blend would take its transmittance below 1e-4 (that Gaussian is not
+ *    blended); alpha = min(0.99, o * exp(min(power, 0))).
+ *  - Calls are reentrant; concurrent calls on different streams are allowed.
+ */
+#ifndef GSBLEND_H
+#define GSBLEND_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t gsb_status;
+#define GSB_OK 0
+#define GSB_ERR_INVALID 1      /* bad argument (null pointer, size out of range, bad enum) */
+#define GSB_ERR_CAPACITY 2     /* pair list larger than the caller's capacity */
+#define GSB_ERR_UNSUPPORTED 3  /* device is not gfx950 */
+#define GSB_ERR_HIP 4          /* HIP runtime error (message from hipGetErrorString) */
+
+typedef int32_t gsb_precision;
+#define GSB_FP32_PLAIN 0  /* exponent per pixel in FP32 on the vector ALUs (Alg. 1, Eq. (power)) */
+#define GSB_FP16_GEMM 1   /* exponent as an MFMA product, FP16 hi+lo operands, FP32 accumulate */
+#define GSB_BF16_GEMM 2   /* same with BF16 hi+lo operands */
+
+#define GSB_ABI_VERSION 1
+
+/* Version of this interface (GSB_ABI_VERSION of the library that was loaded). */
+int32_t gsb_abi_version(void);
+
+/* Message of the last failed call on this thread ("" if none). Valid until the next call made by
+ * the same thread. */
+const char *gsb_last_error(void);
+
+/* ---------------------------------------------------------------------------------------------
+ * Binning: duplication with tile|depth keys, depth sort and per-tile ranges (paper §2.1(b)-(c);
+ * the ranges are the per-tile sorted index lists that Alg. 1 and Alg. 2 take as input).
+ *
+ * A Gaussian with radius r > 0 at (x, y) covers the tiles tx in [floor((x - r)/16),
+ * floor((x + r + 15)/16)) and ty likewise, clamped to the grid. Each covered tile gets one pair
+ * with the 64-bit key (t << 32) | bits(depth) and the Gaussian's index as value. Pairs are sorted
+ * by key with a stable sort from Gaussian-major emission order, i.e. by (tile, depth, index), so
+ * the result is unique and reproducible bit for bit.
+ *
+ * Use: gsb_bin_workspace_bytes -> gsb_bin_count -> (read *n_pairs, or use a known bound as the
+ * capacity) -> gsb_bin_fill, with the same workspace (it carries the per-Gaussian offsets).
+ * ------------------------------------------------------------------------------------------- */
+
+/* Workspace size in bytes for n Gaussians, up to pair_capacity pairs, on a W x H image.
+ * Errors: INVALID if n < 0, pair_capacity < 0 or > 2^31 - 1, W or H not in [1, 2^16], or
+ * bytes == NULL. */
+gsb_status gsb_bin_workspace_bytes(int64_t n, int64_t pair_capacity, int32_t W, int32_t H,
+                                   size_t *bytes);
+
+/* Counts the pairs each Gaussian emits and their exclusive prefix sum (kept in `ws`), and writes
+ * the total to the device int64 *n_pairs_dev. Asynchronous on `stream`.
+ * ws: device workspace of ws_bytes >= gsb_bin_workspace_bytes(n, 0, W, H) bytes.
+ * Errors: INVALID for null pointers (means2d/radii may be null only when n == 0), bad sizes or a
+ * too-small workspace; HIP for launch failures. */
+gsb_status gsb_bin_count(const float *means2d, const int32_t *radii, int64_t n, int32_t W,
+                         int32_t H, void *ws, size_t ws_bytes, int64_t *n_pairs_dev,
+                         void *stream);
+
+/* Emits, sorts and ranges the pairs counted by the preceding gsb_bin_count on the same `ws`.
+ * point_list: device u32[pair_capacity], receives the Gaussian index of each sorted pair.
+ * ranges:     device u32[gx*gy][2], receives [start, end) of each tile in point_list, [0, 0) for
+ *             an empty tile.
+ * status_dev: device int32, receives GSB_OK, or GSB_ERR_CAPACITY when the pair count exceeds
+ *             pair_capacity; in that case nothing past pair_capacity is written and the contents
+ *             of point_list/ranges are unspecified.
+ * ws_bytes must be >= gsb_bin_workspace_bytes(n, pair_capacity, W, H).
+ * Errors: INVALID for null pointers, bad sizes, too-small workspace; HIP for launch failures. */
+gsb_status gsb_bin_fill(const float *means2d, const int32_t *radii, const float *depths, int64_t n,
+                        int32_t W, int32_t H, void *ws, size_t ws_bytes, uint32_t *point_list,
+                        int64_t pair_capacity, uint32_t *ranges, int32_t *status_dev,
+                        void *stream);
+
+/* ---------------------------------------------------------------------------------------------
+ * Forward blend (Eq. (volume-render) with the per-pixel loop of Alg. 1; in the GEMM precisions
+ * the exponent comes from M_power = M_g . M_p, Eq. (power rewritten) and Eq. (matrix
+ * multiplication), Alg. 2).
+ *
+ * ranges/point_list: output of binning (u32[gx*gy][2], u32[>= max end]).
+ * bg:        host float[3], background added as T_final * bg.
+ * prec:      GSB_FP32_PLAIN, GSB_FP16_GEMM or GSB_BF16_GEMM.
+ * image:     device f32[3][H][W]  = sum_i alpha_i T_i c_i + T_final * bg.
+ * final_T:   device f32[H][W]     transmittance after the last blended Gaussian.
+ * last_contrib: device i32[H][W]  1-based position, within the tile's list, of the last blended
+ *            Gaussian (0 = none).
+ * Every pixel of the image is written. Errors: INVALID (null pointers, sizes, prec), HIP.
+ * ------------------------------------------------------------------------------------------- */
+gsb_status gsb_blend_forward(int32_t W, int32_t H, const uint32_t *ranges,
+                             const uint32_t *point_list, const float *means2d,
+                             const float *conics, const float *opacity, const float *colors,
+                             int64_t n, const float *bg, gsb_precision prec, float *image,
+                             float *final_T, int32_t *last_contrib, void *stream);
+
+/* ---------------------------------------------------------------------------------------------
+ * Backward blend: gradient of L = sum(dL_dimage * image) with respect to the stored inputs, for
+ * fixed binning. The forward's decisions are replayed exactly (same precision `prec`, same
+ * kernels for the exponent), and transmittance is recovered in reverse from final_T:
+ * T_i = T_{i+1} / (1 - alpha_i).
+ *
+ * final_T, last_contrib: the forward's outputs for the same inputs and `prec`.
+ * dL_dimage: device f32[3][H][W].
+ * Outputs (device, overwritten, not accumulated into):
+ *   dL_dmeans2d f32[n][2], dL_dconics f32[n][3] (d/dA, d/dB, d/dC of the stored scalars),
+ *   dL_dopacity f32[n], dL_dcolors f32[n][3].
+ * A clamp that is active for a pair (alpha at 0.99, or a positive exponent) passes no gradient to
+ * the exponent or opacity. Gradient sums use FP32 atomics, so their rounding is not bit-stable
+ * from run to run. Errors: INVALID, HIP.
+ * ------------------------------------------------------------------------------------------- */
+gsb_status gsb_blend_backward(int32_t W, int32_t H, const uint32_t *ranges,
+                              const uint32_t *point_list, const float *means2d,
+                              const float *conics, const float *opacity, const float *colors,
+                              int64_t n, const float *bg, gsb_precision prec,
+                              const float *final_T, const int32_t *last_contrib,
+                              const float *dL_dimage, float *dL_dmeans2d, float *dL_dconics,
+                              float *dL_dopacity, float *dL_dcolors, void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* GSBLEND_H */

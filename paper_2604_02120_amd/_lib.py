@@ -1,0 +1,119 @@
+"""ctypes binding of libgsblend.so: one Python function per C entry point, same names.
+
+Argument marshalling only. Pointers are passed as integers (device addresses, e.g.
+``tensor.data_ptr()``); ``stream`` is a hipStream_t as an integer (0 = default stream). A
+non-zero status raises :class:`GsbError` carrying the library's message.
+
+The library must have been built (``python -m paper_2604_02120_amd.build``); there is no fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libgsblend.so")
+
+GSB_OK = 0
+GSB_ERR_INVALID = 1
+GSB_ERR_CAPACITY = 2
+GSB_ERR_UNSUPPORTED = 3
+GSB_ERR_HIP = 4
+
+GSB_FP32_PLAIN = 0
+GSB_FP16_GEMM = 1
+GSB_BF16_GEMM = 2
+PRECISIONS = {"fp32": GSB_FP32_PLAIN, "fp16": GSB_FP16_GEMM, "bf16": GSB_BF16_GEMM}
+
+# every function declared in include/gsblend.h
+EXPORTS = ("gsb_abi_version", "gsb_last_error", "gsb_bin_workspace_bytes", "gsb_bin_count",
+           "gsb_bin_fill", "gsb_blend_forward", "gsb_blend_backward")
+
+
+class GsbError(RuntimeError):
+    def __init__(self, status: int, message: str):
+        super().__init__(f"gsblend status {status}: {message}")
+        self.status = status
+
+
+_lib = None
+
+
+def load() -> ctypes.CDLL:
+    """Load libgsblend.so (once). Raises if it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is missing: build it with "
+                           "`python -m paper_2604_02120_amd.build` (hipcc, gfx950)")
+    lib = ctypes.CDLL(LIB_PATH)
+    P, i64, i32, sz = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32, ctypes.c_size_t
+    lib.gsb_abi_version.argtypes = []
+    lib.gsb_abi_version.restype = i32
+    lib.gsb_last_error.argtypes = []
+    lib.gsb_last_error.restype = ctypes.c_char_p
+    lib.gsb_bin_workspace_bytes.argtypes = [i64, i64, i32, i32, ctypes.POINTER(sz)]
+    lib.gsb_bin_count.argtypes = [P, P, i64, i32, i32, P, sz, P, P]
+    lib.gsb_bin_fill.argtypes = [P, P, P, i64, i32, i32, P, sz, P, i64, P, P, P]
+    lib.gsb_blend_forward.argtypes = [i32, i32, P, P, P, P, P, P, i64, P, i32, P, P, P, P]
+    lib.gsb_blend_backward.argtypes = [i32, i32, P, P, P, P, P, P, i64, P, i32, P, P, P, P, P,
+                                       P, P, P]
+    for name in EXPORTS[2:]:
+        getattr(lib, name).restype = i32
+    _lib = lib
+    return lib
+
+
+def _check(status: int) -> None:
+    if status != GSB_OK:
+        raise GsbError(status, gsb_last_error())
+
+
+def _bg(bg) -> ctypes.Array:
+    if bg is None:
+        return None
+    b = (ctypes.c_float * 3)(*[float(v) for v in bg])
+    return b
+
+
+def gsb_abi_version() -> int:
+    return int(load().gsb_abi_version())
+
+
+def gsb_last_error() -> str:
+    return load().gsb_last_error().decode()
+
+
+def gsb_bin_workspace_bytes(n: int, pair_capacity: int, W: int, H: int) -> int:
+    out = ctypes.c_size_t(0)
+    _check(load().gsb_bin_workspace_bytes(n, pair_capacity, W, H, ctypes.byref(out)))
+    return int(out.value)
+
+
+def gsb_bin_count(means2d: int, radii: int, n: int, W: int, H: int, ws: int, ws_bytes: int,
+                  n_pairs_dev: int, stream: int = 0) -> None:
+    _check(load().gsb_bin_count(means2d, radii, n, W, H, ws, ws_bytes, n_pairs_dev, stream))
+
+
+def gsb_bin_fill(means2d: int, radii: int, depths: int, n: int, W: int, H: int, ws: int,
+                 ws_bytes: int, point_list: int, pair_capacity: int, ranges: int,
+                 status_dev: int, stream: int = 0) -> None:
+    _check(load().gsb_bin_fill(means2d, radii, depths, n, W, H, ws, ws_bytes, point_list,
+                               pair_capacity, ranges, status_dev, stream))
+
+
+def gsb_blend_forward(W: int, H: int, ranges: int, point_list: int, means2d: int, conics: int,
+                      opacity: int, colors: int, n: int, bg, prec: int, image: int, final_T: int,
+                      last_contrib: int, stream: int = 0) -> None:
+    _check(load().gsb_blend_forward(W, H, ranges, point_list, means2d, conics, opacity, colors, n,
+                                    _bg(bg), prec, image, final_T, last_contrib, stream))
+
+
+def gsb_blend_backward(W: int, H: int, ranges: int, point_list: int, means2d: int, conics: int,
+                       opacity: int, colors: int, n: int, bg, prec: int, final_T: int,
+                       last_contrib: int, dL_dimage: int, dL_dmeans2d: int, dL_dconics: int,
+                       dL_dopacity: int, dL_dcolors: int, stream: int = 0) -> None:
+    _check(load().gsb_blend_backward(W, H, ranges, point_list, means2d, conics, opacity, colors,
+                                     n, _bg(bg), prec, final_T, last_contrib, dL_dimage,
+                                     dL_dmeans2d, dL_dconics, dL_dopacity, dL_dcolors, stream))

@@ -1,0 +1,178 @@
+// The C ABI of libgsblend (declared in include/gsblend.h): host-side validation, device check,
+// error strings, and dispatch to the binning and blending launchers.
+#include <hip/hip_runtime.h>
+
+#include <stdarg.h>
+#include <stdio.h>
+#include <string.h>
+
+#include "gsb_internal.h"
+
+namespace gsb {
+
+int64_t bin_max_gaussians();
+int64_t bin_max_pairs();
+
+namespace {
+thread_local char g_err[512] = "";
+
+constexpr int32_t kMaxDim = 65536;
+constexpr int kMaxDevices = 64;
+int g_arch_ok[kMaxDevices];   // 0 = unknown, 1 = gfx950, 2 = other
+
+bool aligned(const void *p, size_t a) { return (reinterpret_cast<uintptr_t>(p) % a) == 0; }
+
+gsb_status check_device() {
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return fail(GSB_ERR_HIP, "hipGetDevice: %s", hipGetErrorString(e));
+    if (dev < 0 || dev >= kMaxDevices) return fail(GSB_ERR_UNSUPPORTED, "device id %d out of range", dev);
+    if (g_arch_ok[dev] == 0) {
+        hipDeviceProp_t prop;
+        e = hipGetDeviceProperties(&prop, dev);
+        if (e != hipSuccess) return fail(GSB_ERR_HIP, "hipGetDeviceProperties: %s", hipGetErrorString(e));
+        g_arch_ok[dev] = strncmp(prop.gcnArchName, "gfx950", 6) == 0 ? 1 : 2;
+    }
+    if (g_arch_ok[dev] != 1) return fail(GSB_ERR_UNSUPPORTED, "device %d is not gfx950", dev);
+    return GSB_OK;
+}
+
+gsb_status check_dims(int32_t W, int32_t H) {
+    if (W < 1 || H < 1 || W > kMaxDim || H > kMaxDim)
+        return fail(GSB_ERR_INVALID, "image size %d x %d outside [1, %d]", W, H, kMaxDim);
+    return GSB_OK;
+}
+
+#define GSB_TRY(expr)                      \
+    do {                                   \
+        gsb_status _st = (expr);           \
+        if (_st != GSB_OK) return _st;     \
+    } while (0)
+
+#define GSB_REQUIRE(cond, ...)                                   \
+    do {                                                         \
+        if (!(cond)) return fail(GSB_ERR_INVALID, __VA_ARGS__);  \
+    } while (0)
+
+gsb_status check_blend_common(int32_t W, int32_t H, const uint32_t *ranges,
+                              const uint32_t *point_list, const float *means2d,
+                              const float *conics, const float *opacity, const float *colors,
+                              int64_t n, const float *bg, gsb_precision prec) {
+    GSB_TRY(check_dims(W, H));
+    GSB_REQUIRE(n >= 0 && n <= int64_t(0xffffffffll), "n = %lld out of range", (long long)n);
+    GSB_REQUIRE(ranges != nullptr && point_list != nullptr, "ranges and point_list must be non-null");
+    GSB_REQUIRE(aligned(ranges, 8), "ranges must be 8-byte aligned");
+    GSB_REQUIRE(n == 0 || (means2d && conics && opacity && colors),
+                "Gaussian attribute pointers must be non-null");
+    GSB_REQUIRE(aligned(means2d, 8), "means2d must be 8-byte aligned");
+    GSB_REQUIRE(bg != nullptr, "bg must be a host pointer to 3 floats");
+    GSB_REQUIRE(prec == GSB_FP32_PLAIN || prec == GSB_FP16_GEMM || prec == GSB_BF16_GEMM,
+                "unknown precision %d", int(prec));
+    return GSB_OK;
+}
+
+}  // namespace
+
+gsb_status fail(gsb_status code, const char *fmt, ...) {
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(g_err, sizeof(g_err), fmt, ap);
+    va_end(ap);
+    return code;
+}
+
+gsb_status check_launch(const char *what) {
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return fail(GSB_ERR_HIP, "%s: %s", what, hipGetErrorString(e));
+    return GSB_OK;
+}
+
+}  // namespace gsb
+
+using namespace gsb;
+
+extern "C" {
+
+int32_t gsb_abi_version(void) { return GSB_ABI_VERSION; }
+
+const char *gsb_last_error(void) { return g_err; }
+
+gsb_status gsb_bin_workspace_bytes(int64_t n, int64_t pair_capacity, int32_t W, int32_t H,
+                                   size_t *bytes) {
+    g_err[0] = '\0';
+    GSB_TRY(check_dims(W, H));
+    GSB_REQUIRE(bytes != nullptr, "bytes must be non-null");
+    GSB_REQUIRE(n >= 0 && n <= bin_max_gaussians(), "n = %lld outside [0, %lld]", (long long)n,
+                (long long)bin_max_gaussians());
+    GSB_REQUIRE(pair_capacity >= 0 && pair_capacity <= bin_max_pairs() &&
+                    pair_capacity <= int64_t(0x7fffffff),
+                "pair_capacity = %lld outside [0, %lld]", (long long)pair_capacity,
+                (long long)(bin_max_pairs() < 0x7fffffff ? bin_max_pairs() : 0x7fffffff));
+    *bytes = bin_workspace_bytes(n, pair_capacity, grid_x(W) * grid_y(H));
+    return GSB_OK;
+}
+
+gsb_status gsb_bin_count(const float *means2d, const int32_t *radii, int64_t n, int32_t W,
+                         int32_t H, void *ws, size_t ws_bytes, int64_t *n_pairs_dev,
+                         void *stream) {
+    size_t need = 0;
+    GSB_TRY(gsb_bin_workspace_bytes(n, 0, W, H, &need));
+    GSB_REQUIRE(n == 0 || (means2d && radii), "means2d and radii must be non-null");
+    GSB_REQUIRE(aligned(means2d, 8), "means2d must be 8-byte aligned");
+    GSB_REQUIRE(ws != nullptr && aligned(ws, 256), "workspace must be non-null and 256-byte aligned");
+    GSB_REQUIRE(ws_bytes >= need, "workspace of %zu bytes is smaller than the %zu needed", ws_bytes, need);
+    GSB_REQUIRE(n_pairs_dev != nullptr && aligned(n_pairs_dev, 8), "n_pairs_dev must be a non-null, 8-byte aligned device pointer");
+    GSB_TRY(check_device());
+    return bin_count(means2d, radii, n, W, H, ws, n_pairs_dev, static_cast<hipStream_t>(stream));
+}
+
+gsb_status gsb_bin_fill(const float *means2d, const int32_t *radii, const float *depths, int64_t n,
+                        int32_t W, int32_t H, void *ws, size_t ws_bytes, uint32_t *point_list,
+                        int64_t pair_capacity, uint32_t *ranges, int32_t *status_dev,
+                        void *stream) {
+    size_t need = 0;
+    GSB_TRY(gsb_bin_workspace_bytes(n, pair_capacity, W, H, &need));
+    GSB_REQUIRE(n == 0 || (means2d && radii && depths), "means2d, radii and depths must be non-null");
+    GSB_REQUIRE(aligned(means2d, 8), "means2d must be 8-byte aligned");
+    GSB_REQUIRE(ws != nullptr && aligned(ws, 256), "workspace must be non-null and 256-byte aligned");
+    GSB_REQUIRE(ws_bytes >= need, "workspace of %zu bytes is smaller than the %zu needed", ws_bytes, need);
+    GSB_REQUIRE(pair_capacity == 0 || point_list != nullptr, "point_list must be non-null");
+    GSB_REQUIRE(ranges != nullptr && status_dev != nullptr, "ranges and status_dev must be non-null");
+    GSB_TRY(check_device());
+    return bin_fill(means2d, radii, depths, n, W, H, ws, point_list, pair_capacity, ranges,
+                    status_dev, static_cast<hipStream_t>(stream));
+}
+
+gsb_status gsb_blend_forward(int32_t W, int32_t H, const uint32_t *ranges,
+                             const uint32_t *point_list, const float *means2d,
+                             const float *conics, const float *opacity, const float *colors,
+                             int64_t n, const float *bg, gsb_precision prec, float *image,
+                             float *final_T, int32_t *last_contrib, void *stream) {
+    g_err[0] = '\0';
+    GSB_TRY(check_blend_common(W, H, ranges, point_list, means2d, conics, opacity, colors, n, bg, prec));
+    GSB_REQUIRE(image && final_T && last_contrib, "output pointers must be non-null");
+    GSB_TRY(check_device());
+    BlendArgs a{W, H, ranges, point_list, means2d, conics, opacity, colors, n, {bg[0], bg[1], bg[2]}};
+    return blend_forward(a, prec, image, final_T, last_contrib, static_cast<hipStream_t>(stream));
+}
+
+gsb_status gsb_blend_backward(int32_t W, int32_t H, const uint32_t *ranges,
+                              const uint32_t *point_list, const float *means2d,
+                              const float *conics, const float *opacity, const float *colors,
+                              int64_t n, const float *bg, gsb_precision prec,
+                              const float *final_T, const int32_t *last_contrib,
+                              const float *dL_dimage, float *dL_dmeans2d, float *dL_dconics,
+                              float *dL_dopacity, float *dL_dcolors, void *stream) {
+    g_err[0] = '\0';
+    GSB_TRY(check_blend_common(W, H, ranges, point_list, means2d, conics, opacity, colors, n, bg, prec));
+    GSB_REQUIRE(final_T && last_contrib && dL_dimage, "final_T, last_contrib and dL_dimage must be non-null");
+    GSB_REQUIRE(n == 0 || (dL_dmeans2d && dL_dconics && dL_dopacity && dL_dcolors),
+                "gradient pointers must be non-null");
+    GSB_REQUIRE(aligned(dL_dmeans2d, 8), "dL_dmeans2d must be 8-byte aligned");
+    GSB_TRY(check_device());
+    BlendArgs a{W, H, ranges, point_list, means2d, conics, opacity, colors, n, {bg[0], bg[1], bg[2]}};
+    return blend_backward(a, prec, final_T, last_contrib, dL_dimage, dL_dmeans2d, dL_dconics,
+                          dL_dopacity, dL_dcolors, static_cast<hipStream_t>(stream));
+}
+
+}  // extern "C"

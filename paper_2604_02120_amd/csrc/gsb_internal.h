@@ -1,0 +1,60 @@
+// Internal declarations shared by the HIP translation units of libgsblend (not installed).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "../../include/gsblend.h"
+
+namespace gsb {
+
+constexpr int kTile = 16;             // screen tile edge, pixels
+constexpr int kTilePixels = kTile * kTile;
+constexpr int kBlock = 256;           // threads per tile block = 4 wavefronts of 64
+
+// Status helpers (capi.hip): record a message for gsb_last_error() and return the code.
+gsb_status fail(gsb_status code, const char *fmt, ...);
+gsb_status check_launch(const char *what);
+
+// Tile grid of a W x H image.
+inline int64_t grid_x(int32_t W) { return (W + kTile - 1) / kTile; }
+inline int64_t grid_y(int32_t H) { return (H + kTile - 1) / kTile; }
+
+// Blocks of a tile launch are spread over the 8 XCDs of the MI355X round-robin by the hardware
+// dispatcher (block b runs on XCD b % 8). Mapping block b to tile (b % 8) * chunk + b / 8 gives
+// every XCD one contiguous band of rows, so the Gaussians shared by neighbouring tiles are reused
+// from that XCD's own L2. Blocks past the last tile exit at once.
+constexpr int kXcds = 8;
+inline int64_t xcd_grid(int64_t n_tiles) {
+    const int64_t chunk = (n_tiles + kXcds - 1) / kXcds;
+    return chunk * kXcds;
+}
+__device__ inline int64_t xcd_tile(int64_t block, int64_t n_tiles) {
+    const int64_t chunk = (n_tiles + kXcds - 1) / kXcds;
+    return (block % kXcds) * chunk + block / kXcds;
+}
+
+// ---- binning (bin.hip)
+size_t bin_workspace_bytes(int64_t n, int64_t pair_capacity, int64_t n_tiles);
+gsb_status bin_count(const float *means2d, const int32_t *radii, int64_t n, int32_t W, int32_t H,
+                     void *ws, int64_t *n_pairs_dev, hipStream_t s);
+gsb_status bin_fill(const float *means2d, const int32_t *radii, const float *depths, int64_t n,
+                    int32_t W, int32_t H, void *ws, uint32_t *point_list, int64_t pair_capacity,
+                    uint32_t *ranges, int32_t *status_dev, hipStream_t s);
+
+// ---- blending (blend.hip)
+struct BlendArgs {
+    int32_t W, H;
+    const uint32_t *ranges;
+    const uint32_t *point_list;
+    const float *means2d, *conics, *opacity, *colors;
+    int64_t n;
+    float bg[3];
+};
+gsb_status blend_forward(const BlendArgs &a, gsb_precision prec, float *image, float *final_T,
+                         int32_t *last_contrib, hipStream_t s);
+gsb_status blend_backward(const BlendArgs &a, gsb_precision prec, const float *final_T,
+                          const int32_t *last_contrib, const float *dL_dimage, float *dL_dmeans2d,
+                          float *dL_dconics, float *dL_dopacity, float *dL_dcolors, hipStream_t s);
+
+}  // namespace gsb

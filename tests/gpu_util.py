@@ -1,0 +1,81 @@
+"""Helpers shared by the GPU tests: upload a scene, run the library, compare with the oracle."""
+from __future__ import annotations
+
+import math
+import sys
+
+import numpy as np
+import torch
+
+import oracle
+from paper_2604_02120_amd import api
+
+# Tolerances:
+PLAIN_ABS = 1e-5        # plain FP32 path vs FP64 oracle, pixels whose decisions are not marginal
+MARGIN = 1e-5           # relative distance of every skip/stop decision from its threshold
+GEMM_PSNR = 50.0        # FP16/BF16 GEMM path vs FP64 oracle, all pixels
+GEMM_GRAD = 1e-3        # normwise relative gradient error, GEMM path
+PLAIN_GRAD = 1e-4       # normwise relative gradient error, plain FP32 path
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def upload(scene: dict, dev) -> dict:
+    out = {"width": scene["width"], "height": scene["height"]}
+    for k in ("means2d", "conics", "opacity", "colors", "depths"):
+        out[k] = torch.from_numpy(np.ascontiguousarray(scene[k], np.float32)).to(dev)
+    out["radii"] = torch.from_numpy(np.ascontiguousarray(scene["radii"], np.int32)).to(dev)
+    return out
+
+
+def upload_bins(point_list, ranges, dev):
+    pl = torch.from_numpy(np.ascontiguousarray(point_list).astype(np.int32)).to(dev)
+    rg = torch.from_numpy(np.ascontiguousarray(ranges).astype(np.int32)).to(dev)
+    return pl, rg
+
+
+def gpu_forward(sd: dict, pl, rg, prec, bg=(0.0, 0.0, 0.0)):
+    img, T, last = api.blend_forward(sd["means2d"], sd["conics"], sd["opacity"], sd["colors"], rg,
+                                     pl, sd["width"], sd["height"], bg, prec)
+    torch.cuda.synchronize()
+    return img.cpu().numpy().astype(np.float64), T.cpu().numpy().astype(np.float64), \
+        last.cpu().numpy()
+
+
+def psnr(a: np.ndarray, b: np.ndarray) -> float:
+    mse = float(np.mean((a - b) ** 2))
+    return math.inf if mse == 0 else 10.0 * math.log10(1.0 / mse)
+
+
+def check_plain(ref: dict, img, T, last, label=""):
+    """Pixels whose every decision is further than MARGIN from its threshold must match in
+    last_contrib exactly and in image / final_T within PLAIN_ABS."""
+    ok = ref["margin"] > MARGIN
+    frac_excluded = 1.0 - ok.mean()
+    err_img = np.abs(img - ref["image"])[:, ok].max(initial=0.0)
+    err_T = np.abs(T - ref["final_T"])[ok].max(initial=0.0)
+    mism = int((last != ref["last_contrib"])[ok].sum())
+    say(f"  plain {label}: max|d image| {err_img:.3e}  max|d T| {err_T:.3e}  "
+        f"last mismatches {mism}  excluded {frac_excluded:.2e}  psnr {psnr(img, ref['image']):.1f} dB")
+    assert frac_excluded < 0.01
+    assert mism == 0
+    assert err_img <= PLAIN_ABS and err_T <= PLAIN_ABS
+    return err_img
+
+
+def check_gemm(ref: dict, img, T, label=""):
+    p = psnr(img, ref["image"])
+    maxabs = [float(np.abs(img[c] - ref["image"][c]).max()) for c in range(3)]
+    say(f"  gemm {label}: psnr {p:.1f} dB  max|d| per channel {maxabs}  "
+        f"max|d T| {np.abs(T - ref['final_T']).max():.3e}")
+    assert p >= GEMM_PSNR
+    return p
+
+
+def normwise(a, b) -> float:
+    d = np.linalg.norm(np.ravel(a) - np.ravel(b))
+    n = np.linalg.norm(np.ravel(b))
+    return float(d / n) if n > 0 else float(d)

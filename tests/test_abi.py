@@ -1,0 +1,115 @@
+"""Host-side checks of the C ABI: the library loads, exports every declared function, and rejects
+bad arguments before touching a device (these run without a GPU)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+from paper_2604_02120_amd import _lib, build
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "gsblend.h")
+
+
+@pytest.fixture(scope="module", autouse=True)
+def built():
+    if not os.path.exists(_lib.LIB_PATH):
+        build.build()
+    _lib.load()
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(gsb_\w+)\s*\(", text)))
+
+
+def test_header_declares_what_binding_exposes():
+    assert declared_functions() == sorted(_lib.EXPORTS)
+
+
+def test_library_exports_every_declared_symbol():
+    lib = ctypes.CDLL(_lib.LIB_PATH)
+    for name in declared_functions():
+        assert hasattr(lib, name), name
+
+
+def test_abi_version():
+    assert _lib.gsb_abi_version() == 1
+
+
+def test_no_oracle_in_library():
+    # the product library must not contain or link the CPU oracle
+    data = open(_lib.LIB_PATH, "rb").read()
+    assert b"orc_forward" not in data and b"libgsoracle" not in data
+
+
+@pytest.mark.parametrize("args,frag", [
+    ((-1, 0, 16, 16), "n = -1"),
+    ((10, -5, 16, 16), "pair_capacity"),
+    ((10, 0, 0, 16), "image size"),
+    ((10, 0, 16, 70000), "image size"),
+])
+def test_workspace_validation(args, frag):
+    with pytest.raises(_lib.GsbError) as e:
+        _lib.gsb_bin_workspace_bytes(*args)
+    assert e.value.status == _lib.GSB_ERR_INVALID and frag in str(e.value)
+
+
+def test_workspace_grows_with_capacity():
+    a = _lib.gsb_bin_workspace_bytes(1000, 0, 64, 64)
+    b = _lib.gsb_bin_workspace_bytes(1000, 100_000, 64, 64)
+    assert b > a + 100_000 * 20
+
+
+def test_forward_validation_before_device():
+    ok = 256  # a non-null, 8-byte aligned fake address: validation fails before any use
+    cases = [
+        ((0, 16, ok, ok, ok, ok, ok, ok, 1, (0, 0, 0), 0, ok, ok, ok), "image size"),
+        ((16, 16, 0, ok, ok, ok, ok, ok, 1, (0, 0, 0), 0, ok, ok, ok), "ranges"),
+        ((16, 16, ok + 4, ok, ok, ok, ok, ok, 1, (0, 0, 0), 0, ok, ok, ok), "aligned"),
+        ((16, 16, ok, ok, 0, ok, ok, ok, 1, (0, 0, 0), 0, ok, ok, ok), "attribute"),
+        ((16, 16, ok, ok, ok, ok, ok, ok, 1, None, 0, ok, ok, ok), "bg"),
+        ((16, 16, ok, ok, ok, ok, ok, ok, 1, (0, 0, 0), 9, ok, ok, ok), "precision"),
+        ((16, 16, ok, ok, ok, ok, ok, ok, 1, (0, 0, 0), 1, 0, ok, ok), "output"),
+    ]
+    for args, frag in cases:
+        with pytest.raises(_lib.GsbError) as e:
+            _lib.gsb_blend_forward(*args)
+        assert e.value.status == _lib.GSB_ERR_INVALID, args
+        assert frag in str(e.value), (frag, str(e.value))
+
+
+def test_backward_validation_before_device():
+    ok = 256
+    with pytest.raises(_lib.GsbError) as e:
+        _lib.gsb_blend_backward(16, 16, ok, ok, ok, ok, ok, ok, 3, (0, 0, 0), 0, ok, ok, ok,
+                                0, ok, ok, ok)
+    assert e.value.status == _lib.GSB_ERR_INVALID and "gradient" in str(e.value)
+
+
+def test_bin_validation_before_device():
+    ok = 256
+    need = _lib.gsb_bin_workspace_bytes(100, 0, 32, 32)
+    with pytest.raises(_lib.GsbError) as e:
+        _lib.gsb_bin_count(ok, ok, 100, 32, 32, ok, need - 1, ok)
+    assert e.value.status == _lib.GSB_ERR_INVALID and "workspace" in str(e.value)
+    with pytest.raises(_lib.GsbError) as e:
+        _lib.gsb_bin_count(ok, ok, 100, 32, 32, ok + 8, need, ok)
+    assert "256-byte" in str(e.value)
+    need2 = _lib.gsb_bin_workspace_bytes(100, 50, 32, 32)
+    with pytest.raises(_lib.GsbError) as e:
+        _lib.gsb_bin_fill(ok, ok, ok, 100, 32, 32, ok, need2, 0, 50, ok, ok)
+    assert "point_list" in str(e.value)
+
+
+def test_last_error_is_thread_local():
+    import threading
+    with pytest.raises(_lib.GsbError):
+        _lib.gsb_bin_workspace_bytes(-1, 0, 16, 16)
+    seen = []
+    t = threading.Thread(target=lambda: seen.append(_lib.gsb_last_error()))
+    t.start(); t.join()
+    assert seen == [""]
+    assert "n = -1" in _lib.gsb_last_error()

@@ -1,0 +1,236 @@
+"""GPU parity: libgsblend (through its C ABI) against the FP64 CPU oracle on seeded scenes.
+
+Binning must be bit-exact; the plain FP32 blend within 1e-5 of the oracle on every pixel whose
+decisions are not marginal; the FP16/BF16 GEMM blends at >= 50 dB PSNR; gradients within the
+normwise bounds in gpu_util.
+"""
+import json
+import os
+
+import numpy as np
+import pytest
+import torch
+
+import gsinputs
+import oracle
+from gpu_util import (GEMM_GRAD, PLAIN_GRAD, check_gemm, check_plain, gpu_forward, normwise,
+                      say, upload, upload_bins)
+from paper_2604_02120_amd import api
+from paper_2604_02120_amd.autograd import blend
+
+pytestmark = pytest.mark.gpu
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+PRECS = ["fp32", "fp16", "bf16"]
+
+
+def ragged_scene(seed=41, n=1500, W=70, H=37):
+    s = gsinputs.make_scene("C1", seed=seed, n=n, width=W, height=H)
+    s["means2d"][:20] -= np.float32(25.0)       # off-screen to the top-left
+    s["means2d"][20:30] += np.float32([W + 4, H + 4])
+    s["radii"][30:40] = 0                       # not rendered
+    s["opacity"][40:60] = 0.001                 # below the skip threshold everywhere
+    return s
+
+
+def scenes():
+    return {
+        "C1": gsinputs.make_scene("C1"),
+        "ragged": ragged_scene(),
+        "ties": gsinputs.make_scene("C1", seed=42, n=3000, width=96, height=80, depth_levels=4),
+        "lognormal": gsinputs.make_scene("C2", seed=43, n=12000, width=200, height=120),
+    }
+
+
+SCENES = scenes()
+
+
+# ----------------------------------------------------------------------------- binning
+@pytest.mark.parametrize("name", list(SCENES))
+def test_bin_bitexact(gpu, name):
+    s = SCENES[name]
+    say(f"[bin] {name} {s['width']}x{s['height']} n={len(s['radii'])}")
+    pl_ref, rg_ref = oracle.bin_tiles(s["means2d"], s["radii"], s["depths"], s["width"], s["height"])
+    sd = upload(s, gpu)
+    pl, rg = api.bin_tiles(sd["means2d"], sd["radii"], sd["depths"], s["width"], s["height"])
+    np.testing.assert_array_equal(rg.cpu().numpy().astype(np.uint32), rg_ref)
+    np.testing.assert_array_equal(pl.cpu().numpy().astype(np.uint32), pl_ref)
+
+
+def test_bin_capacity_overflow_flag(gpu):
+    s = SCENES["C1"]
+    sd = upload(s, gpu)
+    W, H = s["width"], s["height"]
+    n = len(s["radii"])
+    ws = api.BinWorkspace(n, 1000, W, H, device=gpu)
+    npairs = api.bin_count(sd["means2d"], sd["radii"], W, H, ws)
+    pl = torch.full((1000,), -1, dtype=torch.int32, device=gpu)
+    rg = torch.empty((16, 2), dtype=torch.int32, device=gpu)
+    st = api.bin_fill(sd["means2d"], sd["radii"], sd["depths"], W, H, ws, pl, rg)
+    torch.cuda.synchronize()
+    assert int(npairs.item()) > 1000
+    assert int(st.item()) == 2        # GSB_ERR_CAPACITY
+    ok = api.BinWorkspace(n, int(npairs.item()), W, H, device=gpu)
+    ok.buf[: ws.nbytes].copy_(ws.buf[: ws.nbytes])
+    pl2 = torch.empty(int(npairs.item()), dtype=torch.int32, device=gpu)
+    st2 = api.bin_fill(sd["means2d"], sd["radii"], sd["depths"], W, H, ok, pl2, rg)
+    torch.cuda.synchronize()
+    assert int(st2.item()) == 0
+
+
+# ----------------------------------------------------------------------------- forward
+@pytest.mark.parametrize("name", list(SCENES))
+@pytest.mark.parametrize("prec", PRECS)
+def test_forward_parity(gpu, name, prec):
+    s = SCENES[name]
+    bg = (0.05, 0.1, 0.2)
+    say(f"[fwd] {name} {prec} {s['width']}x{s['height']} n={len(s['radii'])}")
+    ref = oracle.render(s, bg)
+    sd = upload(s, gpu)
+    pl, rg = upload_bins(ref["point_list"], ref["ranges"], gpu)
+    img, T, last = gpu_forward(sd, pl, rg, prec, bg)
+    if prec == "fp32":
+        check_plain(ref, img, T, last, name)
+    else:
+        check_gemm(ref, img, T, name)
+
+
+@pytest.mark.parametrize("prec", PRECS)
+def test_forward_deterministic(gpu, prec):
+    s = SCENES["lognormal"]
+    sd = upload(s, gpu)
+    pl, rg = api.bin_tiles(sd["means2d"], sd["radii"], sd["depths"], s["width"], s["height"])
+    a = gpu_forward(sd, pl, rg, prec)
+    b = gpu_forward(sd, pl, rg, prec)
+    for x, y in zip(a, b):
+        np.testing.assert_array_equal(x, y)
+
+
+@pytest.mark.parametrize("prec", PRECS)
+def test_forward_five_stack_golden(gpu, prec):
+    g = json.load(open(os.path.join(GOLDEN, "five_stack.json")))
+    s = gsinputs.stack_scene(g["n"], g["opacity"], at=tuple(g["pixel"]))
+    sd = upload(s, gpu)
+    pl, rg = api.bin_tiles(sd["means2d"], sd["radii"], sd["depths"], 16, 16)
+    img, T, last = gpu_forward(sd, pl, rg, prec)
+    px, py = g["pixel"]
+    assert last[py, px] == g["last_contrib"]
+    np.testing.assert_allclose(img[:, py, px], g["image"], atol=2e-6)
+    assert abs(T[py, px] - g["final_T"]) < 1e-7
+
+
+@pytest.mark.parametrize("prec", PRECS)
+def test_forward_empty_and_degenerate(gpu, prec):
+    bg = (0.25, 0.5, 0.75)
+    # no Gaussians at all, odd-sized image
+    empty = gsinputs.make_scene("C1", seed=9, n=5, width=33, height=17)
+    empty["radii"][:] = 0
+    sd = upload(empty, gpu)
+    pl, rg = api.bin_tiles(sd["means2d"], sd["radii"], sd["depths"], 33, 17)
+    assert pl.numel() == 0
+    img, T, last = gpu_forward(sd, pl, rg, prec, bg)
+    for c in range(3):
+        assert np.all(img[c] == np.float32(bg[c]))
+    assert np.all(T == 1.0) and np.all(last == 0)
+    # a 1x1 image with a single Gaussian on the pixel
+    one = gsinputs.stack_scene(1, 0.5, width=1, height=1, at=(0.0, 0.0))
+    sd = upload(one, gpu)
+    pl, rg = api.bin_tiles(sd["means2d"], sd["radii"], sd["depths"], 1, 1)
+    img, T, last = gpu_forward(sd, pl, rg, prec)
+    assert last[0, 0] == 1 and abs(T[0, 0] - 0.5) < 1e-6
+    np.testing.assert_allclose(img[:, 0, 0], [0.5, 0.25, 0.125], atol=1e-6)
+
+
+def test_forward_c2_full_size(gpu):
+    """The benchmark's forward workload (1920x1080, 1M Gaussians), GPU binning, all three
+    precisions against the full-frame oracle."""
+    s = gsinputs.make_scene("C2")
+    say("[fwd-full] C2 1920x1080 n=1e6: oracle")
+    ref = oracle.render(s)
+    sd = upload(s, gpu)
+    pl, rg = api.bin_tiles(sd["means2d"], sd["radii"], sd["depths"], 1920, 1080)
+    np.testing.assert_array_equal(rg.cpu().numpy().astype(np.uint32), ref["ranges"])
+    np.testing.assert_array_equal(pl.cpu().numpy().astype(np.uint32), ref["point_list"])
+    for prec in PRECS:
+        say(f"[fwd-full] C2 {prec}")
+        img, T, last = gpu_forward(sd, pl, rg, prec)
+        if prec == "fp32":
+            check_plain(ref, img, T, last, "C2")
+        else:
+            check_gemm(ref, img, T, "C2")
+
+
+# ----------------------------------------------------------------------------- backward
+_REF_CACHE = {}
+
+
+def backward_case(s, gpu, prec, seed=77, bg=(0.1, 0.3, 0.2)):
+    W, H = s["width"], s["height"]
+    g = gsinputs.make_dloss(W, H, seed)
+    key = (id(s), seed, bg)
+    if key not in _REF_CACHE:
+        pl_ref, rg_ref = oracle.bin_tiles(s["means2d"], s["radii"], s["depths"], W, H)
+        ref = oracle.backward(W, H, rg_ref, pl_ref, s["means2d"], s["conics"], s["opacity"],
+                              s["colors"], g, bg)
+        _REF_CACHE.clear()
+        _REF_CACHE[key] = (pl_ref, rg_ref, ref)
+    pl_ref, rg_ref, ref = _REF_CACHE[key]
+    sd = upload(s, gpu)
+    pl, rg = upload_bins(pl_ref, rg_ref, gpu)
+    img, T, last = api.blend_forward(sd["means2d"], sd["conics"], sd["opacity"], sd["colors"], rg,
+                                     pl, W, H, bg, prec)
+    gd = torch.from_numpy(g).to(gpu)
+    out = api.blend_backward(sd["means2d"], sd["conics"], sd["opacity"], sd["colors"], rg, pl, W,
+                             H, T, last, gd, bg, prec)
+    torch.cuda.synchronize()
+    names = ["dmeans2d", "dconics", "dopacity", "dcolors"]
+    return {k: v.cpu().numpy().astype(np.float64) for k, v in zip(names, out)}, ref
+
+
+@pytest.mark.parametrize("prec", PRECS)
+@pytest.mark.parametrize("name", ["C1", "ragged", "lognormal"])
+def test_backward_parity(gpu, prec, name):
+    s = SCENES[name]
+    say(f"[bwd] {name} {prec}")
+    got, ref = backward_case(s, gpu, prec)
+    bound = PLAIN_GRAD if prec == "fp32" else GEMM_GRAD
+    for k in ref:
+        e = normwise(got[k], ref[k])
+        say(f"  {k}: normwise rel err {e:.3e}")
+        assert e <= bound, (k, e)
+
+
+@pytest.mark.parametrize("prec", PRECS)
+def test_autograd_matches_oracle_on_fd_subscene(gpu, prec):
+    """The 32x32, 200-Gaussian subscene whose oracle gradient is pinned to finite differences."""
+    s = gsinputs.fd_subscene(33)
+    W, H = s["width"], s["height"]
+    s32 = {k: (v.astype(np.float32) if isinstance(v, np.ndarray) and v.dtype == np.float64 else v)
+           for k, v in s.items()}
+    bg = (0.2, 0.4, 0.1)
+    g = gsinputs.make_dloss(W, H, 34)
+    pl_ref, rg_ref = oracle.bin_tiles(s32["means2d"], s32["radii"], s32["depths"], W, H)
+    ref = oracle.backward(W, H, rg_ref, pl_ref, s32["means2d"], s32["conics"], s32["opacity"],
+                          s32["colors"], g, bg)
+    sd = upload(s32, gpu)
+    pl, rg = upload_bins(pl_ref, rg_ref, gpu)
+    leaves = [sd[k].clone().requires_grad_(True) for k in ("means2d", "conics", "opacity", "colors")]
+    img, T, last = blend(*leaves, rg, pl, W, H, bg, prec)
+    (img * torch.from_numpy(g).to(gpu)).sum().backward()
+    bound = PLAIN_GRAD if prec == "fp32" else GEMM_GRAD
+    for leaf, k in zip(leaves, ["dmeans2d", "dconics", "dopacity", "dcolors"]):
+        e = normwise(leaf.grad.cpu().numpy().astype(np.float64), ref[k])
+        say(f"  {prec} {k}: {e:.3e}")
+        assert e <= bound, (k, e)
+
+
+def test_backward_c3_full_size(gpu):
+    """The benchmark-shaped differentiable workload at full size (1280x720, 500k Gaussians)."""
+    s = gsinputs.make_scene("C3")
+    for prec in PRECS:
+        say(f"[bwd-full] C3 {prec}")
+        got, ref = backward_case(s, gpu, prec, seed=1003, bg=(0.0, 0.0, 0.0))
+        bound = PLAIN_GRAD if prec == "fp32" else GEMM_GRAD
+        for k in ref:
+            e = normwise(got[k], ref[k])
+            say(f"  {k}: {e:.3e}")
+            assert e <= bound, (k, e)
