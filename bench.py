@@ -1,0 +1,243 @@
+#!/usr/bin/env python3
+"""Throughput of the differentiable Gaussian blend on one MI355X.
+
+Workload (the headline configuration): one 1920x1080 frame of 1,000,000 projected 2D Gaussians
+(log-normal footprint, median sigma 2 px; seeded synthetic stand-in for the paper's trained
+scenes), upstream gradient dL/dimage ~ N(0, 1). One step is the whole hot path for that frame:
+tile binning (count, duplicate, radix sort, ranges) + forward blend + backward blend, with inputs
+resident in HBM. The GEMM form (FP16 hi+lo exponent on MFMA, FP32 accumulate and compositing)
+is the headline; the plain FP32 per-pixel form and the BF16 GEMM form are timed the same way.
+
+Prints one JSON line. `value` = frame pixels x steps / wall time of the timed steps (binning
+included); `blend_mpix_s` = pixels / (forward + backward kernel time) alone.
+
+    python bench.py [--steps K] [--warmup W] [--no-cpu-baseline]
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+import numpy as np  # noqa: E402
+import torch  # noqa: E402
+
+import gsinputs  # noqa: E402
+from paper_2604_02120_amd import api  # noqa: E402
+
+METRIC = "Mpix/s fwd+bwd blend, GEMM-form vs plain FP32 on 1 MI355X at ≥50 dB vs oracle"
+# FP32 vector peak without packed math (v_pk_*_f32 are disabled in this build):
+# 256 CUs x 4 SIMDs x 16 lanes x 2 flop (FMA) x 2.4 GHz.
+PEAK_ALU_TFLOPS = 256 * 4 * 16 * 2 * 2.4e9 / 1e12
+# Algorithmic FP32 operations per pair (see the design notes, "Roofline"):
+#   forward : 16 per evaluated pair + 10 per blended pair
+#   backward: 16 per revisited pair + 39 per blended pair
+FLOPS = {"forward": (16, 10), "backward": (16, 39)}
+COUNTS = os.path.join(ROOT, "tests", "golden", "workload_counts.json")
+TRAFFIC = os.path.join(ROOT, "profiles", "traffic.json")
+KERNEL_SRC = os.path.join(ROOT, "paper_2604_02120_amd", "csrc", "blend.hip")
+
+
+def parse():
+    p = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    p.add_argument("--gpus", type=int, default=1)
+    p.add_argument("--steps", type=int, default=20)
+    p.add_argument("--warmup", type=int, default=5)
+    p.add_argument("--config", default="C2", choices=["C2", "C3"])
+    p.add_argument("--precs", default="fp16,fp32,bf16",
+                   help="comma list; the first is the headline")
+    p.add_argument("--no-cpu-baseline", action="store_true")
+    return p.parse_args()
+
+
+class Frame:
+    """Device buffers of one frame: inputs, binning workspace sized for the exact pair count,
+    outputs and gradients."""
+
+    def __init__(self, cfg, dev):
+        s = gsinputs.make_scene(cfg)
+        self.scene = s
+        self.W, self.H, self.n = s["width"], s["height"], len(s["radii"])
+        t = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(dev)  # noqa: E731
+        self.means2d, self.conics, self.opacity = t(s["means2d"]), t(s["conics"]), t(s["opacity"])
+        self.colors, self.depths, self.radii = t(s["colors"]), t(s["depths"]), t(s["radii"])
+        self.dloss_np = gsinputs.make_dloss(self.W, self.H, cfg.dloss_seed)
+        self.dloss = t(self.dloss_np)
+        ws0 = api.BinWorkspace(self.n, 0, self.W, self.H, device=dev)
+        self.pairs = int(api.bin_count(self.means2d, self.radii, self.W, self.H, ws0).item())
+        self.ws = api.BinWorkspace(self.n, self.pairs, self.W, self.H, device=dev)
+        gx, gy = api.grid(self.W, self.H)
+        self.point_list = torch.empty(self.pairs, dtype=torch.int32, device=dev)
+        self.ranges = torch.empty((gx * gy, 2), dtype=torch.int32, device=dev)
+        self.fwd_out = (torch.empty((3, self.H, self.W), device=dev),
+                        torch.empty((self.H, self.W), device=dev),
+                        torch.empty((self.H, self.W), dtype=torch.int32, device=dev))
+        self.bwd_out = (torch.empty((self.n, 2), device=dev), torch.empty((self.n, 3), device=dev),
+                        torch.empty((self.n,), device=dev), torch.empty((self.n, 3), device=dev))
+        self.status = None
+
+    def step(self, prec, ev=None):
+        if ev is not None:
+            ev[0].record()
+        api.bin_count(self.means2d, self.radii, self.W, self.H, self.ws)
+        self.status = api.bin_fill(self.means2d, self.radii, self.depths, self.W, self.H, self.ws,
+                                   self.point_list, self.ranges)
+        if ev is not None:
+            ev[1].record()
+        img, T, last = api.blend_forward(self.means2d, self.conics, self.opacity, self.colors,
+                                         self.ranges, self.point_list, self.W, self.H,
+                                         (0.0, 0.0, 0.0), prec, out=self.fwd_out)
+        if ev is not None:
+            ev[2].record()
+        api.blend_backward(self.means2d, self.conics, self.opacity, self.colors, self.ranges,
+                           self.point_list, self.W, self.H, T, last, self.dloss, (0.0, 0.0, 0.0),
+                           prec, out=self.bwd_out)
+        if ev is not None:
+            ev[3].record()
+
+
+def time_path(fr: Frame, prec: str, steps: int, warmup: int) -> dict:
+    for _ in range(warmup):
+        fr.step(prec)
+    torch.cuda.synchronize()
+    evs = [[torch.cuda.Event(enable_timing=True) for _ in range(4)] for _ in range(steps)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(steps):
+        fr.step(prec, evs[k])
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    if int(fr.status.item()) != 0:
+        raise RuntimeError("binning overflowed its capacity")
+    bin_ms = [e[0].elapsed_time(e[1]) for e in evs]
+    fwd_ms = [e[1].elapsed_time(e[2]) for e in evs]
+    bwd_ms = [e[2].elapsed_time(e[3]) for e in evs]
+    px = fr.W * fr.H
+    r = {
+        "ms_per_step": 1e3 * wall / steps,
+        "mpix_s": px * steps / wall / 1e6,
+        "bin_ms": float(np.mean(bin_ms)), "fwd_ms": float(np.mean(fwd_ms)),
+        "bwd_ms": float(np.mean(bwd_ms)),
+        "fwd_ms_p10_p90": [float(np.percentile(fwd_ms, 10)), float(np.percentile(fwd_ms, 90))],
+        "bwd_ms_p10_p90": [float(np.percentile(bwd_ms, 10)), float(np.percentile(bwd_ms, 90))],
+    }
+    r["blend_mpix_s"] = px / ((r["fwd_ms"] + r["bwd_ms"]) * 1e-3) / 1e6
+    return r
+
+
+def kernel_hash() -> str:
+    return hashlib.sha256(open(KERNEL_SRC, "rb").read()).hexdigest()[:16]
+
+
+def roofline(res: dict, counts: dict) -> dict:
+    """ALU roofline of the dominant blend kernel (the slower of forward / backward)."""
+    kern = "backward" if res["bwd_ms"] >= res["fwd_ms"] else "forward"
+    per_pair, per_blend = FLOPS[kern]
+    pairs = counts["E"] if kern == "forward" else counts["Eb"]
+    flops = per_pair * pairs + per_blend * counts["K"]
+    ms = res["fwd_ms"] if kern == "forward" else res["bwd_ms"]
+    achieved = flops / (ms * 1e-3) / 1e12
+    traffic = None
+    if os.path.exists(TRAFFIC):
+        tr = json.load(open(TRAFFIC))
+        ent = tr.get(kern)
+        if ent and ent.get("kernel_sha") == kernel_hash():
+            traffic = ent["bytes_per_launch"]
+    return {"bound": "alu", "kernel": f"blend_{kern}", "achieved": round(achieved, 3),
+            "peak": round(PEAK_ALU_TFLOPS, 2), "unit": "TFLOP/s",
+            "frac": round(achieved / PEAK_ALU_TFLOPS, 4), "traffic": traffic,
+            "flops_per_launch": flops, "avg_ms": round(ms, 4)}
+
+
+def psnr(a, b) -> float:
+    mse = float(np.mean((a - b) ** 2))
+    return math.inf if mse == 0 else 10 * math.log10(1.0 / mse)
+
+
+def cpu_baseline_and_accuracy(fr: Frame, gpu_results: dict) -> tuple[dict, dict]:
+    """The FP64 oracle as it stands, on the host's cores, over the same full frame (bin + fwd +
+    bwd), and the accuracy of every GPU path against it."""
+    import oracle
+    s = fr.scene
+    W, H = fr.W, fr.H
+    t0 = time.perf_counter()
+    pl, rg = oracle.bin_tiles(s["means2d"], s["radii"], s["depths"], W, H)
+    t1 = time.perf_counter()
+    ref = oracle.forward(W, H, rg, pl, s["means2d"], s["conics"], s["opacity"], s["colors"])
+    t2 = time.perf_counter()
+    gref = oracle.backward(W, H, rg, pl, s["means2d"], s["conics"], s["opacity"], s["colors"],
+                           fr.dloss_np)
+    t3 = time.perf_counter()
+    cpu = {"value": round(W * H / (t3 - t0) / 1e6, 4), "unit": "Mpix/s",
+           "cores": oracle.threads(), "kind": "oracle",
+           "sample": f"one full {W}x{H} frame of the same scene: binning + forward + backward in "
+                     f"FP64 ({t1 - t0:.1f} s + {t2 - t1:.1f} s + {t3 - t2:.1f} s)",
+           "bin_s": round(t1 - t0, 3), "fwd_s": round(t2 - t1, 3), "bwd_s": round(t3 - t2, 3)}
+    acc = {}
+    for prec, out in gpu_results.items():
+        img, T, last, grads = out
+        a = {"psnr_db": round(psnr(img, ref["image"]), 2),
+             "max_abs_per_channel": [float(np.abs(img[c] - ref["image"][c]).max()) for c in range(3)]}
+        ok = ref["margin"] > 1e-5
+        a["max_abs_nonmarginal"] = float(np.abs(img - ref["image"])[:, ok].max())
+        a["last_contrib_mismatch_nonmarginal"] = int((last != ref["last_contrib"])[ok].sum())
+        for k, g in zip(("dmeans2d", "dconics", "dopacity", "dcolors"), grads):
+            d = np.linalg.norm((g - gref[k]).ravel()) / np.linalg.norm(gref[k].ravel())
+            a[f"grad_rel_{k}"] = float(f"{d:.3e}")
+        acc[prec] = a
+    return cpu, acc
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print("bench.py measures one GPU: this build has no multi-GPU path (the sharding design "
+              "is described in DESIGN.md); run with --gpus 1.", file=sys.stderr)
+        sys.exit(2)
+    dev = torch.device("cuda:0")
+    cfg = gsinputs.CONFIGS[args.config]
+    fr = Frame(cfg, dev)
+    counts = json.load(open(COUNTS))[args.config]
+    precs = args.precs.split(",")
+    results, outputs = {}, {}
+    for prec in precs:
+        results[prec] = time_path(fr, prec, args.steps, args.warmup)
+        if not args.no_cpu_baseline:
+            img, T, last = (x.cpu().numpy() for x in fr.fwd_out)
+            grads = [g.cpu().numpy().astype(np.float64) for g in fr.bwd_out]
+            outputs[prec] = (img.astype(np.float64), T, last, grads)
+    head = results[precs[0]]
+    line = {
+        "metric": METRIC, "value": round(head["mpix_s"], 3), "unit": "Mpix/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(head["ms_per_step"], 4),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": {"fp16": "f16+f32", "bf16": "bf16+f32", "fp32": "f32"}[precs[0]],
+        "data": "synthetic",
+        "config": {"workload": f"{cfg.name}: {fr.W}x{fr.H}, {fr.n} projected Gaussians, "
+                               "log-normal sigma (median 2 px); step = bin + forward + backward",
+                   "width": fr.W, "height": fr.H, "gaussians": fr.n, "pairs": fr.pairs,
+                   "precision": precs[0], "parallelism": "single GPU"},
+        "blend_mpix_s": round(head["blend_mpix_s"], 3),
+        "breakdown_ms": {k: round(head[k], 4) for k in ("bin_ms", "fwd_ms", "bwd_ms")},
+        "roofline": roofline(head, counts),
+        "paths": {p: {k: (round(v, 4) if isinstance(v, float) else v) for k, v in r.items()}
+                  for p, r in results.items()},
+    }
+    if "fp32" in results and precs[0] != "fp32":
+        line["speedup_vs_plain_fp32"] = {
+            "step": round(results["fp32"]["ms_per_step"] / head["ms_per_step"], 3),
+            "blend": round(head["blend_mpix_s"] / results["fp32"]["blend_mpix_s"], 3)}
+    if not args.no_cpu_baseline:
+        line["cpu_baseline"], line["accuracy"] = cpu_baseline_and_accuracy(fr, outputs)
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

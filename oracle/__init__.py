@@ -43,7 +43,7 @@ def _load():
         lib.orc_bin_count.restype = i64
         lib.orc_bin.argtypes = [P, P, P, i64, i32, i32, i64, P, P]
         lib.orc_bin.restype = i64
-        lib.orc_forward.argtypes = [i32, i32, P, P, P, P, P, P, P, P, P, P, P, P]
+        lib.orc_forward.argtypes = [i32, i32, P, P, P, P, P, P, P, P, P, P, P, P, P]
         lib.orc_forward.restype = None
         lib.orc_backward.argtypes = [i32, i32, P, P, P, P, P, P, P, i64, P, P, P, P, P]
         lib.orc_backward.restype = None
@@ -91,7 +91,7 @@ def bin_tiles(means2d, radii, depths, W: int, H: int) -> tuple[np.ndarray, np.nd
 def forward(W: int, H: int, ranges, point_list, means2d, conics, opacity, colors,
             bg=(0.0, 0.0, 0.0)) -> dict[str, np.ndarray]:
     """image f64[3][H][W], final_T f64[H][W], last_contrib i32[H][W], n_eval i32[H][W],
-    margin f64[H][W]."""
+    n_contrib i32[H][W], margin f64[H][W]."""
     lib = _load()
     rg = np.ascontiguousarray(ranges, dtype=np.uint32)
     pl = np.ascontiguousarray(point_list, dtype=np.uint32)
@@ -102,11 +102,13 @@ def forward(W: int, H: int, ranges, point_list, means2d, conics, opacity, colors
     final_T = np.empty((H, W), np.float64)
     last = np.empty((H, W), np.int32)
     n_eval = np.empty((H, W), np.int32)
+    n_contrib = np.empty((H, W), np.int32)
     margin = np.empty((H, W), np.float64)
     lib.orc_forward(W, H, _ptr(rg), _ptr(pl), _ptr(m), _ptr(c), _ptr(o), _ptr(col), _ptr(b),
-                    _ptr(image), _ptr(final_T), _ptr(last), _ptr(n_eval), _ptr(margin))
+                    _ptr(image), _ptr(final_T), _ptr(last), _ptr(n_eval), _ptr(n_contrib),
+                    _ptr(margin))
     return {"image": image, "final_T": final_T, "last_contrib": last, "n_eval": n_eval,
-            "margin": margin}
+            "n_contrib": n_contrib, "margin": margin}
 
 
 def backward(W: int, H: int, ranges, point_list, means2d, conics, opacity, colors, dL_dimage,
@@ -140,8 +142,9 @@ def render(scene: dict, bg=(0.0, 0.0, 0.0)) -> dict[str, np.ndarray]:
 
 
 def work_counts(fwd: dict, ranges) -> dict[str, int]:
-    """E = per-pixel evaluations until stop (sum over pixels); F = entries a tile must fetch
-    (max over its pixels of the stop position, summed over tiles); P = pairs."""
+    """E = per-pixel evaluations until stop (sum over pixels); Eb = list positions before each
+    pixel's last contributor (sum; what the backward revisits); K = blended pairs; F = entries a
+    tile must fetch (max over its pixels of the stop position, summed over tiles); P = pairs."""
     n_eval = fwd["n_eval"]
     H, W = n_eval.shape
     gx, gy = grid(W, H)
@@ -149,5 +152,7 @@ def work_counts(fwd: dict, ranges) -> dict[str, int]:
     pad[:H, :W] = n_eval
     F = int(pad.reshape(gy, TILE, gx, TILE).max(axis=(1, 3)).sum())
     rg = np.asarray(ranges, np.int64)
-    return {"E": int(n_eval.astype(np.int64).sum()), "F": F,
+    return {"E": int(n_eval.astype(np.int64).sum()),
+            "Eb": int(fwd["last_contrib"].astype(np.int64).sum()),
+            "K": int(fwd["n_contrib"].astype(np.int64).sum()), "F": F,
             "P": int((rg[:, 1] - rg[:, 0]).sum())}

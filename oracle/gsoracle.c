@@ -146,12 +146,13 @@ static double rel_margin(double v, double thr) { return fabs(v - thr) / thr; }
 
 /* Forward blend of every pixel. image is planar [3][H][W]; final_T and last_contrib are [H][W].
  * n_eval (optional): list entries examined per pixel, including the one that stops it.
+ * n_contrib (optional): Gaussians blended into the pixel.
  * margin (optional): smallest relative distance of any alpha-skip or stop decision to its
  * threshold, per pixel (decisions this close can flip under rounding). */
 void orc_forward(int32_t W, int32_t H, const uint32_t *ranges, const uint32_t *point_list,
                  const double *means2d, const double *conics, const double *opacity,
                  const double *colors, const double *bg, double *image, double *final_T,
-                 int32_t *last_contrib, int32_t *n_eval, double *margin) {
+                 int32_t *last_contrib, int32_t *n_eval, int32_t *n_contrib, double *margin) {
     const int64_t gx = (W + ORC_TILE - 1) / ORC_TILE, gy = (H + ORC_TILE - 1) / ORC_TILE;
     const int64_t HW = (int64_t)H * W;
     const double tau = tau_cull(), tstop = t_stop(), amax = alpha_max();
@@ -162,7 +163,7 @@ void orc_forward(int32_t W, int32_t H, const uint32_t *ranges, const uint32_t *p
         for (int64_t py = ty * ORC_TILE; py < (ty + 1) * ORC_TILE && py < H; ++py) {
             for (int64_t px = tx * ORC_TILE; px < (tx + 1) * ORC_TILE && px < W; ++px) {
                 double T = 1.0, acc[3] = {0.0, 0.0, 0.0}, mmin = INFINITY;
-                int32_t last = 0, evals = 0;
+                int32_t last = 0, evals = 0, contrib = 0;
                 for (uint32_t n = start; n < end; ++n) {
                     const int64_t i = point_list[n];
                     ++evals;
@@ -180,12 +181,14 @@ void orc_forward(int32_t W, int32_t H, const uint32_t *ranges, const uint32_t *p
                     for (int c = 0; c < 3; ++c) acc[c] += alpha * T * colors[3 * i + c];
                     T = Tn;
                     last = (int32_t)(n - start + 1);
+                    ++contrib;
                 }
                 const int64_t p = py * W + px;
                 for (int c = 0; c < 3; ++c) image[c * HW + p] = acc[c] + T * bg[c];
                 final_T[p] = T;
                 last_contrib[p] = last;
                 if (n_eval) n_eval[p] = evals;
+                if (n_contrib) n_contrib[p] = contrib;
                 if (margin) margin[p] = mmin;
             }
         }

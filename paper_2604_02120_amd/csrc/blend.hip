@@ -22,6 +22,13 @@
 // clear of FP16 subnormals, with the basis scaled by 2^-12 for that product, both exact), so the two
 // MFMAs recover ~22 (FP16) / ~16 (BF16) significant bits of v_g.
 //
+// Conditioning. Needle-like Gaussians (axis ratio up to ~100) make the quadratic form a sum of
+// terms ~1e5 that cancel to O(1); evaluated naively in FP32 the exponent is off by up to ~1e-2.
+// Both paths therefore evaluate Q = d^T Sigma^-1 d as dx*gx + dy*gy with g = Sigma^-1 d, where each
+// product A*dx's rounding error is recovered exactly with an FMA and added back, so g (small along
+// the needle, where the cancellation happens) carries full FP32 relative accuracy. The plain path
+// does this per pair; the GEMM path once per staged Gaussian, for v_g[3], v_g[4] and the constant.
+//
 // MFMA packing (v_mfma_f32_32x32x16_{f16,bf16}): lane l supplies A[l%32][8(l/32)..+7] and
 // B[8(l/32)..+7][l%32]; accumulator register v of lane l holds D[8(v/4) + 4(l/32) + v%4][l%32].
 // B is each lane's own pixel basis. A is block-diagonal: row i carries v_g of Gaussian
@@ -97,8 +104,8 @@ struct Stage {                 // GEMM form
 };
 template <>
 struct Stage<Mode::Plain> {    // plain form
-    float4 geo[2][kBatch];     // (x, y, -L A/2, -L B)
-    float2 geo2[2][kBatch];    // (-L C/2, log2 o)
+    float4 geo[2][kBatch];     // (x, y, A, B)
+    float2 geo2[2][kBatch];    // (C, log2 o)
     float4 attr[2][kBatch];    // (log2 o, r, g, b)
 };
 
@@ -115,6 +122,19 @@ struct GRaw {
 };
 
 struct __attribute__((aligned(4))) F3 { float a, b, c; };
+
+// a*x + b*y to full FP32 relative accuracy: the rounding error of a*x is recovered with an FMA.
+__device__ inline float dot2_acc(float a, float x, float b, float y) {
+    const float p = __fmul_rn(a, x);
+    const float pe = fmaf(a, x, -p);
+    return fmaf(b, y, p) + pe;
+}
+// Q = A dx^2 + 2 B dx dy + C dy^2 as dx*gx + dy*gy with g = Sigma^-1 (dx, dy) from dot2_acc.
+__device__ inline float quad_acc(float A, float B, float C, float dx, float dy, float &gx, float &gy) {
+    gx = dot2_acc(A, dx, B, dy);
+    gy = dot2_acc(C, dy, B, dx);
+    return fmaf(dx, gx, __fmul_rn(dy, gy));
+}
 
 // An index >= n (an inconsistent list) is treated as an empty slot rather than dereferenced.
 __device__ inline GRaw fetch(const uint32_t *plist, int64_t pos, bool valid, uint32_t n,
@@ -145,9 +165,8 @@ __device__ inline void stage(const GRaw &g, int buf, int slot, float xc, float y
     const bool live = g.valid && g.o >= kTauCull;
     const float lo2o = live ? __log2f(g.o) : -INFINITY;
     if constexpr (M == Mode::Plain) {
-        S.geo[buf][slot] = live ? make_float4(g.x, g.y, -0.5f * kLog2e * g.A, -kLog2e * g.B)
-                                : make_float4(0.f, 0.f, 0.f, 0.f);
-        S.geo2[buf][slot] = make_float2(live ? -0.5f * kLog2e * g.C : 0.f, lo2o);
+        S.geo[buf][slot] = live ? make_float4(g.x, g.y, g.A, g.B) : make_float4(0.f, 0.f, 0.f, 0.f);
+        S.geo2[buf][slot] = make_float2(live ? g.C : 0.f, lo2o);
     } else {
         float hi[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
         float lo[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
@@ -158,9 +177,11 @@ __device__ inline void stage(const GRaw &g, int buf, int slot, float xc, float y
             v[0] = -0.5f * kLog2e * g.A;
             v[1] = -0.5f * kLog2e * g.C;
             v[2] = -kLog2e * g.B;
-            v[3] = -kLog2e * (g.A * xh + g.B * yh);
-            v[4] = -kLog2e * (g.C * yh + g.B * xh);
-            k0 = -kLog2e * (0.5f * g.A * xh * xh + 0.5f * g.C * yh * yh + g.B * xh * yh) + lo2o;
+            float gxh, gyh;
+            const float Qh = quad_acc(g.A, g.B, g.C, xh, yh, gxh, gyh);
+            v[3] = -kLog2e * gxh;
+            v[4] = -kLog2e * gyh;
+            k0 = fmaf(Qh, -0.5f * kLog2e, lo2o);
 #pragma unroll
             for (int k = 0; k < 5; ++k) hi[k] = v[k];
             const typename Op<M>::vec vh = Op<M>::cvt(hi);
@@ -239,7 +260,8 @@ __device__ inline float plain_q(const Stage<Mode::Plain> &S, int buf, int idx, c
     const float4 geo = S.geo[buf][idx];
     const float2 g2 = S.geo2[buf][idx];
     const float dx = geo.x - L.px, dy = geo.y - L.py;
-    return (geo.z * dx + geo.w * dy) * dx + (g2.x * dy * dy + g2.y);
+    float gx, gy;
+    return fmaf(quad_acc(geo.z, geo.w, g2.x, dx, dy, gx, gy), -0.5f * kLog2e, g2.y);
 }
 
 // ------------------------------------------------------------------------------- forward

@@ -405,3 +405,21 @@ def test_power_clamp_for_indefinite_conic():
     b = oracle.backward(16, 16, rg, pl, s["means2d"], s["conics"], s["opacity"], s["colors"], g)
     assert np.all(b["dconics"] == 0.0) and np.all(b["dmeans2d"] == 0.0)
     assert b["dopacity"][0] == pytest.approx(1.0, abs=1e-15)
+
+
+def test_work_counters():
+    """n_contrib counts blended Gaussians: the five-stack blends 5 of 6 at its centre pixel, and
+    every pixel blends at most last_contrib Gaussians, which is at most n_eval."""
+    g = json.load(open(os.path.join(GOLDEN, "five_stack.json")))
+    got = oracle.render(gsinputs.stack_scene(g["n"], g["opacity"], at=tuple(g["pixel"])))
+    px, py = g["pixel"]
+    assert got["n_contrib"][py, px] == 5 and got["n_eval"][py, px] == 6
+    s = gsinputs.make_scene("C1")
+    f = oracle.render(s)
+    assert np.all(f["n_contrib"] <= f["last_contrib"]) and np.all(f["last_contrib"] <= f["n_eval"])
+    # with the skip threshold never met nothing is blended
+    s["opacity"][:] = 0.003
+    f0 = oracle.render(s)
+    assert f0["n_contrib"].sum() == 0
+    c = oracle.work_counts(f, f["ranges"])
+    assert c["K"] == int(f["n_contrib"].sum()) and c["Eb"] == int(f["last_contrib"].sum())
