@@ -54,6 +54,9 @@ def parse():
     p.add_argument("--precs", default="fp16,fp32,bf16",
                    help="comma list; the first is the headline")
     p.add_argument("--no-cpu-baseline", action="store_true")
+    p.add_argument("--calib-copy-mib", type=int, default=0,
+                   help="also run one device-to-device copy of this many MiB (a known-size "
+                        "kernel for scaling HBM byte counters)")
     return p.parse_args()
 
 
@@ -202,6 +205,13 @@ def main():
               "is described in DESIGN.md); run with --gpus 1.", file=sys.stderr)
         sys.exit(2)
     dev = torch.device("cuda:0")
+    if args.calib_copy_mib:
+        n = args.calib_copy_mib * (1 << 20) // 4
+        src = torch.ones(n, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     cfg = gsinputs.CONFIGS[args.config]
     fr = Frame(cfg, dev)
     counts = json.load(open(COUNTS))[args.config]

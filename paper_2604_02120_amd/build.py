@@ -22,6 +22,8 @@ HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
     "-munsafe-fp-atomics",
+    # keep per-lane atomics as single instructions (no readlane loop around them)
+    "-mllvm", "-amdgpu-atomic-optimizer-strategy=None",
     # packed FP32 (v_pk_*_f32) stays off
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-Wall", "-Wno-unused-function",

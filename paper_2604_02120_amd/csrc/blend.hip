@@ -47,9 +47,10 @@ namespace {
 
 enum class Mode { Plain, F16, BF16 };
 
-constexpr int kBatch = 256;                 // Gaussians staged per batch (one per thread)
 constexpr int kGroup = 16;                  // Gaussians per MFMA group
-constexpr int kGroups = kBatch / kGroup;
+// Gaussians staged per batch (at most one per thread): forward and backward defaults.
+constexpr int kBatchFwd = 256;
+constexpr int kBatchBwd = 128;
 constexpr float kLog2e = 0x1.715476p+0f;    // log2(e) rounded to FP32
 constexpr float kQCull = -0x1.ffa37cp+2f;   // log2(fp32(1/255)) rounded to FP32
 constexpr float kTauCull = 1.0f / 255.0f;
@@ -93,25 +94,25 @@ template <> struct Op<Mode::BF16> {
 template <> struct Op<Mode::Plain> { typedef h8 vec; };
 
 // ------------------------------------------------------------------------------- LDS staging
-template <Mode M>
+template <Mode M, int NB>
 struct Stage {                 // GEMM form
     typedef typename Op<M>::vec vec;
-    vec ahi[2][kBatch];        // v_g hi terms, 5 used of 8
-    vec alo[2][kBatch];        // v_g lo terms * 2^12
-    float kc[2][kBatch];       // accumulator init: constant term + log2 o (-inf = inert)
-    float4 attr[2][kBatch];    // (log2 o, r, g, b)
+    vec ahi[2][NB];            // v_g hi terms, 5 used of 8
+    vec alo[2][NB];            // v_g lo terms * 2^12
+    float kc[2][NB];           // accumulator init: constant term + log2 o (-inf = inert)
+    float4 attr[2][NB];        // (log2 o, r, g, b)
     vec zero;
 };
-template <>
-struct Stage<Mode::Plain> {    // plain form
-    float4 geo[2][kBatch];     // (x, y, A, B)
-    float2 geo2[2][kBatch];    // (C, log2 o)
-    float4 attr[2][kBatch];    // (log2 o, r, g, b)
+template <int NB>
+struct Stage<Mode::Plain, NB> {  // plain form
+    float4 geo[2][NB];         // (x, y, A, B)
+    float2 geo2[2][NB];        // (C, log2 o)
+    float4 attr[2][NB];        // (log2 o, r, g, b)
 };
 
-template <Mode M>
+template <int NB>
 struct StageBwd {
-    float4 bwd[2][kBatch];     // (x, y, 1/o, index bits)
+    float4 bwd[2][NB];         // (x, y, 1/o, index bits)
 };
 
 // Raw attributes of one list entry, fetched in the prefetch step.
@@ -158,9 +159,9 @@ __device__ inline GRaw fetch(const uint32_t *plist, int64_t pos, bool valid, uin
 }
 
 // Writes one Gaussian into slot `slot` of buffer `buf`. (xc, yc) is the tile centre.
-template <Mode M, bool Bwd>
-__device__ inline void stage(const GRaw &g, int buf, int slot, float xc, float yc, Stage<M> &S,
-                             StageBwd<M> *SB) {
+template <Mode M, int NB, bool Bwd>
+__device__ inline void stage(const GRaw &g, int buf, int slot, float xc, float yc, Stage<M, NB> &S,
+                             StageBwd<NB> *SB) {
     // a Gaussian with o < 1/255 never reaches the skip threshold (alpha <= o); stage it inert
     const bool live = g.valid && g.o >= kTauCull;
     const float lo2o = live ? __log2f(g.o) : -INFINITY;
@@ -236,8 +237,8 @@ __device__ inline void pixel_basis(const Lane &L, typename Op<M>::vec &bhi, type
 }
 
 // q for 16 consecutive staged Gaussians (group g of buffer buf): one value per register.
-template <Mode M>
-__device__ inline f16x group_q_mfma(const Stage<M> &S, int buf, int g, const Lane &L,
+template <Mode M, int NB>
+__device__ inline f16x group_q_mfma(const Stage<M, NB> &S, int buf, int g, const Lane &L,
                                     const typename Op<M>::vec &bhi,
                                     const typename Op<M>::vec &blo) {
     f16x acc;
@@ -256,7 +257,8 @@ __device__ inline f16x group_q_mfma(const Stage<M> &S, int buf, int g, const Lan
 }
 
 // q of one staged Gaussian for this lane's pixel, per pixel in FP32 (Eq. (power)).
-__device__ inline float plain_q(const Stage<Mode::Plain> &S, int buf, int idx, const Lane &L) {
+template <int NB>
+__device__ inline float plain_q(const Stage<Mode::Plain, NB> &S, int buf, int idx, const Lane &L) {
     const float4 geo = S.geo[buf][idx];
     const float2 g2 = S.geo2[buf][idx];
     const float dx = geo.x - L.px, dy = geo.y - L.py;
@@ -286,12 +288,14 @@ __device__ inline void composite(float q, const float4 *attr, int idx, int pos, 
     }
 }
 
-template <Mode M>
+template <Mode M, int NB>
 __global__ __launch_bounds__(kBlock) void k_blend_fwd(
     int W, int H, int gx, int64_t n_tiles, const uint2 *ranges, const uint32_t *plist,
     uint32_t n, const float2 *means, const F3 *conics, const float *opac, const F3 *colors, float bg0,
     float bg1, float bg2, float *image, float *final_T, int32_t *last_contrib) {
-    __shared__ Stage<M> S;
+    static_assert(NB % kGroup == 0 && NB <= kBlock, "batch must be whole groups, <= block");
+    constexpr int kGroups = NB / kGroup;
+    __shared__ Stage<M, NB> S;
     const int64_t tile = xcd_tile(blockIdx.x, n_tiles);
     if (tile >= n_tiles) return;
     const Lane L = lane_setup(tile, gx, W, H);
@@ -304,20 +308,20 @@ __global__ __launch_bounds__(kBlock) void k_blend_fwd(
     }
     const uint2 rg = ranges[tile];
     const int64_t start = rg.x, len = int64_t(rg.y) - int64_t(rg.x);
-    const int nb = int((len + kBatch - 1) / kBatch);
+    const int nb = int((len + NB - 1) / NB);
 
     FwdState st{1.f, 0.f, 0.f, 0.f, L.inside ? kQCull : INFINITY, 0};
-    GRaw nxt = fetch(plist, start + L.t, L.t < len, n, means, conics, opac, colors);
+    GRaw nxt = fetch(plist, start + L.t, L.t < NB && L.t < len, n, means, conics, opac, colors);
     for (int b = 0; b < nb; ++b) {
         const int buf = b & 1;
-        stage<M, false>(nxt, buf, L.t, xc, yc, S, nullptr);
+        if (L.t < NB) stage<M, NB, false>(nxt, buf, L.t, xc, yc, S, nullptr);
         // barrier; also counts the pixels still live (the whole block leaves once none is)
         if (__syncthreads_count(st.thr != INFINITY) == 0) break;
         if (b + 1 < nb) {
-            const int64_t o = int64_t(b + 1) * kBatch + L.t;
-            nxt = fetch(plist, start + o, o < len, n, means, conics, opac, colors);
+            const int64_t o = int64_t(b + 1) * NB + L.t;
+            nxt = fetch(plist, start + o, L.t < NB && o < len, n, means, conics, opac, colors);
         }
-        const int base = b * kBatch;
+        const int base = b * NB;
         const int ng = int((len - base + kGroup - 1) / kGroup) < kGroups
                            ? int((len - base + kGroup - 1) / kGroup) : kGroups;
         for (int g = 0; g < ng; ++g) {
@@ -329,7 +333,7 @@ __global__ __launch_bounds__(kBlock) void k_blend_fwd(
                     composite(plain_q(S, buf, idx, L), S.attr[buf], idx, base + idx, st);
                 }
             } else {
-                const f16x q = group_q_mfma<M>(S, buf, g, L, bhi, blo);
+                const f16x q = group_q_mfma<M, NB>(S, buf, g, L, bhi, blo);
 #pragma unroll
                 for (int v = 0; v < kGroup; ++v)
                     composite(q[v], S.attr[buf], g * kGroup + v, base + g * kGroup + v, st);
@@ -348,86 +352,85 @@ __global__ __launch_bounds__(kBlock) void k_blend_fwd(
 }
 
 // ------------------------------------------------------------------------------- backward
-// Sum over the 64 lanes of a wavefront; the total lands in lane 63 (row shifts within each row of
-// 16 lanes, then the two row broadcasts of GFX9 DPP). Call with every lane active.
-template <int Ctrl, int RowMask>
+// Sum over each row of 16 lanes with DPP row shifts; lane 15 of every row (lanes 15, 31, 47, 63)
+// ends up holding its row's total. Call with every lane active.
+template <int Ctrl>
 __device__ inline float dpp_add(float x) {
-    const int y = __builtin_amdgcn_update_dpp(0, __float_as_int(x), Ctrl, RowMask, 0xf, false);
+    const int y = __builtin_amdgcn_update_dpp(0, __float_as_int(x), Ctrl, 0xf, 0xf, false);
     return x + __int_as_float(y);
 }
-__device__ inline float wave_sum_lane63(float x) {
-    x = dpp_add<0x111, 0xf>(x);  // row_shr:1
-    x = dpp_add<0x112, 0xf>(x);  // row_shr:2
-    x = dpp_add<0x114, 0xf>(x);  // row_shr:4
-    x = dpp_add<0x118, 0xf>(x);  // row_shr:8
-    x = dpp_add<0x142, 0xa>(x);  // row_bcast:15
-    x = dpp_add<0x143, 0xc>(x);  // row_bcast:31
+__device__ inline float row_sum16(float x) {
+    x = dpp_add<0x111>(x);  // row_shr:1
+    x = dpp_add<0x112>(x);  // row_shr:2
+    x = dpp_add<0x114>(x);  // row_shr:4
+    x = dpp_add<0x118>(x);  // row_shr:8
     return x;
 }
+
+constexpr int kGrad = 9;   // per-Gaussian sums kept per batch
 
 struct BwdState {
     float T, Tfin, behind, gr, gg, gb, bgg;
     int last;
 };
 
-// Reverse step for one (Gaussian, pixel) pair; accumulates the pair's gradient terms, reduces them
-// over the wave when any lane has a live pair, and adds the wave's sums to the Gaussian's slots.
-// Slots hold raw sums: dconics <- sum dP (dx^2, dx dy, dy^2), dmeans <- sum dP (dx, dy), which a
-// final pass turns into d/dA, d/dB, d/dC, d/dx, d/dy.
-__device__ inline void reverse_pair(float q, bool in_range, const float4 &attr, const float4 &bw,
-                                    const Lane &L, BwdState &st, float *dmeans, float *dconics,
-                                    float *dopac, float *dcolors) {
+// Reverse step for one (Gaussian, pixel) pair. Nothing but a compare and a scalar branch is
+// spent when no lane of the wave has a live pair. Otherwise the pair's 9 gradient terms are summed
+// over each row of 16 lanes and the row totals are added into the Gaussian's LDS accumulator
+// (`acc`), which the block flushes to global memory once per batch. Raw sums: S_xx, S_xy, S_yy,
+// S_x, S_y (times dL/dpower), dL/do, and the three colour gradients.
+__device__ inline void reverse_pair(float q, bool in_range, const float4 *attr_p,
+                                    const float4 *bw_p, const Lane &L, BwdState &st, float *acc) {
     const bool alive = in_range && (q >= kQCull);
-    float s[9] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+    const unsigned long long live = __builtin_amdgcn_ballot_w64(alive);
+    if (live == 0ull) return;
+    float s[kGrad] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
     if (alive) {
+        const float4 attr = *attr_p;
         const float araw = __builtin_amdgcn_exp2f(fminf(q, attr.x));
         const float a = fminf(araw, kAlphaMax);
-        const float om = 1.0f - a;
-        const float Tb = st.T / om;
+        const float r = __builtin_amdgcn_rcpf(1.0f - a);
+        const float Tb = st.T * r;                       // T in front of this Gaussian
         const float gc = st.gr * attr.y + st.gg * attr.z + st.gb * attr.w;
-        const float dLda = Tb * gc - (st.behind + st.Tfin * st.bgg) / om;
-        st.behind += a * Tb * gc;
-        st.T = Tb;
+        const float dLda = Tb * gc - (st.behind + st.Tfin * st.bgg) * r;
         const float wc = a * Tb;
+        st.behind = fmaf(wc, gc, st.behind);
+        st.T = Tb;
         s[6] = wc * st.gr; s[7] = wc * st.gg; s[8] = wc * st.gb;
         const bool clamp_a = araw >= kAlphaMax;
         const bool clamp_p = q > attr.x;   // power > 0
         if (!clamp_a) {
+            const float4 bw = *bw_p;
             s[5] = a * bw.z * dLda;        // d alpha / d o = alpha / o
             if (!clamp_p) {
                 const float dP = a * dLda;  // d alpha / d power = alpha
                 const float dx = bw.x - L.px, dy = bw.y - L.py;
-                s[0] = dP * dx * dx; s[1] = dP * dx * dy; s[2] = dP * dy * dy;
-                s[3] = dP * dx; s[4] = dP * dy;
+                const float tx = dP * dx, ty = dP * dy;
+                s[0] = tx * dx; s[1] = tx * dy; s[2] = ty * dy;
+                s[3] = tx; s[4] = ty;
             }
         }
     }
-    if (__ballot(alive) != 0) {
 #pragma unroll
-        for (int k = 0; k < 9; ++k) s[k] = wave_sum_lane63(s[k]);
-        if (L.l == 63) {
-            const uint32_t id = __float_as_uint(bw.w);
-            unsafeAtomicAdd(&dconics[3 * id + 0], s[0]);
-            unsafeAtomicAdd(&dconics[3 * id + 1], s[1]);
-            unsafeAtomicAdd(&dconics[3 * id + 2], s[2]);
-            unsafeAtomicAdd(&dmeans[2 * id + 0], s[3]);
-            unsafeAtomicAdd(&dmeans[2 * id + 1], s[4]);
-            unsafeAtomicAdd(&dopac[id], s[5]);
-            unsafeAtomicAdd(&dcolors[3 * id + 0], s[6]);
-            unsafeAtomicAdd(&dcolors[3 * id + 1], s[7]);
-            unsafeAtomicAdd(&dcolors[3 * id + 2], s[8]);
-        }
+    for (int k = 0; k < kGrad; ++k) s[k] = row_sum16(s[k]);
+    const bool row_live = ((live >> (L.l & 48)) & 0xffffull) != 0ull;
+    if ((L.l & 15) == 15 && row_live) {
+#pragma unroll
+        for (int k = 0; k < kGrad; ++k) atomicAdd(&acc[k], s[k]);
     }
 }
 
-template <Mode M>
+template <Mode M, int NB>
 __global__ __launch_bounds__(kBlock) void k_blend_bwd(
     int W, int H, int gx, int64_t n_tiles, const uint2 *ranges, const uint32_t *plist,
     uint32_t n, const float2 *means, const F3 *conics, const float *opac, const F3 *colors, float bg0,
     float bg1, float bg2, const float *final_T, const int32_t *last_contrib,
     const float *dL_dimage, float *dmeans, float *dconics, float *dopac, float *dcolors) {
-    __shared__ Stage<M> S;
-    __shared__ StageBwd<M> SB;
+    static_assert(NB % kGroup == 0 && NB <= kBlock, "batch must be whole groups, <= block");
+    constexpr int kGroups = NB / kGroup;
+    __shared__ Stage<M, NB> S;
+    __shared__ StageBwd<NB> SB;
+    __shared__ float s_acc[NB][kGrad];   // per-Gaussian gradient sums of the current batch
     __shared__ int s_maxlast;
     const int64_t tile = xcd_tile(blockIdx.x, n_tiles);
     if (tile >= n_tiles) return;
@@ -457,48 +460,78 @@ __global__ __launch_bounds__(kBlock) void k_blend_bwd(
     // positions [0, max last) are the only ones that matter (never more than the list holds)
     const int64_t len = s_maxlast < int64_t(rg.y) - int64_t(rg.x) ? s_maxlast
                                                                    : int64_t(rg.y) - int64_t(rg.x);
-    const int nb = int((len + kBatch - 1) / kBatch);
+    const int nb = int((len + NB - 1) / NB);
     if (nb == 0) return;
 
     GRaw nxt;
     {
-        const int64_t o = int64_t(nb - 1) * kBatch + L.t;
-        nxt = fetch(plist, start + o, o < len, n, means, conics, opac, colors);
+        const int64_t o = int64_t(nb - 1) * NB + L.t;
+        nxt = fetch(plist, start + o, L.t < NB && o < len, n, means, conics, opac, colors);
     }
     for (int b = nb - 1; b >= 0; --b) {
         const int buf = b & 1;
-        stage<M, true>(nxt, buf, L.t, xc, yc, S, &SB);
+        if (L.t < NB) {
+            stage<M, NB, true>(nxt, buf, L.t, xc, yc, S, &SB);
+#pragma unroll
+            for (int k = 0; k < kGrad; ++k) s_acc[L.t][k] = 0.f;
+        }
         __syncthreads();
         if (b > 0) {
-            const int64_t o = int64_t(b - 1) * kBatch + L.t;
-            nxt = fetch(plist, start + o, o < len, n, means, conics, opac, colors);
+            const int64_t o = int64_t(b - 1) * NB + L.t;
+            nxt = fetch(plist, start + o, L.t < NB && o < len, n, means, conics, opac, colors);
         }
-        const int base = b * kBatch;
+        const int base = b * NB;
         const int ng = int((len - base + kGroup - 1) / kGroup) < kGroups
                            ? int((len - base + kGroup - 1) / kGroup) : kGroups;
         for (int g = ng - 1; g >= 0; --g) {
             // nothing to do for this wave unless one of its pixels blended past the group start
             if (__ballot(st.last > base + g * kGroup) == 0) continue;
             if constexpr (M == Mode::Plain) {
+                const float4 *attr = &S.attr[buf][g * kGroup];
+                const float4 *bw = &SB.bwd[buf][g * kGroup];
+                float *acc = &s_acc[g * kGroup][0];
+                const int rel = st.last - (base + g * kGroup);   // positions < last are in range
 #pragma unroll
                 for (int v = kGroup - 1; v >= 0; --v) {
-                    const int idx = g * kGroup + v;
-                    const float q = plain_q(S, buf, idx, L);
-                    reverse_pair(q, base + idx < st.last, S.attr[buf][idx], SB.bwd[buf][idx], L, st,
-                                 dmeans, dconics, dopac, dcolors);
+                    const float q = plain_q(S, buf, g * kGroup + v, L);
+                    reverse_pair(q, v < rel, attr + v, bw + v, L, st, acc + v * kGrad);
                 }
             } else {
-                const f16x q = group_q_mfma<M>(S, buf, g, L, bhi, blo);
+                const f16x q = group_q_mfma<M, NB>(S, buf, g, L, bhi, blo);
+                const float4 *attr = &S.attr[buf][g * kGroup];
+                const float4 *bw = &SB.bwd[buf][g * kGroup];
+                float *acc = &s_acc[g * kGroup][0];
+                const int rel = st.last - (base + g * kGroup);
 #pragma unroll
-                for (int v = kGroup - 1; v >= 0; --v) {
-                    const int idx = g * kGroup + v;
-                    reverse_pair(q[v], base + idx < st.last, S.attr[buf][idx], SB.bwd[buf][idx], L,
-                                 st, dmeans, dconics, dopac, dcolors);
-                }
+                for (int v = kGroup - 1; v >= 0; --v)
+                    reverse_pair(q[v], v < rel, attr + v, bw + v, L, st, acc + v * kGrad);
             }
         }
-        // the next stage() writes the other buffer; the buffer read here is rewritten two
-        // iterations later, after the next barrier
+        // flush: thread t owns staged Gaussian t's sums (a Gaussian with no live pair in this
+        // tile has all-zero sums and costs no atomics)
+        __syncthreads();
+        if (L.t >= NB) continue;
+        float a9[kGrad];
+        bool any = false;
+#pragma unroll
+        for (int k = 0; k < kGrad; ++k) {
+            a9[k] = s_acc[L.t][k];
+            any |= a9[k] != 0.f;
+        }
+        if (any) {
+            const uint32_t id = __float_as_uint(SB.bwd[buf][L.t].w);
+            unsafeAtomicAdd(&dconics[3 * id + 0], a9[0]);
+            unsafeAtomicAdd(&dconics[3 * id + 1], a9[1]);
+            unsafeAtomicAdd(&dconics[3 * id + 2], a9[2]);
+            unsafeAtomicAdd(&dmeans[2 * id + 0], a9[3]);
+            unsafeAtomicAdd(&dmeans[2 * id + 1], a9[4]);
+            unsafeAtomicAdd(&dopac[id], a9[5]);
+            unsafeAtomicAdd(&dcolors[3 * id + 0], a9[6]);
+            unsafeAtomicAdd(&dcolors[3 * id + 1], a9[7]);
+            unsafeAtomicAdd(&dcolors[3 * id + 2], a9[8]);
+        }
+        // the next iteration stages into the other buffer and re-zeroes slot t (program order
+        // after this read); the buffer read here is rewritten two iterations later
     }
 }
 
@@ -520,23 +553,23 @@ __global__ __launch_bounds__(256) void k_zero_f32(float *p, int64_t m) {
     if (i < m) p[i] = 0.f;
 }
 
-template <Mode M>
+template <Mode M, int NB = kBatchFwd>
 void launch_fwd(const BlendArgs &a, float *image, float *final_T, int32_t *last, hipStream_t s) {
     const int gx = int(grid_x(a.W));
     const int64_t n_tiles = int64_t(gx) * grid_y(a.H);
-    k_blend_fwd<M><<<dim3(unsigned(xcd_grid(n_tiles))), kBlock, 0, s>>>(
+    k_blend_fwd<M, NB><<<dim3(unsigned(xcd_grid(n_tiles))), kBlock, 0, s>>>(
         a.W, a.H, gx, n_tiles, reinterpret_cast<const uint2 *>(a.ranges), a.point_list, uint32_t(a.n),
         reinterpret_cast<const float2 *>(a.means2d), reinterpret_cast<const F3 *>(a.conics),
         a.opacity, reinterpret_cast<const F3 *>(a.colors), a.bg[0], a.bg[1], a.bg[2], image,
         final_T, last);
 }
 
-template <Mode M>
+template <Mode M, int NB = kBatchBwd>
 void launch_bwd(const BlendArgs &a, const float *final_T, const int32_t *last, const float *dimg,
                 float *dm, float *dc, float *dop, float *dcol, hipStream_t s) {
     const int gx = int(grid_x(a.W));
     const int64_t n_tiles = int64_t(gx) * grid_y(a.H);
-    k_blend_bwd<M><<<dim3(unsigned(xcd_grid(n_tiles))), kBlock, 0, s>>>(
+    k_blend_bwd<M, NB><<<dim3(unsigned(xcd_grid(n_tiles))), kBlock, 0, s>>>(
         a.W, a.H, gx, n_tiles, reinterpret_cast<const uint2 *>(a.ranges), a.point_list, uint32_t(a.n),
         reinterpret_cast<const float2 *>(a.means2d), reinterpret_cast<const F3 *>(a.conics),
         a.opacity, reinterpret_cast<const F3 *>(a.colors), a.bg[0], a.bg[1], a.bg[2], final_T,
