@@ -54,6 +54,8 @@ def parse():
     p.add_argument("--precs", default="fp16,fp32,bf16",
                    help="comma list; the first is the headline")
     p.add_argument("--no-cpu-baseline", action="store_true")
+    p.add_argument("--no-batched", action="store_true",
+                   help="skip the 16-view batched measurement")
     p.add_argument("--calib-copy-mib", type=int, default=0,
                    help="also run one device-to-device copy of this many MiB (a known-size "
                         "kernel for scaling HBM byte counters)")
@@ -133,6 +135,80 @@ def time_path(fr: Frame, prec: str, steps: int, warmup: int) -> dict:
     }
     r["blend_mpix_s"] = px / ((r["fwd_ms"] + r["bwd_ms"]) * 1e-3) / 1e6
     return r
+
+
+def time_batched(steps: int, warmup: int, dev) -> dict:
+    """The multi-view workload: 16 views (854x480 / 1280x720 / 1920x1080 drawn with seed 4), 300k
+    Gaussians each, FP16 GEMM form. One step = binning of every view + one persistent forward
+    launch + one persistent backward launch, autotuned, replayed from a hipGraph. Also timed:
+    the same step eagerly, and as a loop of single-view calls."""
+    scenes = gsinputs.make_views()
+    views = []
+    for sc in scenes:
+        d = {"width": sc["width"], "height": sc["height"]}
+        for k in ("means2d", "conics", "opacity", "colors", "depths", "radii"):
+            d[k] = torch.from_numpy(np.ascontiguousarray(sc[k])).to(dev)
+        views.append(d)
+    bv = api.BatchedViews(views, prec="fp16", tuning="auto")
+    for i, v in enumerate(bv.views):
+        v["dL_dimage"].copy_(torch.from_numpy(gsinputs.make_dloss(v["width"], v["height"], 500 + i)))
+    px = bv.pixels()
+
+    def timed(fn):
+        for _ in range(warmup):
+            fn()
+        torch.cuda.synchronize()
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        t0 = time.perf_counter()
+        a.record()
+        for _ in range(steps):
+            fn()
+        b.record()
+        torch.cuda.synchronize()
+        return 1e3 * (time.perf_counter() - t0) / steps, a.elapsed_time(b) / steps
+
+    eager_wall, eager_ev = timed(bv.step)
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        bv.step()
+    torch.cuda.current_stream().wait_stream(side)
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph):
+        bv.step()
+    graph_wall, graph_ev = timed(graph.replay)
+
+    def per_view_loop():
+        for v in bv.views:
+            W, H = v["width"], v["height"]
+            api.bin_count(v["means2d"], v["radii"], W, H, v["ws"])
+            api.bin_fill(v["means2d"], v["radii"], v["depths"], W, H, v["ws"], v["point_list"],
+                         v["ranges"])
+            img, T, last = api.blend_forward(v["means2d"], v["conics"], v["opacity"], v["colors"],
+                                             v["ranges"], v["point_list"], W, H, (0.0, 0.0, 0.0),
+                                             "fp16", out=(v["image"], v["final_T"], v["last_contrib"]))
+            api.blend_backward(v["means2d"], v["conics"], v["opacity"], v["colors"], v["ranges"],
+                               v["point_list"], W, H, T, last, v["dL_dimage"], (0.0, 0.0, 0.0),
+                               "fp16", out=(v["dL_dmeans2d"], v["dL_dconics"], v["dL_dopacity"],
+                                            v["dL_dcolors"]))
+    loop_wall, loop_ev = timed(per_view_loop)
+    # batched kernels alone (binning excluded), eager, for the blend-only rate
+    def fwd_bwd():
+        bv.forward()
+        bv.backward()
+    fb_wall, fb_ev = timed(fwd_bwd)
+    del graph
+    tune = {k: bv.tuning[k] for k in ("batch_fwd", "batch_bwd", "blocks_per_cu")}
+    out = {"workload": "16 views from {854x480, 1280x720, 1920x1080} (seed 4), 300k Gaussians "
+                       "each (seeds 400+v); step = bin all views + batched fwd + batched bwd",
+           "views": len(bv.views), "pixels": px, "gaussians": sum(v["n"] for v in bv.views),
+           "tuning": tune,
+           "graph_ms_per_step": round(graph_ev, 4), "graph_mpix_s": round(px / graph_ev / 1e3, 2),
+           "eager_ms_per_step": round(eager_ev, 4),
+           "per_view_loop_ms_per_step": round(loop_ev, 4),
+           "batched_blend_ms": round(fb_ev, 4), "batched_blend_mpix_s": round(px / fb_ev / 1e3, 2)}
+    bv.close()
+    return out
 
 
 def kernel_hash() -> str:
@@ -244,6 +320,8 @@ def main():
         line["speedup_vs_plain_fp32"] = {
             "step": round(results["fp32"]["ms_per_step"] / head["ms_per_step"], 3),
             "blend": round(head["blend_mpix_s"] / results["fp32"]["blend_mpix_s"], 3)}
+    if not args.no_batched:
+        line["batched_c4"] = time_batched(max(5, args.steps // 2), 2, dev)
     if not args.no_cpu_baseline:
         line["cpu_baseline"], line["accuracy"] = cpu_baseline_and_accuracy(fr, outputs)
     print(json.dumps(line), flush=True)

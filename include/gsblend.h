@@ -145,6 +145,60 @@ gsb_status gsb_blend_backward(int32_t W, int32_t H, const uint32_t *ranges,
                               const float *dL_dimage, float *dL_dmeans2d, float *dL_dconics,
                               float *dL_dopacity, float *dL_dcolors, void *stream);
 
+/* ---------------------------------------------------------------------------------------------
+ * Batched views: many images (views) of uneven size, each with its own Gaussians and binning,
+ * blended by ONE persistent launch per direction. The (view, tile) items are served from 8 work
+ * queues, one per XCD of the MI355X (each XCD takes a contiguous band of every view), views in
+ * order of decreasing Gaussians per tile (heaviest first); a block whose queue runs dry takes
+ * items from the others. The per-tile computation is exactly gsb_blend_forward /
+ * gsb_blend_backward's, so each view's results equal the single-view calls'.
+ *
+ * A plan holds the view table (device copy), the queue counters and the launch shape. Those are
+ * the only device memory the library allocates; gsb_plan_destroy frees them. The pointers in the
+ * views are captured at creation: the buffers must stay allocated and in place while the plan is
+ * used. Plan calls enqueue only kernels (no memset, no allocation, no synchronisation), so they
+ * can be captured into a hipGraph and replayed. Two plan calls in flight at once on different
+ * streams would share the queue counters: serialise calls on one plan.
+ * ------------------------------------------------------------------------------------------- */
+typedef struct gsb_view {
+    int32_t width, height;             /* image size W x H */
+    int64_t n;                         /* Gaussians of this view */
+    const uint32_t *ranges;            /* device u32[gx*gy][2] (from binning) */
+    const uint32_t *point_list;        /* device u32[pairs] */
+    const float *means2d, *conics, *opacity, *colors;   /* device, shapes as above */
+    float bg[3];                       /* background (by value) */
+    float *image, *final_T;            /* forward outputs: f32[3][H][W], f32[H][W] */
+    int32_t *last_contrib;             /* forward output: i32[H][W] */
+    const float *dL_dimage;            /* backward input f32[3][H][W] */
+    float *dL_dmeans2d, *dL_dconics, *dL_dopacity, *dL_dcolors;   /* backward outputs */
+} gsb_view;
+
+/* Launch shape. Zero fields take the defaults. */
+typedef struct gsb_tuning {
+    int32_t batch_fwd;       /* Gaussians staged in LDS per batch, forward: 64, 128, 256 (256) */
+    int32_t batch_bwd;       /* same, backward (128) */
+    int32_t blocks_per_cu;   /* resident blocks per compute unit; 0 = as many as fit */
+} gsb_tuning;
+
+typedef struct gsb_plan_s *gsb_plan;
+
+/* Validates every view as gsb_blend_forward / gsb_blend_backward would (all outputs, including
+ * the gradients, must be given), uploads the view table and sizes the persistent grids.
+ * tuning may be NULL. On error *plan is NULL and nothing is allocated.
+ * Errors: INVALID, UNSUPPORTED, HIP. */
+gsb_status gsb_plan_create(const gsb_view *views, int32_t n_views, gsb_precision prec,
+                           const gsb_tuning *tuning, gsb_plan *plan);
+
+/* Frees the plan (NULL is allowed). Call once the stream work that uses it has completed. */
+gsb_status gsb_plan_destroy(gsb_plan plan);
+
+/* Forward of every view of the plan (as gsb_blend_forward per view). */
+gsb_status gsb_blend_batched_forward(gsb_plan plan, void *stream);
+
+/* Backward of every view (as gsb_blend_backward per view); the views' final_T and last_contrib
+ * must hold the forward's outputs. */
+gsb_status gsb_blend_batched_backward(gsb_plan plan, void *stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -27,7 +27,27 @@ PRECISIONS = {"fp32": GSB_FP32_PLAIN, "fp16": GSB_FP16_GEMM, "bf16": GSB_BF16_GE
 
 # every function declared in include/gsblend.h
 EXPORTS = ("gsb_abi_version", "gsb_last_error", "gsb_bin_workspace_bytes", "gsb_bin_count",
-           "gsb_bin_fill", "gsb_blend_forward", "gsb_blend_backward")
+           "gsb_bin_fill", "gsb_blend_forward", "gsb_blend_backward", "gsb_plan_create",
+           "gsb_plan_destroy", "gsb_blend_batched_forward", "gsb_blend_batched_backward")
+
+
+class GsbView(ctypes.Structure):
+    """struct gsb_view: one view of a batched plan (device pointers as integers)."""
+    _fields_ = [("width", ctypes.c_int32), ("height", ctypes.c_int32), ("n", ctypes.c_int64),
+                ("ranges", ctypes.c_void_p), ("point_list", ctypes.c_void_p),
+                ("means2d", ctypes.c_void_p), ("conics", ctypes.c_void_p),
+                ("opacity", ctypes.c_void_p), ("colors", ctypes.c_void_p),
+                ("bg", ctypes.c_float * 3),
+                ("image", ctypes.c_void_p), ("final_T", ctypes.c_void_p),
+                ("last_contrib", ctypes.c_void_p), ("dL_dimage", ctypes.c_void_p),
+                ("dL_dmeans2d", ctypes.c_void_p), ("dL_dconics", ctypes.c_void_p),
+                ("dL_dopacity", ctypes.c_void_p), ("dL_dcolors", ctypes.c_void_p)]
+
+
+class GsbTuning(ctypes.Structure):
+    """struct gsb_tuning (zero fields take the library defaults)."""
+    _fields_ = [("batch_fwd", ctypes.c_int32), ("batch_bwd", ctypes.c_int32),
+                ("blocks_per_cu", ctypes.c_int32)]
 
 
 class GsbError(RuntimeError):
@@ -59,6 +79,11 @@ def load() -> ctypes.CDLL:
     lib.gsb_blend_forward.argtypes = [i32, i32, P, P, P, P, P, P, i64, P, i32, P, P, P, P]
     lib.gsb_blend_backward.argtypes = [i32, i32, P, P, P, P, P, P, i64, P, i32, P, P, P, P, P,
                                        P, P, P]
+    lib.gsb_plan_create.argtypes = [ctypes.POINTER(GsbView), i32, i32, ctypes.POINTER(GsbTuning),
+                                    ctypes.POINTER(ctypes.c_void_p)]
+    lib.gsb_plan_destroy.argtypes = [P]
+    lib.gsb_blend_batched_forward.argtypes = [P, P]
+    lib.gsb_blend_batched_backward.argtypes = [P, P]
     for name in EXPORTS[2:]:
         getattr(lib, name).restype = i32
     _lib = lib
@@ -117,3 +142,24 @@ def gsb_blend_backward(W: int, H: int, ranges: int, point_list: int, means2d: in
     _check(load().gsb_blend_backward(W, H, ranges, point_list, means2d, conics, opacity, colors,
                                      n, _bg(bg), prec, final_T, last_contrib, dL_dimage,
                                      dL_dmeans2d, dL_dconics, dL_dopacity, dL_dcolors, stream))
+
+
+def gsb_plan_create(views, prec: int, tuning=None) -> int:
+    """views: sequence of GsbView; tuning: GsbTuning or None. Returns the plan handle."""
+    arr = (GsbView * max(len(views), 1))(*views)
+    out = ctypes.c_void_p(0)
+    tp = ctypes.byref(tuning) if tuning is not None else None
+    _check(load().gsb_plan_create(arr, len(views), prec, tp, ctypes.byref(out)))
+    return int(out.value)
+
+
+def gsb_plan_destroy(plan: int) -> None:
+    _check(load().gsb_plan_destroy(plan))
+
+
+def gsb_blend_batched_forward(plan: int, stream: int = 0) -> None:
+    _check(load().gsb_blend_batched_forward(plan, stream))
+
+
+def gsb_blend_batched_backward(plan: int, stream: int = 0) -> None:
+    _check(load().gsb_blend_batched_backward(plan, stream))

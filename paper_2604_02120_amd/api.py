@@ -7,6 +7,8 @@ Tensors must be contiguous and on the current HIP device:
 """
 from __future__ import annotations
 
+import ctypes
+
 import torch
 
 from . import _lib
@@ -132,3 +134,111 @@ def blend_backward(means2d, conics, opacity, colors, ranges, point_list, W: int,
                             dL_dimage.data_ptr(), dm.data_ptr(), dc.data_ptr(), do.data_ptr(),
                             dcol.data_ptr(), _stream(stream))
     return dm, dc, do, dcol
+
+
+class BatchedViews:
+    """Many views blended by one persistent launch per direction (gsb_plan_*).
+
+    ``scenes``: list of dicts of contiguous device tensors (means2d, conics, opacity, colors,
+    depths, radii) plus ``width``/``height``. Each view's binning buffers are sized once, eagerly,
+    from its exact pair count (times ``capacity_slack``), so that ``bin()``, ``forward()`` and
+    ``backward()`` afterwards enqueue kernels only: the whole step can be captured in a hipGraph.
+    ``tuning``: None (library defaults), a dict (batch_fwd, batch_bwd, blocks_per_cu) or "auto"
+    (``autotune.tune``). ``dL_dimage[v]`` is allocated here (zeros) for the caller to fill.
+    """
+
+    def __init__(self, scenes, prec="fp16", tuning=None, bg=(0.0, 0.0, 0.0),
+                 capacity_slack: float = 1.0, stream=None):
+        self.prec = prec_code(prec)
+        self.bg = tuple(float(v) for v in bg)
+        self.views = []
+        for sc in scenes:
+            W, H = sc["width"], sc["height"]
+            n = sc["radii"].shape[0]
+            dev = sc["means2d"].device
+            ws0 = BinWorkspace(n, 0, W, H, device=dev)
+            pairs = int(bin_count(sc["means2d"], sc["radii"], W, H, ws0, stream).item())
+            cap = max(1, int(pairs * capacity_slack))
+            gx, gy = grid(W, H)
+            v = dict(sc)
+            v.update(
+                n=n, pairs=pairs, ws=BinWorkspace(n, cap, W, H, device=dev),
+                n_pairs=torch.zeros(1, dtype=torch.int64, device=dev),
+                status=torch.zeros(1, dtype=torch.int32, device=dev),
+                point_list=torch.empty(cap, dtype=torch.int32, device=dev),
+                ranges=torch.empty((gx * gy, 2), dtype=torch.int32, device=dev),
+                image=torch.empty((3, H, W), dtype=torch.float32, device=dev),
+                final_T=torch.empty((H, W), dtype=torch.float32, device=dev),
+                last_contrib=torch.empty((H, W), dtype=torch.int32, device=dev),
+                dL_dimage=torch.zeros((3, H, W), dtype=torch.float32, device=dev),
+                dL_dmeans2d=torch.empty((n, 2), dtype=torch.float32, device=dev),
+                dL_dconics=torch.empty((n, 3), dtype=torch.float32, device=dev),
+                dL_dopacity=torch.empty((n,), dtype=torch.float32, device=dev),
+                dL_dcolors=torch.empty((n, 3), dtype=torch.float32, device=dev))
+            self.views.append(v)
+        self.plan = None
+        if tuning == "auto":
+            from . import autotune
+            self._make_plan(None)
+            tuning = autotune.tune(self)
+        self.tuning = tuning
+        self._make_plan(tuning)
+
+    def _gsb_views(self):
+        out = []
+        for v in self.views:
+            out.append(_lib.GsbView(
+                v["width"], v["height"], v["n"], v["ranges"].data_ptr(), v["point_list"].data_ptr(),
+                v["means2d"].data_ptr(), v["conics"].data_ptr(), v["opacity"].data_ptr(),
+                v["colors"].data_ptr(), (ctypes.c_float * 3)(*self.bg), v["image"].data_ptr(),
+                v["final_T"].data_ptr(), v["last_contrib"].data_ptr(), v["dL_dimage"].data_ptr(),
+                v["dL_dmeans2d"].data_ptr(), v["dL_dconics"].data_ptr(),
+                v["dL_dopacity"].data_ptr(), v["dL_dcolors"].data_ptr()))
+        return out
+
+    def _make_plan(self, tuning):
+        if self.plan is not None:
+            _lib.gsb_plan_destroy(self.plan)
+            self.plan = None
+        t = None
+        if tuning:
+            t = _lib.GsbTuning(int(tuning.get("batch_fwd", 0)), int(tuning.get("batch_bwd", 0)),
+                               int(tuning.get("blocks_per_cu", 0)))
+        self.plan = _lib.gsb_plan_create(self._gsb_views(), self.prec, t)
+
+    def bin(self, stream=None):
+        s = _stream(stream)
+        for v in self.views:
+            W, H = v["width"], v["height"]
+            ws = v["ws"]
+            _lib.gsb_bin_count(v["means2d"].data_ptr(), v["radii"].data_ptr(), v["n"], W, H,
+                               ws.ptr(), ws.nbytes, v["n_pairs"].data_ptr(), s)
+            _lib.gsb_bin_fill(v["means2d"].data_ptr(), v["radii"].data_ptr(),
+                              v["depths"].data_ptr(), v["n"], W, H, ws.ptr(), ws.nbytes,
+                              v["point_list"].data_ptr(), v["point_list"].numel(),
+                              v["ranges"].data_ptr(), v["status"].data_ptr(), s)
+
+    def forward(self, stream=None):
+        _lib.gsb_blend_batched_forward(self.plan, _stream(stream))
+
+    def backward(self, stream=None):
+        _lib.gsb_blend_batched_backward(self.plan, _stream(stream))
+
+    def step(self, stream=None):
+        self.bin(stream)
+        self.forward(stream)
+        self.backward(stream)
+
+    def pixels(self) -> int:
+        return sum(v["width"] * v["height"] for v in self.views)
+
+    def close(self):
+        if self.plan is not None:
+            _lib.gsb_plan_destroy(self.plan)
+            self.plan = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -40,6 +40,9 @@
 
 #include <math.h>
 
+#include <algorithm>
+#include <vector>
+
 #include "gsb_internal.h"
 
 namespace gsb {
@@ -288,25 +291,27 @@ __device__ inline void composite(float q, const float4 *attr, int idx, int pos, 
     }
 }
 
+// Forward of one tile of one view (all 256 threads of the block take part; block-uniform control
+// flow around every barrier).
 template <Mode M, int NB>
-__global__ __launch_bounds__(kBlock) void k_blend_fwd(
-    int W, int H, int gx, int64_t n_tiles, const uint2 *ranges, const uint32_t *plist,
-    uint32_t n, const float2 *means, const F3 *conics, const float *opac, const F3 *colors, float bg0,
-    float bg1, float bg2, float *image, float *final_T, int32_t *last_contrib) {
+__device__ inline void fwd_tile(const ViewDesc &v, int64_t tile, Stage<M, NB> &S) {
     static_assert(NB % kGroup == 0 && NB <= kBlock, "batch must be whole groups, <= block");
     constexpr int kGroups = NB / kGroup;
-    __shared__ Stage<M, NB> S;
-    const int64_t tile = xcd_tile(blockIdx.x, n_tiles);
-    if (tile >= n_tiles) return;
-    const Lane L = lane_setup(tile, gx, W, H);
-    const float xc = float(int(tile % gx) * kTile) + 7.5f, yc = float(int(tile / gx) * kTile) + 7.5f;
+    const uint32_t *plist = v.point_list;
+    const uint32_t n = uint32_t(v.n);
+    const float2 *means = reinterpret_cast<const float2 *>(v.means2d);
+    const F3 *conics = reinterpret_cast<const F3 *>(v.conics);
+    const F3 *colors = reinterpret_cast<const F3 *>(v.colors);
+    const float *opac = v.opacity;
+    const Lane L = lane_setup(tile, v.gx, v.W, v.H);
+    const float xc = float(int(tile % v.gx) * kTile) + 7.5f, yc = float(int(tile / v.gx) * kTile) + 7.5f;
     typename Op<M>::vec bhi, blo;
     pixel_basis<M>(L, bhi, blo);
     if (L.t == 0) {
         float z[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
         if constexpr (M != Mode::Plain) S.zero = Op<M>::cvt(z);
     }
-    const uint2 rg = ranges[tile];
+    const uint2 rg = reinterpret_cast<const uint2 *>(v.ranges)[tile];
     const int64_t start = rg.x, len = int64_t(rg.y) - int64_t(rg.x);
     const int nb = int((len + NB - 1) / NB);
 
@@ -328,26 +333,26 @@ __global__ __launch_bounds__(kBlock) void k_blend_fwd(
             if (__ballot(st.thr != INFINITY) == 0) break;
             if constexpr (M == Mode::Plain) {
 #pragma unroll
-                for (int v = 0; v < kGroup; ++v) {
-                    const int idx = g * kGroup + v;
+                for (int u = 0; u < kGroup; ++u) {
+                    const int idx = g * kGroup + u;
                     composite(plain_q(S, buf, idx, L), S.attr[buf], idx, base + idx, st);
                 }
             } else {
                 const f16x q = group_q_mfma<M, NB>(S, buf, g, L, bhi, blo);
 #pragma unroll
-                for (int v = 0; v < kGroup; ++v)
-                    composite(q[v], S.attr[buf], g * kGroup + v, base + g * kGroup + v, st);
+                for (int u = 0; u < kGroup; ++u)
+                    composite(q[u], S.attr[buf], g * kGroup + u, base + g * kGroup + u, st);
             }
         }
     }
     if (L.inside) {
-        const int64_t p = int64_t(L.py) * W + int64_t(L.px);
-        const int64_t HW = int64_t(H) * W;
-        image[p] = st.r + st.T * bg0;
-        image[HW + p] = st.g + st.T * bg1;
-        image[2 * HW + p] = st.b + st.T * bg2;
-        final_T[p] = st.T;
-        last_contrib[p] = st.last;
+        const int64_t p = int64_t(L.py) * v.W + int64_t(L.px);
+        const int64_t HW = int64_t(v.H) * v.W;
+        v.image[p] = st.r + st.T * v.bg[0];
+        v.image[HW + p] = st.g + st.T * v.bg[1];
+        v.image[2 * HW + p] = st.b + st.T * v.bg[2];
+        v.final_T[p] = st.T;
+        v.last_contrib[p] = st.last;
     }
 }
 
@@ -420,22 +425,20 @@ __device__ inline void reverse_pair(float q, bool in_range, const float4 *attr_p
     }
 }
 
+// Backward of one tile of one view.
 template <Mode M, int NB>
-__global__ __launch_bounds__(kBlock) void k_blend_bwd(
-    int W, int H, int gx, int64_t n_tiles, const uint2 *ranges, const uint32_t *plist,
-    uint32_t n, const float2 *means, const F3 *conics, const float *opac, const F3 *colors, float bg0,
-    float bg1, float bg2, const float *final_T, const int32_t *last_contrib,
-    const float *dL_dimage, float *dmeans, float *dconics, float *dopac, float *dcolors) {
+__device__ inline void bwd_tile(const ViewDesc &v, int64_t tile, Stage<M, NB> &S, StageBwd<NB> &SB,
+                                float (*s_acc)[kGrad], int &s_maxlast) {
     static_assert(NB % kGroup == 0 && NB <= kBlock, "batch must be whole groups, <= block");
     constexpr int kGroups = NB / kGroup;
-    __shared__ Stage<M, NB> S;
-    __shared__ StageBwd<NB> SB;
-    __shared__ float s_acc[NB][kGrad];   // per-Gaussian gradient sums of the current batch
-    __shared__ int s_maxlast;
-    const int64_t tile = xcd_tile(blockIdx.x, n_tiles);
-    if (tile >= n_tiles) return;
-    const Lane L = lane_setup(tile, gx, W, H);
-    const float xc = float(int(tile % gx) * kTile) + 7.5f, yc = float(int(tile / gx) * kTile) + 7.5f;
+    const uint32_t *plist = v.point_list;
+    const uint32_t n = uint32_t(v.n);
+    const float2 *means = reinterpret_cast<const float2 *>(v.means2d);
+    const F3 *conics = reinterpret_cast<const F3 *>(v.conics);
+    const F3 *colors = reinterpret_cast<const F3 *>(v.colors);
+    const float *opac = v.opacity;
+    const Lane L = lane_setup(tile, v.gx, v.W, v.H);
+    const float xc = float(int(tile % v.gx) * kTile) + 7.5f, yc = float(int(tile / v.gx) * kTile) + 7.5f;
     typename Op<M>::vec bhi, blo;
     pixel_basis<M>(L, bhi, blo);
     if (L.t == 0) {
@@ -445,17 +448,17 @@ __global__ __launch_bounds__(kBlock) void k_blend_bwd(
     }
     BwdState st{1.f, 1.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0};
     if (L.inside) {
-        const int64_t p = int64_t(L.py) * W + int64_t(L.px);
-        const int64_t HW = int64_t(H) * W;
-        st.T = st.Tfin = final_T[p];
-        st.last = last_contrib[p];
-        st.gr = dL_dimage[p]; st.gg = dL_dimage[HW + p]; st.gb = dL_dimage[2 * HW + p];
-        st.bgg = bg0 * st.gr + bg1 * st.gg + bg2 * st.gb;
+        const int64_t p = int64_t(L.py) * v.W + int64_t(L.px);
+        const int64_t HW = int64_t(v.H) * v.W;
+        st.T = st.Tfin = v.final_T[p];
+        st.last = v.last_contrib[p];
+        st.gr = v.dL_dimage[p]; st.gg = v.dL_dimage[HW + p]; st.gb = v.dL_dimage[2 * HW + p];
+        st.bgg = v.bg[0] * st.gr + v.bg[1] * st.gg + v.bg[2] * st.gb;
     }
     __syncthreads();
     if (st.last > 0) atomicMax(&s_maxlast, st.last);
     __syncthreads();
-    const uint2 rg = ranges[tile];
+    const uint2 rg = reinterpret_cast<const uint2 *>(v.ranges)[tile];
     const int64_t start = rg.x;
     // positions [0, max last) are the only ones that matter (never more than the list holds)
     const int64_t len = s_maxlast < int64_t(rg.y) - int64_t(rg.x) ? s_maxlast
@@ -486,131 +489,383 @@ __global__ __launch_bounds__(kBlock) void k_blend_bwd(
         for (int g = ng - 1; g >= 0; --g) {
             // nothing to do for this wave unless one of its pixels blended past the group start
             if (__ballot(st.last > base + g * kGroup) == 0) continue;
+            const float4 *attr = &S.attr[buf][g * kGroup];
+            const float4 *bw = &SB.bwd[buf][g * kGroup];
+            float *acc = &s_acc[g * kGroup][0];
+            const int rel = st.last - (base + g * kGroup);   // positions < last are in range
             if constexpr (M == Mode::Plain) {
-                const float4 *attr = &S.attr[buf][g * kGroup];
-                const float4 *bw = &SB.bwd[buf][g * kGroup];
-                float *acc = &s_acc[g * kGroup][0];
-                const int rel = st.last - (base + g * kGroup);   // positions < last are in range
 #pragma unroll
-                for (int v = kGroup - 1; v >= 0; --v) {
-                    const float q = plain_q(S, buf, g * kGroup + v, L);
-                    reverse_pair(q, v < rel, attr + v, bw + v, L, st, acc + v * kGrad);
+                for (int u = kGroup - 1; u >= 0; --u) {
+                    const float q = plain_q(S, buf, g * kGroup + u, L);
+                    reverse_pair(q, u < rel, attr + u, bw + u, L, st, acc + u * kGrad);
                 }
             } else {
                 const f16x q = group_q_mfma<M, NB>(S, buf, g, L, bhi, blo);
-                const float4 *attr = &S.attr[buf][g * kGroup];
-                const float4 *bw = &SB.bwd[buf][g * kGroup];
-                float *acc = &s_acc[g * kGroup][0];
-                const int rel = st.last - (base + g * kGroup);
 #pragma unroll
-                for (int v = kGroup - 1; v >= 0; --v)
-                    reverse_pair(q[v], v < rel, attr + v, bw + v, L, st, acc + v * kGrad);
+                for (int u = kGroup - 1; u >= 0; --u)
+                    reverse_pair(q[u], u < rel, attr + u, bw + u, L, st, acc + u * kGrad);
             }
         }
         // flush: thread t owns staged Gaussian t's sums (a Gaussian with no live pair in this
         // tile has all-zero sums and costs no atomics)
         __syncthreads();
-        if (L.t >= NB) continue;
-        float a9[kGrad];
-        bool any = false;
+        if (L.t < NB) {
+            float a9[kGrad];
+            bool any = false;
 #pragma unroll
-        for (int k = 0; k < kGrad; ++k) {
-            a9[k] = s_acc[L.t][k];
-            any |= a9[k] != 0.f;
-        }
-        if (any) {
-            const uint32_t id = __float_as_uint(SB.bwd[buf][L.t].w);
-            unsafeAtomicAdd(&dconics[3 * id + 0], a9[0]);
-            unsafeAtomicAdd(&dconics[3 * id + 1], a9[1]);
-            unsafeAtomicAdd(&dconics[3 * id + 2], a9[2]);
-            unsafeAtomicAdd(&dmeans[2 * id + 0], a9[3]);
-            unsafeAtomicAdd(&dmeans[2 * id + 1], a9[4]);
-            unsafeAtomicAdd(&dopac[id], a9[5]);
-            unsafeAtomicAdd(&dcolors[3 * id + 0], a9[6]);
-            unsafeAtomicAdd(&dcolors[3 * id + 1], a9[7]);
-            unsafeAtomicAdd(&dcolors[3 * id + 2], a9[8]);
+            for (int k = 0; k < kGrad; ++k) {
+                a9[k] = s_acc[L.t][k];
+                any |= a9[k] != 0.f;
+            }
+            if (any) {
+                const uint32_t id = __float_as_uint(SB.bwd[buf][L.t].w);
+                unsafeAtomicAdd(&v.dL_dconics[3 * id + 0], a9[0]);
+                unsafeAtomicAdd(&v.dL_dconics[3 * id + 1], a9[1]);
+                unsafeAtomicAdd(&v.dL_dconics[3 * id + 2], a9[2]);
+                unsafeAtomicAdd(&v.dL_dmeans2d[2 * id + 0], a9[3]);
+                unsafeAtomicAdd(&v.dL_dmeans2d[2 * id + 1], a9[4]);
+                unsafeAtomicAdd(&v.dL_dopacity[id], a9[5]);
+                unsafeAtomicAdd(&v.dL_dcolors[3 * id + 0], a9[6]);
+                unsafeAtomicAdd(&v.dL_dcolors[3 * id + 1], a9[7]);
+                unsafeAtomicAdd(&v.dL_dcolors[3 * id + 2], a9[8]);
+            }
         }
         // the next iteration stages into the other buffer and re-zeroes slot t (program order
         // after this read); the buffer read here is rewritten two iterations later
     }
 }
 
+// ------------------------------------------------------------------------------- kernels
+// Single view: block b renders tile xcd_tile(b).
+template <Mode M, int NB>
+__global__ __launch_bounds__(kBlock) void k_blend_fwd(ViewDesc v) {
+    __shared__ Stage<M, NB> S;
+    const int64_t tile = xcd_tile(blockIdx.x, v.n_tiles);
+    if (tile >= v.n_tiles) return;
+    fwd_tile<M, NB>(v, tile, S);
+}
+
+template <Mode M, int NB>
+__global__ __launch_bounds__(kBlock) void k_blend_bwd(ViewDesc v) {
+    __shared__ Stage<M, NB> S;
+    __shared__ StageBwd<NB> SB;
+    __shared__ float s_acc[NB][kGrad];   // per-Gaussian gradient sums of the current batch
+    __shared__ int s_maxlast;
+    const int64_t tile = xcd_tile(blockIdx.x, v.n_tiles);
+    if (tile >= v.n_tiles) return;
+    bwd_tile<M, NB>(v, tile, S, SB, s_acc, s_maxlast);
+}
+
+// Many views, one persistent launch. The (view, tile) items are split into 8 queues, one per XCD:
+// queue x holds the tiles [n_tiles * x / 8, n_tiles * (x + 1) / 8) of every view, views in plan
+// order (heaviest per-tile cost first). A block serves the queue of its own XCD (block b runs on
+// XCD b % 8) so that neighbouring tiles share that XCD's L2, and moves on to the next queue when
+// its own is empty, so every block exits once all queues are drained.
+// prefix[x * (n_views + 1) + k] = items of queue x that belong to views before k.
+struct Queues {
+    const ViewDesc *views;
+    const int64_t *prefix;
+    unsigned int *counters;    // 8 per direction
+    int n_views;
+};
+
+__device__ inline int64_t band_lo(int64_t n_tiles, int x) { return n_tiles * x / kXcds; }
+
+// Next item for the calling block (thread 0 only): returns false when every queue is drained.
+__device__ inline bool next_item(const Queues &Q, int &q, int &tried, int &view, int64_t &tile) {
+    while (tried < kXcds) {
+        const int64_t *pre = Q.prefix + int64_t(q) * (Q.n_views + 1);
+        const int64_t total = pre[Q.n_views];
+        const int64_t i = total > 0 ? int64_t(atomicAdd(&Q.counters[q], 1u)) : total;
+        if (i < total) {
+            int lo = 0, hi = Q.n_views - 1;       // last k with pre[k] <= i
+            while (lo < hi) {
+                const int mid = (lo + hi + 1) >> 1;
+                if (pre[mid] <= i) lo = mid; else hi = mid - 1;
+            }
+            view = lo;
+            tile = band_lo(Q.views[lo].n_tiles, q) + (i - pre[lo]);
+            return true;
+        }
+        q = (q + 1) % kXcds;
+        ++tried;
+    }
+    return false;
+}
+
+template <Mode M, int NB>
+__global__ __launch_bounds__(kBlock) void k_blend_fwd_batched(Queues Q) {
+    __shared__ Stage<M, NB> S;
+    __shared__ int s_view;
+    __shared__ int64_t s_tile;
+    int q = int(blockIdx.x % kXcds), tried = 0;
+    for (;;) {
+        if (threadIdx.x == 0) {
+            int view = -1;
+            int64_t tile = 0;
+            if (!next_item(Q, q, tried, view, tile)) view = -1;
+            s_view = view;
+            s_tile = tile;
+        }
+        __syncthreads();
+        const int view = s_view;
+        const int64_t tile = s_tile;
+        __syncthreads();
+        if (view < 0) break;
+        fwd_tile<M, NB>(Q.views[view], tile, S);
+        __syncthreads();
+    }
+}
+
+template <Mode M, int NB>
+__global__ __launch_bounds__(kBlock) void k_blend_bwd_batched(Queues Q) {
+    __shared__ Stage<M, NB> S;
+    __shared__ StageBwd<NB> SB;
+    __shared__ float s_acc[NB][kGrad];
+    __shared__ int s_maxlast;
+    __shared__ int s_view;
+    __shared__ int64_t s_tile;
+    int q = int(blockIdx.x % kXcds), tried = 0;
+    for (;;) {
+        if (threadIdx.x == 0) {
+            int view = -1;
+            int64_t tile = 0;
+            if (!next_item(Q, q, tried, view, tile)) view = -1;
+            s_view = view;
+            s_tile = tile;
+        }
+        __syncthreads();
+        const int view = s_view;
+        const int64_t tile = s_tile;
+        __syncthreads();
+        if (view < 0) break;
+        bwd_tile<M, NB>(Q.views[view], tile, S, SB, s_acc, s_maxlast);
+        __syncthreads();
+    }
+}
+
 // Raw sums -> gradients of the stored scalars: d/dA = -S_xx/2, d/dB = -S_xy, d/dC = -S_yy/2,
 // d/dx = -(A S_x + B S_y), d/dy = -(B S_x + C S_y) (power = -A dx^2/2 - B dx dy - C dy^2/2).
-__global__ __launch_bounds__(256) void k_bwd_finish(int64_t n, const F3 *conics, float2 *dmeans,
-                                                    F3 *dconics) {
+// blockIdx.y selects the view.
+__global__ __launch_bounds__(256) void k_bwd_finish(const ViewDesc *views, ViewDesc single) {
+    const ViewDesc &v = views ? views[blockIdx.y] : single;
     const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    const F3 c = conics[i];
-    const F3 s = dconics[i];
-    const float2 m = dmeans[i];
-    dconics[i] = F3{-0.5f * s.a, -s.b, -0.5f * s.c};
-    dmeans[i] = make_float2(-(c.a * m.x + c.b * m.y), -(c.b * m.x + c.c * m.y));
+    if (i >= v.n) return;
+    const F3 c = reinterpret_cast<const F3 *>(v.conics)[i];
+    F3 *dc = reinterpret_cast<F3 *>(v.dL_dconics);
+    float2 *dm = reinterpret_cast<float2 *>(v.dL_dmeans2d);
+    const F3 s = dc[i];
+    const float2 m = dm[i];
+    dc[i] = F3{-0.5f * s.a, -s.b, -0.5f * s.c};
+    dm[i] = make_float2(-(c.a * m.x + c.b * m.y), -(c.b * m.x + c.c * m.y));
 }
 
-__global__ __launch_bounds__(256) void k_zero_f32(float *p, int64_t m) {
+// Zero every gradient output (graph-capturable: a kernel, not a memset). blockIdx.y = view.
+__global__ __launch_bounds__(256) void k_zero_grads(const ViewDesc *views, ViewDesc single) {
+    const ViewDesc &v = views ? views[blockIdx.y] : single;
     const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-    if (i < m) p[i] = 0.f;
+    if (i >= v.n) return;
+    v.dL_dmeans2d[2 * i] = 0.f; v.dL_dmeans2d[2 * i + 1] = 0.f;
+    v.dL_dconics[3 * i] = 0.f; v.dL_dconics[3 * i + 1] = 0.f; v.dL_dconics[3 * i + 2] = 0.f;
+    v.dL_dopacity[i] = 0.f;
+    v.dL_dcolors[3 * i] = 0.f; v.dL_dcolors[3 * i + 1] = 0.f; v.dL_dcolors[3 * i + 2] = 0.f;
 }
 
-template <Mode M, int NB = kBatchFwd>
-void launch_fwd(const BlendArgs &a, float *image, float *final_T, int32_t *last, hipStream_t s) {
-    const int gx = int(grid_x(a.W));
-    const int64_t n_tiles = int64_t(gx) * grid_y(a.H);
-    k_blend_fwd<M, NB><<<dim3(unsigned(xcd_grid(n_tiles))), kBlock, 0, s>>>(
-        a.W, a.H, gx, n_tiles, reinterpret_cast<const uint2 *>(a.ranges), a.point_list, uint32_t(a.n),
-        reinterpret_cast<const float2 *>(a.means2d), reinterpret_cast<const F3 *>(a.conics),
-        a.opacity, reinterpret_cast<const F3 *>(a.colors), a.bg[0], a.bg[1], a.bg[2], image,
-        final_T, last);
+__global__ void k_reset_counters(unsigned int *c, int m) {
+    if (int(threadIdx.x) < m) c[threadIdx.x] = 0u;
 }
 
-template <Mode M, int NB = kBatchBwd>
-void launch_bwd(const BlendArgs &a, const float *final_T, const int32_t *last, const float *dimg,
-                float *dm, float *dc, float *dop, float *dcol, hipStream_t s) {
-    const int gx = int(grid_x(a.W));
-    const int64_t n_tiles = int64_t(gx) * grid_y(a.H);
-    k_blend_bwd<M, NB><<<dim3(unsigned(xcd_grid(n_tiles))), kBlock, 0, s>>>(
-        a.W, a.H, gx, n_tiles, reinterpret_cast<const uint2 *>(a.ranges), a.point_list, uint32_t(a.n),
-        reinterpret_cast<const float2 *>(a.means2d), reinterpret_cast<const F3 *>(a.conics),
-        a.opacity, reinterpret_cast<const F3 *>(a.colors), a.bg[0], a.bg[1], a.bg[2], final_T,
-        last, dimg, dm, dc, dop, dcol);
+// ------------------------------------------------------------------------------- dispatch
+bool valid_batch(int nb) { return nb == 64 || nb == 128 || nb == 256; }
+
+template <Mode M>
+void launch_fwd_single(const ViewDesc &v, int nb, hipStream_t s) {
+    const dim3 grid(unsigned(xcd_grid(v.n_tiles)));
+    if (nb == 64) k_blend_fwd<M, 64><<<grid, kBlock, 0, s>>>(v);
+    else if (nb == 128) k_blend_fwd<M, 128><<<grid, kBlock, 0, s>>>(v);
+    else k_blend_fwd<M, 256><<<grid, kBlock, 0, s>>>(v);
+}
+
+template <Mode M>
+void launch_bwd_single(const ViewDesc &v, int nb, hipStream_t s) {
+    const dim3 grid(unsigned(xcd_grid(v.n_tiles)));
+    if (nb == 64) k_blend_bwd<M, 64><<<grid, kBlock, 0, s>>>(v);
+    else if (nb == 128) k_blend_bwd<M, 128><<<grid, kBlock, 0, s>>>(v);
+    else k_blend_bwd<M, 256><<<grid, kBlock, 0, s>>>(v);
+}
+
+template <Mode M>
+const void *fwd_batched_fn(int nb) {
+    if (nb == 64) return reinterpret_cast<const void *>(&k_blend_fwd_batched<M, 64>);
+    if (nb == 128) return reinterpret_cast<const void *>(&k_blend_fwd_batched<M, 128>);
+    return reinterpret_cast<const void *>(&k_blend_fwd_batched<M, 256>);
+}
+template <Mode M>
+const void *bwd_batched_fn(int nb) {
+    if (nb == 64) return reinterpret_cast<const void *>(&k_blend_bwd_batched<M, 64>);
+    if (nb == 128) return reinterpret_cast<const void *>(&k_blend_bwd_batched<M, 128>);
+    return reinterpret_cast<const void *>(&k_blend_bwd_batched<M, 256>);
+}
+const void *batched_fn(gsb_precision prec, bool fwd, int nb) {
+    switch (prec) {
+        case GSB_FP32_PLAIN: return fwd ? fwd_batched_fn<Mode::Plain>(nb) : bwd_batched_fn<Mode::Plain>(nb);
+        case GSB_FP16_GEMM: return fwd ? fwd_batched_fn<Mode::F16>(nb) : bwd_batched_fn<Mode::F16>(nb);
+        default: return fwd ? fwd_batched_fn<Mode::BF16>(nb) : bwd_batched_fn<Mode::BF16>(nb);
+    }
 }
 
 }  // namespace
 
-gsb_status blend_forward(const BlendArgs &a, gsb_precision prec, float *image, float *final_T,
-                         int32_t *last, hipStream_t s) {
+ViewDesc make_view(int32_t W, int32_t H, const uint32_t *ranges, const uint32_t *point_list,
+                   const float *means2d, const float *conics, const float *opacity,
+                   const float *colors, int64_t n, const float bg[3]) {
+    ViewDesc v{};
+    v.W = W; v.H = H; v.gx = int32_t(grid_x(W));
+    v.n_tiles = grid_x(W) * grid_y(H);
+    v.ranges = ranges; v.point_list = point_list; v.n = n;
+    v.means2d = means2d; v.conics = conics; v.opacity = opacity; v.colors = colors;
+    v.bg[0] = bg[0]; v.bg[1] = bg[1]; v.bg[2] = bg[2];
+    return v;
+}
+
+gsb_status blend_forward(const ViewDesc &v, gsb_precision prec, int nb, hipStream_t s) {
+    if (!valid_batch(nb)) return fail(GSB_ERR_INVALID, "batch %d not in {64, 128, 256}", nb);
     switch (prec) {
-        case GSB_FP32_PLAIN: launch_fwd<Mode::Plain>(a, image, final_T, last, s); break;
-        case GSB_FP16_GEMM: launch_fwd<Mode::F16>(a, image, final_T, last, s); break;
-        case GSB_BF16_GEMM: launch_fwd<Mode::BF16>(a, image, final_T, last, s); break;
+        case GSB_FP32_PLAIN: launch_fwd_single<Mode::Plain>(v, nb, s); break;
+        case GSB_FP16_GEMM: launch_fwd_single<Mode::F16>(v, nb, s); break;
+        case GSB_BF16_GEMM: launch_fwd_single<Mode::BF16>(v, nb, s); break;
         default: return fail(GSB_ERR_INVALID, "unknown precision %d", int(prec));
     }
     return check_launch("blend_forward");
 }
 
-gsb_status blend_backward(const BlendArgs &a, gsb_precision prec, const float *final_T,
-                          const int32_t *last, const float *dimg, float *dm, float *dc,
-                          float *dop, float *dcol, hipStream_t s) {
+gsb_status blend_backward(const ViewDesc &v, gsb_precision prec, int nb, hipStream_t s) {
+    if (!valid_batch(nb)) return fail(GSB_ERR_INVALID, "batch %d not in {64, 128, 256}", nb);
     if (prec != GSB_FP32_PLAIN && prec != GSB_FP16_GEMM && prec != GSB_BF16_GEMM)
         return fail(GSB_ERR_INVALID, "unknown precision %d", int(prec));
-    if (a.n > 0) {
-        const unsigned zb2 = unsigned((2 * a.n + 255) / 256), zb3 = unsigned((3 * a.n + 255) / 256);
-        k_zero_f32<<<zb2, 256, 0, s>>>(dm, 2 * a.n);
-        k_zero_f32<<<zb3, 256, 0, s>>>(dc, 3 * a.n);
-        k_zero_f32<<<unsigned((a.n + 255) / 256), 256, 0, s>>>(dop, a.n);
-        k_zero_f32<<<zb3, 256, 0, s>>>(dcol, 3 * a.n);
-    }
+    const unsigned gz = unsigned((v.n + 255) / 256);
+    if (v.n > 0) k_zero_grads<<<dim3(gz, 1), 256, 0, s>>>(nullptr, v);
     switch (prec) {
-        case GSB_FP32_PLAIN: launch_bwd<Mode::Plain>(a, final_T, last, dimg, dm, dc, dop, dcol, s); break;
-        case GSB_FP16_GEMM: launch_bwd<Mode::F16>(a, final_T, last, dimg, dm, dc, dop, dcol, s); break;
-        default: launch_bwd<Mode::BF16>(a, final_T, last, dimg, dm, dc, dop, dcol, s); break;
+        case GSB_FP32_PLAIN: launch_bwd_single<Mode::Plain>(v, nb, s); break;
+        case GSB_FP16_GEMM: launch_bwd_single<Mode::F16>(v, nb, s); break;
+        default: launch_bwd_single<Mode::BF16>(v, nb, s); break;
     }
-    if (a.n > 0)
-        k_bwd_finish<<<unsigned((a.n + 255) / 256), 256, 0, s>>>(
-            a.n, reinterpret_cast<const F3 *>(a.conics), reinterpret_cast<float2 *>(dm),
-            reinterpret_cast<F3 *>(dc));
+    if (v.n > 0) k_bwd_finish<<<dim3(gz, 1), 256, 0, s>>>(nullptr, v);
     return check_launch("blend_backward");
+}
+
+// ------------------------------------------------------------------------------- plans
+struct Plan {
+    int device = 0;
+    int n_views = 0;
+    gsb_precision prec = GSB_FP16_GEMM;
+    Tuning tune{};
+    int64_t max_n = 0;
+    ViewDesc *d_views = nullptr;    // device copy, plan order
+    int64_t *d_prefix = nullptr;    // [8][n_views + 1]
+    unsigned int *d_counters = nullptr;   // [16]: forward queues, backward queues
+    int grid_fwd = 0, grid_bwd = 0;
+};
+
+gsb_status plan_create(const ViewDesc *views, int n_views, gsb_precision prec, const Tuning &t,
+                       Plan **out) {
+    if (!valid_batch(t.batch_fwd) || !valid_batch(t.batch_bwd))
+        return fail(GSB_ERR_INVALID, "batch sizes must be 64, 128 or 256");
+    Plan *p = new Plan();
+    p->n_views = n_views;
+    p->prec = prec;
+    p->tune = t;
+    hipGetDevice(&p->device);
+    // heaviest-first: Gaussians per tile is proportional to the mean tile list length
+    std::vector<int> order(n_views);
+    for (int i = 0; i < n_views; ++i) order[i] = i;
+    std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
+        return double(views[a].n) / double(views[a].n_tiles) > double(views[b].n) / double(views[b].n_tiles);
+    });
+    std::vector<ViewDesc> ordered(n_views);
+    for (int i = 0; i < n_views; ++i) {
+        ordered[i] = views[order[i]];
+        p->max_n = std::max(p->max_n, ordered[i].n);
+    }
+    std::vector<int64_t> prefix(size_t(kXcds) * (n_views + 1), 0);
+    for (int x = 0; x < kXcds; ++x) {
+        int64_t run = 0;
+        for (int k = 0; k < n_views; ++k) {
+            prefix[size_t(x) * (n_views + 1) + k] = run;
+            const int64_t T = ordered[k].n_tiles;
+            run += T * (x + 1) / kXcds - T * x / kXcds;
+        }
+        prefix[size_t(x) * (n_views + 1) + n_views] = run;
+    }
+    hipError_t e = hipMalloc(&p->d_views, sizeof(ViewDesc) * size_t(n_views));
+    if (e == hipSuccess) e = hipMalloc(&p->d_prefix, sizeof(int64_t) * prefix.size());
+    if (e == hipSuccess) e = hipMalloc(&p->d_counters, sizeof(unsigned int) * 2 * kXcds);
+    if (e == hipSuccess) e = hipMemcpy(p->d_views, ordered.data(), sizeof(ViewDesc) * size_t(n_views), hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(p->d_prefix, prefix.data(), sizeof(int64_t) * prefix.size(), hipMemcpyHostToDevice);
+    int cus = 0, occ_f = 0, occ_b = 0;
+    if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, p->device);
+    if (e == hipSuccess) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ_f, batched_fn(prec, true, t.batch_fwd), kBlock, 0);
+    if (e == hipSuccess) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ_b, batched_fn(prec, false, t.batch_bwd), kBlock, 0);
+    if (e != hipSuccess) {
+        plan_destroy(p);
+        return fail(GSB_ERR_HIP, "plan_create: %s", hipGetErrorString(e));
+    }
+    const int want = t.blocks_per_cu > 0 ? t.blocks_per_cu : 1 << 30;
+    p->grid_fwd = cus * std::max(1, std::min(want, occ_f));
+    p->grid_bwd = cus * std::max(1, std::min(want, occ_b));
+    // a multiple of 8 keeps every XCD's queue served by the same number of blocks
+    p->grid_fwd = (p->grid_fwd + kXcds - 1) / kXcds * kXcds;
+    p->grid_bwd = (p->grid_bwd + kXcds - 1) / kXcds * kXcds;
+    *out = p;
+    return GSB_OK;
+}
+
+void plan_destroy(Plan *p) {
+    if (!p) return;
+    if (p->d_views) hipFree(p->d_views);
+    if (p->d_prefix) hipFree(p->d_prefix);
+    if (p->d_counters) hipFree(p->d_counters);
+    delete p;
+}
+
+template <Mode M>
+void launch_fwd_batched(const Queues &Q, int nb, int grid, hipStream_t s) {
+    if (nb == 64) k_blend_fwd_batched<M, 64><<<grid, kBlock, 0, s>>>(Q);
+    else if (nb == 128) k_blend_fwd_batched<M, 128><<<grid, kBlock, 0, s>>>(Q);
+    else k_blend_fwd_batched<M, 256><<<grid, kBlock, 0, s>>>(Q);
+}
+template <Mode M>
+void launch_bwd_batched(const Queues &Q, int nb, int grid, hipStream_t s) {
+    if (nb == 64) k_blend_bwd_batched<M, 64><<<grid, kBlock, 0, s>>>(Q);
+    else if (nb == 128) k_blend_bwd_batched<M, 128><<<grid, kBlock, 0, s>>>(Q);
+    else k_blend_bwd_batched<M, 256><<<grid, kBlock, 0, s>>>(Q);
+}
+
+gsb_status plan_forward(Plan *p, hipStream_t s) {
+    if (p->n_views == 0) return GSB_OK;
+    Queues Q{p->d_views, p->d_prefix, p->d_counters, p->n_views};
+    k_reset_counters<<<1, 64, 0, s>>>(p->d_counters, kXcds);
+    switch (p->prec) {
+        case GSB_FP32_PLAIN: launch_fwd_batched<Mode::Plain>(Q, p->tune.batch_fwd, p->grid_fwd, s); break;
+        case GSB_FP16_GEMM: launch_fwd_batched<Mode::F16>(Q, p->tune.batch_fwd, p->grid_fwd, s); break;
+        default: launch_fwd_batched<Mode::BF16>(Q, p->tune.batch_fwd, p->grid_fwd, s); break;
+    }
+    return check_launch("blend_batched_forward");
+}
+
+gsb_status plan_backward(Plan *p, hipStream_t s) {
+    if (p->n_views == 0) return GSB_OK;
+    Queues Q{p->d_views, p->d_prefix, p->d_counters + kXcds, p->n_views};
+    const dim3 gz(unsigned((p->max_n + 255) / 256 > 0 ? (p->max_n + 255) / 256 : 1), unsigned(p->n_views));
+    k_zero_grads<<<gz, 256, 0, s>>>(p->d_views, ViewDesc{});
+    k_reset_counters<<<1, 64, 0, s>>>(p->d_counters + kXcds, kXcds);
+    switch (p->prec) {
+        case GSB_FP32_PLAIN: launch_bwd_batched<Mode::Plain>(Q, p->tune.batch_bwd, p->grid_bwd, s); break;
+        case GSB_FP16_GEMM: launch_bwd_batched<Mode::F16>(Q, p->tune.batch_bwd, p->grid_bwd, s); break;
+        default: launch_bwd_batched<Mode::BF16>(Q, p->tune.batch_bwd, p->grid_bwd, s); break;
+    }
+    k_bwd_finish<<<gz, 256, 0, s>>>(p->d_views, ViewDesc{});
+    return check_launch("blend_batched_backward");
 }
 
 }  // namespace gsb

@@ -6,6 +6,9 @@
 #include <stdio.h>
 #include <string.h>
 
+#include <string>
+#include <vector>
+
 #include "gsb_internal.h"
 
 namespace gsb {
@@ -17,6 +20,7 @@ namespace {
 thread_local char g_err[512] = "";
 
 constexpr int32_t kMaxDim = 65536;
+constexpr int32_t kMaxViews = 4096;
 constexpr int kMaxDevices = 64;
 int g_arch_ok[kMaxDevices];   // 0 = unknown, 1 = gfx950, 2 = other
 
@@ -152,8 +156,11 @@ gsb_status gsb_blend_forward(int32_t W, int32_t H, const uint32_t *ranges,
     GSB_TRY(check_blend_common(W, H, ranges, point_list, means2d, conics, opacity, colors, n, bg, prec));
     GSB_REQUIRE(image && final_T && last_contrib, "output pointers must be non-null");
     GSB_TRY(check_device());
-    BlendArgs a{W, H, ranges, point_list, means2d, conics, opacity, colors, n, {bg[0], bg[1], bg[2]}};
-    return blend_forward(a, prec, image, final_T, last_contrib, static_cast<hipStream_t>(stream));
+    ViewDesc v = make_view(W, H, ranges, point_list, means2d, conics, opacity, colors, n, bg);
+    v.image = image;
+    v.final_T = final_T;
+    v.last_contrib = last_contrib;
+    return blend_forward(v, prec, kDefaultBatchFwd, static_cast<hipStream_t>(stream));
 }
 
 gsb_status gsb_blend_backward(int32_t W, int32_t H, const uint32_t *ranges,
@@ -170,9 +177,81 @@ gsb_status gsb_blend_backward(int32_t W, int32_t H, const uint32_t *ranges,
                 "gradient pointers must be non-null");
     GSB_REQUIRE(aligned(dL_dmeans2d, 8), "dL_dmeans2d must be 8-byte aligned");
     GSB_TRY(check_device());
-    BlendArgs a{W, H, ranges, point_list, means2d, conics, opacity, colors, n, {bg[0], bg[1], bg[2]}};
-    return blend_backward(a, prec, final_T, last_contrib, dL_dimage, dL_dmeans2d, dL_dconics,
-                          dL_dopacity, dL_dcolors, static_cast<hipStream_t>(stream));
+    ViewDesc v = make_view(W, H, ranges, point_list, means2d, conics, opacity, colors, n, bg);
+    v.final_T = const_cast<float *>(final_T);
+    v.last_contrib = const_cast<int32_t *>(last_contrib);
+    v.dL_dimage = dL_dimage;
+    v.dL_dmeans2d = dL_dmeans2d;
+    v.dL_dconics = dL_dconics;
+    v.dL_dopacity = dL_dopacity;
+    v.dL_dcolors = dL_dcolors;
+    return blend_backward(v, prec, kDefaultBatchBwd, static_cast<hipStream_t>(stream));
+}
+
+gsb_status gsb_plan_create(const gsb_view *views, int32_t n_views, gsb_precision prec,
+                           const gsb_tuning *tuning, gsb_plan *plan) {
+    g_err[0] = '\0';
+    GSB_REQUIRE(plan != nullptr, "plan must be non-null");
+    *plan = nullptr;
+    GSB_REQUIRE(n_views >= 1 && n_views <= kMaxViews, "n_views = %d outside [1, %d]", int(n_views), kMaxViews);
+    GSB_REQUIRE(views != nullptr, "views must be non-null");
+    GSB_REQUIRE(prec == GSB_FP32_PLAIN || prec == GSB_FP16_GEMM || prec == GSB_BF16_GEMM,
+                "unknown precision %d", int(prec));
+    Tuning t{kDefaultBatchFwd, kDefaultBatchBwd, 0};
+    if (tuning) {
+        if (tuning->batch_fwd) t.batch_fwd = tuning->batch_fwd;
+        if (tuning->batch_bwd) t.batch_bwd = tuning->batch_bwd;
+        t.blocks_per_cu = tuning->blocks_per_cu;
+        GSB_REQUIRE(t.blocks_per_cu >= 0, "blocks_per_cu must be >= 0");
+    }
+    std::vector<ViewDesc> vd(static_cast<size_t>(n_views));
+    for (int i = 0; i < n_views; ++i) {
+        const gsb_view &u = views[i];
+        gsb_status st = check_blend_common(u.width, u.height, u.ranges, u.point_list, u.means2d,
+                                           u.conics, u.opacity, u.colors, u.n, u.bg, prec);
+        if (st != GSB_OK) return fail(st, "view %d: %s", i, std::string(g_err).c_str());
+        GSB_REQUIRE(u.image && u.final_T && u.last_contrib, "view %d: forward outputs must be non-null", i);
+        GSB_REQUIRE(u.dL_dimage != nullptr, "view %d: dL_dimage must be non-null", i);
+        GSB_REQUIRE(u.n == 0 || (u.dL_dmeans2d && u.dL_dconics && u.dL_dopacity && u.dL_dcolors),
+                    "view %d: gradient pointers must be non-null", i);
+        GSB_REQUIRE(aligned(u.dL_dmeans2d, 8), "view %d: dL_dmeans2d must be 8-byte aligned", i);
+        ViewDesc v = make_view(u.width, u.height, u.ranges, u.point_list, u.means2d, u.conics,
+                               u.opacity, u.colors, u.n, u.bg);
+        v.image = u.image;
+        v.final_T = u.final_T;
+        v.last_contrib = u.last_contrib;
+        v.dL_dimage = u.dL_dimage;
+        v.dL_dmeans2d = u.dL_dmeans2d;
+        v.dL_dconics = u.dL_dconics;
+        v.dL_dopacity = u.dL_dopacity;
+        v.dL_dcolors = u.dL_dcolors;
+        vd[size_t(i)] = v;
+    }
+    GSB_TRY(check_device());
+    Plan *p = nullptr;
+    GSB_TRY(plan_create(vd.data(), n_views, prec, t, &p));
+    *plan = reinterpret_cast<gsb_plan>(p);
+    return GSB_OK;
+}
+
+gsb_status gsb_plan_destroy(gsb_plan plan) {
+    g_err[0] = '\0';
+    plan_destroy(reinterpret_cast<Plan *>(plan));
+    return GSB_OK;
+}
+
+gsb_status gsb_blend_batched_forward(gsb_plan plan, void *stream) {
+    g_err[0] = '\0';
+    GSB_REQUIRE(plan != nullptr, "plan must be non-null");
+    GSB_TRY(check_device());
+    return plan_forward(reinterpret_cast<Plan *>(plan), static_cast<hipStream_t>(stream));
+}
+
+gsb_status gsb_blend_batched_backward(gsb_plan plan, void *stream) {
+    g_err[0] = '\0';
+    GSB_REQUIRE(plan != nullptr, "plan must be non-null");
+    GSB_TRY(check_device());
+    return plan_backward(reinterpret_cast<Plan *>(plan), static_cast<hipStream_t>(stream));
 }
 
 }  // extern "C"

@@ -43,18 +43,45 @@ gsb_status bin_fill(const float *means2d, const int32_t *radii, const float *dep
                     uint32_t *ranges, int32_t *status_dev, hipStream_t s);
 
 // ---- blending (blend.hip)
-struct BlendArgs {
-    int32_t W, H;
+// Everything one tile launch needs about one view (image): geometry, inputs, outputs. Built on the
+// host; passed by value to the single-view kernels and stored in device memory for batches.
+struct ViewDesc {
+    int32_t W, H, gx, pad0;
+    int64_t n_tiles;
     const uint32_t *ranges;
     const uint32_t *point_list;
-    const float *means2d, *conics, *opacity, *colors;
     int64_t n;
+    const float *means2d, *conics, *opacity, *colors;
     float bg[3];
+    float pad1;
+    float *image, *final_T;
+    int32_t *last_contrib;
+    const float *dL_dimage;
+    float *dL_dmeans2d, *dL_dconics, *dL_dopacity, *dL_dcolors;
 };
-gsb_status blend_forward(const BlendArgs &a, gsb_precision prec, float *image, float *final_T,
-                         int32_t *last_contrib, hipStream_t s);
-gsb_status blend_backward(const BlendArgs &a, gsb_precision prec, const float *final_T,
-                          const int32_t *last_contrib, const float *dL_dimage, float *dL_dmeans2d,
-                          float *dL_dconics, float *dL_dopacity, float *dL_dcolors, hipStream_t s);
+
+ViewDesc make_view(int32_t W, int32_t H, const uint32_t *ranges, const uint32_t *point_list,
+                   const float *means2d, const float *conics, const float *opacity,
+                   const float *colors, int64_t n, const float bg[3]);
+
+// Launch shape choices (all have defaults).
+struct Tuning {
+    int batch_fwd;       // Gaussians per LDS batch in the forward: 64, 128 or 256
+    int batch_bwd;       // same for the backward
+    int blocks_per_cu;   // persistent batched launches: resident blocks per compute unit
+};
+constexpr int kDefaultBatchFwd = 256;
+constexpr int kDefaultBatchBwd = 128;
+
+gsb_status blend_forward(const ViewDesc &v, gsb_precision prec, int batch, hipStream_t s);
+gsb_status blend_backward(const ViewDesc &v, gsb_precision prec, int batch, hipStream_t s);
+
+// Batched (multi-view) persistent launches.
+struct Plan;
+gsb_status plan_create(const ViewDesc *views, int n_views, gsb_precision prec, const Tuning &t,
+                       Plan **out);
+void plan_destroy(Plan *p);
+gsb_status plan_forward(Plan *p, hipStream_t s);
+gsb_status plan_backward(Plan *p, hipStream_t s);
 
 }  // namespace gsb

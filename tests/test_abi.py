@@ -113,3 +113,25 @@ def test_last_error_is_thread_local():
     t.start(); t.join()
     assert seen == [""]
     assert "n = -1" in _lib.gsb_last_error()
+
+
+def test_plan_validation_before_device():
+    ok = 256
+    with pytest.raises(_lib.GsbError) as e:
+        _lib.gsb_plan_create([], 1)
+    assert e.value.status == _lib.GSB_ERR_INVALID and "n_views" in str(e.value)
+    v = _lib.GsbView(16, 16, 10, ok, ok, ok, ok, ok, ok, (0.0, 0.0, 0.0), ok, ok, ok, 0, ok, ok, ok, ok)
+    with pytest.raises(_lib.GsbError) as e:
+        _lib.gsb_plan_create([v], 1)
+    assert e.value.status == _lib.GSB_ERR_INVALID and "dL_dimage" in str(e.value)
+    bad = _lib.GsbView(0, 16, 10, ok, ok, ok, ok, ok, ok, (0.0, 0.0, 0.0), ok, ok, ok, ok, ok, ok, ok, ok)
+    with pytest.raises(_lib.GsbError) as e:
+        _lib.gsb_plan_create([bad], 1)
+    assert "view 0" in str(e.value) and "image size" in str(e.value)
+    with pytest.raises(_lib.GsbError) as e:
+        _lib.gsb_plan_create([v], 7)
+    assert "precision" in str(e.value)
+    with pytest.raises(_lib.GsbError) as e:
+        _lib.gsb_blend_batched_forward(0)
+    assert "plan" in str(e.value)
+    _lib.gsb_plan_destroy(0)     # NULL is allowed
