@@ -198,11 +198,12 @@ def time_batched(steps: int, warmup: int, dev) -> dict:
         bv.backward()
     fb_wall, fb_ev = timed(fwd_bwd)
     del graph
-    tune = {k: bv.tuning[k] for k in ("batch_fwd", "batch_bwd", "blocks_per_cu")}
+    tune = {k: bv.tuning[k] for k in ("batch_fwd", "batch_bwd", "blocks_per_cu", "launch")}
+    trials = bv.tuning.get("trials")
     out = {"workload": "16 views from {854x480, 1280x720, 1920x1080} (seed 4), 300k Gaussians "
                        "each (seeds 400+v); step = bin all views + batched fwd + batched bwd",
            "views": len(bv.views), "pixels": px, "gaussians": sum(v["n"] for v in bv.views),
-           "tuning": tune,
+           "tuning": tune, "tuning_trials_ms": trials,
            "graph_ms_per_step": round(graph_ev, 4), "graph_mpix_s": round(px / graph_ev / 1e3, 2),
            "eager_ms_per_step": round(eager_ev, 4),
            "per_view_loop_ms_per_step": round(loop_ev, 4),

@@ -147,10 +147,11 @@ gsb_status gsb_blend_backward(int32_t W, int32_t H, const uint32_t *ranges,
 
 /* ---------------------------------------------------------------------------------------------
  * Batched views: many images (views) of uneven size, each with its own Gaussians and binning,
- * blended by ONE persistent launch per direction. The (view, tile) items are served from 8 work
- * queues, one per XCD of the MI355X (each XCD takes a contiguous band of every view), views in
- * order of decreasing Gaussians per tile (heaviest first); a block whose queue runs dry takes
- * items from the others. The per-tile computation is exactly gsb_blend_forward /
+ * blended by ONE launch per direction. The (view, tile) items form 8 queues, one per XCD of the
+ * MI355X (each XCD takes a contiguous band of every view), views in order of decreasing Gaussians
+ * per tile (heaviest first). By default the launch is persistent: resident blocks pull items from
+ * their own XCD's queue and take items from the others once it runs dry; GSB_LAUNCH_GRID instead
+ * launches one block per item in the same order. The per-tile computation is exactly gsb_blend_forward /
  * gsb_blend_backward's, so each view's results equal the single-view calls'.
  *
  * A plan holds the view table (device copy), the queue counters and the launch shape. Those are
@@ -174,10 +175,13 @@ typedef struct gsb_view {
 } gsb_view;
 
 /* Launch shape. Zero fields take the defaults. */
+#define GSB_LAUNCH_PERSISTENT 0   /* resident blocks pull items from the per-XCD queues */
+#define GSB_LAUNCH_GRID 1         /* one block per item: block b takes item b/8 of queue b%8 */
 typedef struct gsb_tuning {
     int32_t batch_fwd;       /* Gaussians staged in LDS per batch, forward: 64, 128, 256 (256) */
     int32_t batch_bwd;       /* same, backward (128) */
-    int32_t blocks_per_cu;   /* resident blocks per compute unit; 0 = as many as fit */
+    int32_t blocks_per_cu;   /* persistent: resident blocks per compute unit; 0 = as many as fit */
+    int32_t launch;          /* GSB_LAUNCH_PERSISTENT (default) or GSB_LAUNCH_GRID */
 } gsb_tuning;
 
 typedef struct gsb_plan_s *gsb_plan;

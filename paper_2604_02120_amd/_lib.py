@@ -24,6 +24,8 @@ GSB_FP32_PLAIN = 0
 GSB_FP16_GEMM = 1
 GSB_BF16_GEMM = 2
 PRECISIONS = {"fp32": GSB_FP32_PLAIN, "fp16": GSB_FP16_GEMM, "bf16": GSB_BF16_GEMM}
+GSB_LAUNCH_PERSISTENT = 0
+GSB_LAUNCH_GRID = 1
 
 # every function declared in include/gsblend.h
 EXPORTS = ("gsb_abi_version", "gsb_last_error", "gsb_bin_workspace_bytes", "gsb_bin_count",
@@ -47,7 +49,7 @@ class GsbView(ctypes.Structure):
 class GsbTuning(ctypes.Structure):
     """struct gsb_tuning (zero fields take the library defaults)."""
     _fields_ = [("batch_fwd", ctypes.c_int32), ("batch_bwd", ctypes.c_int32),
-                ("blocks_per_cu", ctypes.c_int32)]
+                ("blocks_per_cu", ctypes.c_int32), ("launch", ctypes.c_int32)]
 
 
 class GsbError(RuntimeError):

@@ -143,7 +143,8 @@ class BatchedViews:
     depths, radii) plus ``width``/``height``. Each view's binning buffers are sized once, eagerly,
     from its exact pair count (times ``capacity_slack``), so that ``bin()``, ``forward()`` and
     ``backward()`` afterwards enqueue kernels only: the whole step can be captured in a hipGraph.
-    ``tuning``: None (library defaults), a dict (batch_fwd, batch_bwd, blocks_per_cu) or "auto"
+    ``tuning``: None (library defaults), a dict (batch_fwd, batch_bwd, blocks_per_cu, launch) or
+    "auto"
     (``autotune.tune``). ``dL_dimage[v]`` is allocated here (zeros) for the caller to fill.
     """
 
@@ -203,7 +204,7 @@ class BatchedViews:
         t = None
         if tuning:
             t = _lib.GsbTuning(int(tuning.get("batch_fwd", 0)), int(tuning.get("batch_bwd", 0)),
-                               int(tuning.get("blocks_per_cu", 0)))
+                               int(tuning.get("blocks_per_cu", 0)), int(tuning.get("launch", 0)))
         self.plan = _lib.gsb_plan_create(self._gsb_views(), self.prec, t)
 
     def bin(self, stream=None):

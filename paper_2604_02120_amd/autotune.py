@@ -17,9 +17,12 @@ import torch
 
 BATCHES_FWD = (128, 256)
 BATCHES_BWD = (64, 128, 256)
-BLOCKS_PER_CU = (0, 2)          # 0 = as many as fit
-CANDIDATES = [dict(batch_fwd=f, batch_bwd=b, blocks_per_cu=c)
-              for f in BATCHES_FWD for b in BATCHES_BWD for c in BLOCKS_PER_CU]
+BLOCKS_PER_CU = (0, 2)          # persistent launches: 0 = as many as fit
+# launch 0: persistent blocks pulling from the per-XCD queues; 1: one block per item
+CANDIDATES = ([dict(batch_fwd=f, batch_bwd=b, blocks_per_cu=c, launch=0)
+               for f in BATCHES_FWD for b in BATCHES_BWD for c in BLOCKS_PER_CU] +
+              [dict(batch_fwd=f, batch_bwd=b, blocks_per_cu=0, launch=1)
+               for f in BATCHES_FWD for b in BATCHES_BWD])
 
 
 def cache_path() -> str:

@@ -571,6 +571,12 @@ struct Queues {
 
 __device__ inline int64_t band_lo(int64_t n_tiles, int x) { return n_tiles * x / kXcds; }
 
+__device__ inline int64_t uniform_i64(int64_t x) {
+    const uint32_t lo = __builtin_amdgcn_readfirstlane(uint32_t(uint64_t(x)));
+    const uint32_t hi = __builtin_amdgcn_readfirstlane(uint32_t(uint64_t(x) >> 32));
+    return int64_t((uint64_t(hi) << 32) | lo);
+}
+
 // Next item for the calling block (thread 0 only): returns false when every queue is drained.
 __device__ inline bool next_item(const Queues &Q, int &q, int &tried, int &view, int64_t &tile) {
     while (tried < kXcds) {
@@ -593,8 +599,14 @@ __device__ inline bool next_item(const Queues &Q, int &q, int &tried, int &view,
     return false;
 }
 
+// Register budgets for the persistent kernels (waves per SIMD): left alone the compiler spreads
+// their registers over the loop and gives up a wave or more against the single-view kernels;
+// these are the highest targets reached without spilling.
+template <Mode M> constexpr int waves_fwd() { return M == Mode::Plain ? 7 : 5; }
+template <Mode M> constexpr int waves_bwd() { return M == Mode::Plain ? 5 : 4; }
+
 template <Mode M, int NB>
-__global__ __launch_bounds__(kBlock) void k_blend_fwd_batched(Queues Q) {
+__global__ __launch_bounds__(kBlock, waves_fwd<M>()) void k_blend_fwd_batched(Queues Q) {
     __shared__ Stage<M, NB> S;
     __shared__ int s_view;
     __shared__ int64_t s_tile;
@@ -608,17 +620,20 @@ __global__ __launch_bounds__(kBlock) void k_blend_fwd_batched(Queues Q) {
             s_tile = tile;
         }
         __syncthreads();
-        const int view = s_view;
-        const int64_t tile = s_tile;
+        // the item is block-uniform: move it to scalar registers so the view descriptor is read
+        // with scalar loads and its pointers stay in SGPRs
+        const int view = __builtin_amdgcn_readfirstlane(s_view);
+        const int64_t tile = uniform_i64(s_tile);
         __syncthreads();
         if (view < 0) break;
-        fwd_tile<M, NB>(Q.views[view], tile, S);
+        const ViewDesc vd = Q.views[view];
+        fwd_tile<M, NB>(vd, tile, S);
         __syncthreads();
     }
 }
 
 template <Mode M, int NB>
-__global__ __launch_bounds__(kBlock) void k_blend_bwd_batched(Queues Q) {
+__global__ __launch_bounds__(kBlock, waves_bwd<M>()) void k_blend_bwd_batched(Queues Q) {
     __shared__ Stage<M, NB> S;
     __shared__ StageBwd<NB> SB;
     __shared__ float s_acc[NB][kGrad];
@@ -635,13 +650,56 @@ __global__ __launch_bounds__(kBlock) void k_blend_bwd_batched(Queues Q) {
             s_tile = tile;
         }
         __syncthreads();
-        const int view = s_view;
-        const int64_t tile = s_tile;
+        const int view = __builtin_amdgcn_readfirstlane(s_view);
+        const int64_t tile = uniform_i64(s_tile);
         __syncthreads();
         if (view < 0) break;
-        bwd_tile<M, NB>(Q.views[view], tile, S, SB, s_acc, s_maxlast);
+        const ViewDesc vd = Q.views[view];
+        bwd_tile<M, NB>(vd, tile, S, SB, s_acc, s_maxlast);
         __syncthreads();
     }
+}
+
+// The same items in one non-persistent launch: block b takes item b / 8 of queue b % 8 (the
+// dispatcher places block b on XCD b % 8 and hands out blocks in index order, so each XCD still
+// walks its own bands heaviest view first). No loop state: registers as in the single-view
+// kernels.
+__device__ inline bool grid_item(const Queues &Q, int64_t b, int &view, int64_t &tile) {
+    const int x = int(b % kXcds);
+    const int64_t i = b / kXcds;
+    const int64_t *pre = Q.prefix + int64_t(x) * (Q.n_views + 1);
+    if (i >= pre[Q.n_views]) return false;
+    int lo = 0, hi = Q.n_views - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (pre[mid] <= i) lo = mid; else hi = mid - 1;
+    }
+    view = lo;
+    tile = band_lo(Q.views[lo].n_tiles, x) + (i - pre[lo]);
+    return true;
+}
+
+template <Mode M, int NB>
+__global__ __launch_bounds__(kBlock) void k_blend_fwd_grid(Queues Q) {
+    __shared__ Stage<M, NB> S;
+    int view;
+    int64_t tile;
+    if (!grid_item(Q, blockIdx.x, view, tile)) return;
+    const ViewDesc vd = Q.views[view];
+    fwd_tile<M, NB>(vd, tile, S);
+}
+
+template <Mode M, int NB>
+__global__ __launch_bounds__(kBlock) void k_blend_bwd_grid(Queues Q) {
+    __shared__ Stage<M, NB> S;
+    __shared__ StageBwd<NB> SB;
+    __shared__ float s_acc[NB][kGrad];
+    __shared__ int s_maxlast;
+    int view;
+    int64_t tile;
+    if (!grid_item(Q, blockIdx.x, view, tile)) return;
+    const ViewDesc vd = Q.views[view];
+    bwd_tile<M, NB>(vd, tile, S, SB, s_acc, s_maxlast);
 }
 
 // Raw sums -> gradients of the stored scalars: d/dA = -S_xx/2, d/dB = -S_xy, d/dC = -S_yy/2,
@@ -764,13 +822,16 @@ struct Plan {
     ViewDesc *d_views = nullptr;    // device copy, plan order
     int64_t *d_prefix = nullptr;    // [8][n_views + 1]
     unsigned int *d_counters = nullptr;   // [16]: forward queues, backward queues
-    int grid_fwd = 0, grid_bwd = 0;
+    int grid_fwd = 0, grid_bwd = 0;   // persistent grids
+    int64_t grid_items = 0;            // one-shot grid: 8 x the longest queue
 };
 
 gsb_status plan_create(const ViewDesc *views, int n_views, gsb_precision prec, const Tuning &t,
                        Plan **out) {
     if (!valid_batch(t.batch_fwd) || !valid_batch(t.batch_bwd))
         return fail(GSB_ERR_INVALID, "batch sizes must be 64, 128 or 256");
+    if (t.launch != kLaunchPersistent && t.launch != kLaunchGrid)
+        return fail(GSB_ERR_INVALID, "launch mode %d unknown", t.launch);
     Plan *p = new Plan();
     p->n_views = n_views;
     p->prec = prec;
@@ -796,6 +857,7 @@ gsb_status plan_create(const ViewDesc *views, int n_views, gsb_precision prec, c
             run += T * (x + 1) / kXcds - T * x / kXcds;
         }
         prefix[size_t(x) * (n_views + 1) + n_views] = run;
+        p->grid_items = std::max(p->grid_items, run * kXcds);
     }
     hipError_t e = hipMalloc(&p->d_views, sizeof(ViewDesc) * size_t(n_views));
     if (e == hipSuccess) e = hipMalloc(&p->d_prefix, sizeof(int64_t) * prefix.size());
@@ -829,13 +891,29 @@ void plan_destroy(Plan *p) {
 }
 
 template <Mode M>
-void launch_fwd_batched(const Queues &Q, int nb, int grid, hipStream_t s) {
+void launch_fwd_batched(const Queues &Q, int nb, const Plan &p, hipStream_t s) {
+    if (p.tune.launch == kLaunchGrid) {
+        const dim3 g(unsigned(p.grid_items));
+        if (nb == 64) k_blend_fwd_grid<M, 64><<<g, kBlock, 0, s>>>(Q);
+        else if (nb == 128) k_blend_fwd_grid<M, 128><<<g, kBlock, 0, s>>>(Q);
+        else k_blend_fwd_grid<M, 256><<<g, kBlock, 0, s>>>(Q);
+        return;
+    }
+    const int grid = p.grid_fwd;
     if (nb == 64) k_blend_fwd_batched<M, 64><<<grid, kBlock, 0, s>>>(Q);
     else if (nb == 128) k_blend_fwd_batched<M, 128><<<grid, kBlock, 0, s>>>(Q);
     else k_blend_fwd_batched<M, 256><<<grid, kBlock, 0, s>>>(Q);
 }
 template <Mode M>
-void launch_bwd_batched(const Queues &Q, int nb, int grid, hipStream_t s) {
+void launch_bwd_batched(const Queues &Q, int nb, const Plan &p, hipStream_t s) {
+    if (p.tune.launch == kLaunchGrid) {
+        const dim3 g(unsigned(p.grid_items));
+        if (nb == 64) k_blend_bwd_grid<M, 64><<<g, kBlock, 0, s>>>(Q);
+        else if (nb == 128) k_blend_bwd_grid<M, 128><<<g, kBlock, 0, s>>>(Q);
+        else k_blend_bwd_grid<M, 256><<<g, kBlock, 0, s>>>(Q);
+        return;
+    }
+    const int grid = p.grid_bwd;
     if (nb == 64) k_blend_bwd_batched<M, 64><<<grid, kBlock, 0, s>>>(Q);
     else if (nb == 128) k_blend_bwd_batched<M, 128><<<grid, kBlock, 0, s>>>(Q);
     else k_blend_bwd_batched<M, 256><<<grid, kBlock, 0, s>>>(Q);
@@ -844,11 +922,11 @@ void launch_bwd_batched(const Queues &Q, int nb, int grid, hipStream_t s) {
 gsb_status plan_forward(Plan *p, hipStream_t s) {
     if (p->n_views == 0) return GSB_OK;
     Queues Q{p->d_views, p->d_prefix, p->d_counters, p->n_views};
-    k_reset_counters<<<1, 64, 0, s>>>(p->d_counters, kXcds);
+    if (p->tune.launch == kLaunchPersistent) k_reset_counters<<<1, 64, 0, s>>>(p->d_counters, kXcds);
     switch (p->prec) {
-        case GSB_FP32_PLAIN: launch_fwd_batched<Mode::Plain>(Q, p->tune.batch_fwd, p->grid_fwd, s); break;
-        case GSB_FP16_GEMM: launch_fwd_batched<Mode::F16>(Q, p->tune.batch_fwd, p->grid_fwd, s); break;
-        default: launch_fwd_batched<Mode::BF16>(Q, p->tune.batch_fwd, p->grid_fwd, s); break;
+        case GSB_FP32_PLAIN: launch_fwd_batched<Mode::Plain>(Q, p->tune.batch_fwd, *p, s); break;
+        case GSB_FP16_GEMM: launch_fwd_batched<Mode::F16>(Q, p->tune.batch_fwd, *p, s); break;
+        default: launch_fwd_batched<Mode::BF16>(Q, p->tune.batch_fwd, *p, s); break;
     }
     return check_launch("blend_batched_forward");
 }
@@ -858,11 +936,12 @@ gsb_status plan_backward(Plan *p, hipStream_t s) {
     Queues Q{p->d_views, p->d_prefix, p->d_counters + kXcds, p->n_views};
     const dim3 gz(unsigned((p->max_n + 255) / 256 > 0 ? (p->max_n + 255) / 256 : 1), unsigned(p->n_views));
     k_zero_grads<<<gz, 256, 0, s>>>(p->d_views, ViewDesc{});
-    k_reset_counters<<<1, 64, 0, s>>>(p->d_counters + kXcds, kXcds);
+    if (p->tune.launch == kLaunchPersistent)
+        k_reset_counters<<<1, 64, 0, s>>>(p->d_counters + kXcds, kXcds);
     switch (p->prec) {
-        case GSB_FP32_PLAIN: launch_bwd_batched<Mode::Plain>(Q, p->tune.batch_bwd, p->grid_bwd, s); break;
-        case GSB_FP16_GEMM: launch_bwd_batched<Mode::F16>(Q, p->tune.batch_bwd, p->grid_bwd, s); break;
-        default: launch_bwd_batched<Mode::BF16>(Q, p->tune.batch_bwd, p->grid_bwd, s); break;
+        case GSB_FP32_PLAIN: launch_bwd_batched<Mode::Plain>(Q, p->tune.batch_bwd, *p, s); break;
+        case GSB_FP16_GEMM: launch_bwd_batched<Mode::F16>(Q, p->tune.batch_bwd, *p, s); break;
+        default: launch_bwd_batched<Mode::BF16>(Q, p->tune.batch_bwd, *p, s); break;
     }
     k_bwd_finish<<<gz, 256, 0, s>>>(p->d_views, ViewDesc{});
     return check_launch("blend_batched_backward");

@@ -197,12 +197,15 @@ gsb_status gsb_plan_create(const gsb_view *views, int32_t n_views, gsb_precision
     GSB_REQUIRE(views != nullptr, "views must be non-null");
     GSB_REQUIRE(prec == GSB_FP32_PLAIN || prec == GSB_FP16_GEMM || prec == GSB_BF16_GEMM,
                 "unknown precision %d", int(prec));
-    Tuning t{kDefaultBatchFwd, kDefaultBatchBwd, 0};
+    Tuning t{kDefaultBatchFwd, kDefaultBatchBwd, 0, kLaunchPersistent};
     if (tuning) {
         if (tuning->batch_fwd) t.batch_fwd = tuning->batch_fwd;
         if (tuning->batch_bwd) t.batch_bwd = tuning->batch_bwd;
         t.blocks_per_cu = tuning->blocks_per_cu;
+        t.launch = tuning->launch;
         GSB_REQUIRE(t.blocks_per_cu >= 0, "blocks_per_cu must be >= 0");
+        GSB_REQUIRE(t.launch == GSB_LAUNCH_PERSISTENT || t.launch == GSB_LAUNCH_GRID,
+                    "launch mode %d unknown", int(t.launch));
     }
     std::vector<ViewDesc> vd(static_cast<size_t>(n_views));
     for (int i = 0; i < n_views; ++i) {

@@ -69,7 +69,10 @@ struct Tuning {
     int batch_fwd;       // Gaussians per LDS batch in the forward: 64, 128 or 256
     int batch_bwd;       // same for the backward
     int blocks_per_cu;   // persistent batched launches: resident blocks per compute unit
+    int launch;          // batched: kLaunchPersistent or kLaunchGrid
 };
+constexpr int kLaunchPersistent = 0;
+constexpr int kLaunchGrid = 1;
 constexpr int kDefaultBatchFwd = 256;
 constexpr int kDefaultBatchBwd = 128;
 

@@ -150,11 +150,11 @@ def test_autotune_picks_a_candidate(gpu, small_views, tmp_path, monkeypatch):
     bv = api.BatchedViews(views, prec="fp16")
     best = autotune.tune(bv, reps=2)
     say(f"[autotune] {best}")
-    assert {k: best[k] for k in ("batch_fwd", "batch_bwd", "blocks_per_cu")} in autotune.CANDIDATES
+    keys = ("batch_fwd", "batch_bwd", "blocks_per_cu", "launch")
+    assert {k: best[k] for k in keys} in autotune.CANDIDATES
     assert len(best["trials"]) == len(autotune.CANDIDATES)
     again = autotune.tune(bv)            # from the cache
-    assert {k: again[k] for k in ("batch_fwd", "batch_bwd", "blocks_per_cu")} == \
-        {k: best[k] for k in ("batch_fwd", "batch_bwd", "blocks_per_cu")}
+    assert {k: again[k] for k in keys} == {k: best[k] for k in keys}
     bv.close()
 
 
