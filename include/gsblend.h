@@ -79,8 +79,8 @@ const char *gsb_last_error(void);
 gsb_status gsb_bin_workspace_bytes(int64_t n, int64_t pair_capacity, int32_t W, int32_t H,
                                    size_t *bytes);
 
-/* Counts the pairs each Gaussian emits and their exclusive prefix sum (kept in `ws`), and writes
- * the total to the device int64 *n_pairs_dev. Asynchronous on `stream`.
+/* Counts the pairs each Gaussian emits (kept in `ws`) and writes the total to the device int64
+ * *n_pairs_dev. Asynchronous on `stream`.
  * ws: device workspace of ws_bytes >= gsb_bin_workspace_bytes(n, 0, W, H) bytes.
  * Errors: INVALID for null pointers (means2d/radii may be null only when n == 0), bad sizes or a
  * too-small workspace; HIP for launch failures. */
@@ -88,7 +88,11 @@ gsb_status gsb_bin_count(const float *means2d, const int32_t *radii, int64_t n, 
                          int32_t H, void *ws, size_t ws_bytes, int64_t *n_pairs_dev,
                          void *stream);
 
-/* Emits, sorts and ranges the pairs counted by the preceding gsb_bin_count on the same `ws`.
+/* Emits, sorts and ranges the pairs counted by the preceding gsb_bin_count on the same `ws`
+ * (a workspace at least as large, whose leading gsb_bin_workspace_bytes(n, 0, W, H) bytes are the
+ * ones gsb_bin_count wrote). Implementation: the Gaussians are sorted by depth, pairs are emitted
+ * in that order and stably sorted on the tile id alone, which yields the same (tile, depth, index)
+ * order as sorting the 64-bit keys.
  * point_list: device u32[pair_capacity], receives the Gaussian index of each sorted pair.
  * ranges:     device u32[gx*gy][2], receives [start, end) of each tile in point_list, [0, 0) for
  *             an empty tile.

@@ -1,11 +1,20 @@
-// Tile binning on the GPU: per-Gaussian tile count and prefix sum, duplication with
-// tile|depth keys (paper §2.1(b)), stable LSD radix sort of the keys (§2.1(c)), and per-tile
-// [start, end) ranges of the sorted list (the per-tile index lists consumed by Alg. 1 / Alg. 2).
+// Tile binning on the GPU: duplication with tile|depth keys (paper §2.1(b)), depth sort (§2.1(c))
+// and per-tile [start, end) ranges of the sorted list (the per-tile index lists that Alg. 1 and
+// Alg. 2 consume).
 //
-// Everything is integer work and bit-exact: the covered-tile rectangle is evaluated in integer
-// arithmetic (floor((x - r)/16) == (floor(x) - r) >> 4 for integer r), and the sort is stable over
-// Gaussian-major emission order, so ties in depth keep increasing Gaussian index.
+// The result is the list of (tile, Gaussian) pairs ordered by (tile, depth, Gaussian index). It is
+// produced without ever sorting 64-bit tile|depth keys:
+//   1. the Gaussians themselves are sorted by depth (stable LSD radix sort of N 32-bit keys, so
+//      equal depths keep increasing index): this fixes every Gaussian's rank in (depth, index);
+//   2. pairs are emitted in rank order, each with its tile id as a 32-bit key;
+//   3. a stable LSD radix sort of the pairs on the tile id alone (ceil(log2 tiles / 8) passes, 2
+//      up to 65536 tiles) then leaves each tile's pairs in rank order, i.e. (depth, index) order.
+// Against sorting (tile << 32 | depth) pairs directly this moves ~48 instead of ~200 bytes per
+// pair. Everything is integer work and bit-exact: the covered-tile rectangle is evaluated in
+// integer arithmetic (floor((x - r)/16) == (floor(x) - r) >> 4 for integer r).
 #include <hip/hip_runtime.h>
+
+#include <utility>
 
 #include "gsb_internal.h"
 
@@ -19,6 +28,7 @@ constexpr int kScanTopThreads = 1024;
 constexpr int kScanTopItems = 4;
 constexpr int kScanMaxBlocks = kScanTopThreads * kScanTopItems;   // single-block top level
 constexpr int64_t kScanMaxLen = int64_t(kScanTile) * kScanMaxBlocks;  // 16.7M elements
+constexpr int kScanSmallBlocks = 1;   // arrays of at most one block: the one-block scan (one launch)
 
 constexpr int kSortThreads = 256;
 constexpr int kSortItems = 16;                           // keys per thread
@@ -26,29 +36,40 @@ constexpr int kSortTile = kSortThreads * kSortItems;     // 4096 keys per block
 constexpr int kRadixBits = 8;
 constexpr int kRadix = 1 << kRadixBits;
 
+constexpr int kBigRect = 32;   // rectangles with more tiles are emitted by the whole wavefront
+
 struct BinHeader {
-    unsigned long long total;   // pairs counted by bin_count
-    unsigned long long pairs;   // min(total, capacity), set by bin_fill
-    uint32_t pad[12];
+    unsigned long long total;     // pairs counted by bin_count
+    unsigned long long pairs;     // min(total, capacity), set by bin_fill
+    unsigned long long gaussians; // n, for the depth sort
+    uint32_t pad[10];
 };
 
 size_t align256(size_t b) { return (b + 255) & ~size_t(255); }
 
 struct Layout {
-    size_t hdr, offsets, partials, keys_a, keys_b, vals_tmp, hist, end;
+    // bin_count's part (depends on n only)
+    size_t hdr, counts, partials;
+    // bin_fill's part
+    size_t dkey_a, dkey_b, dval_a, dval_b, offs, tkey_a, tkey_b, vals_tmp, hist, end;
 };
 
 Layout layout(int64_t n, int64_t cap) {
     Layout L;
+    const size_t nn = size_t(n > 0 ? n : 1), cc = size_t(cap > 0 ? cap : 1);
     size_t o = 0;
     L.hdr = o;       o += align256(sizeof(BinHeader));
-    L.offsets = o;   o += align256(sizeof(unsigned long long) * size_t(n > 0 ? n : 1));
+    L.counts = o;    o += align256(sizeof(unsigned long long) * nn);
     L.partials = o;  o += align256(sizeof(unsigned long long) * kScanMaxBlocks);
-    // everything below depends on the pair capacity (bin_count uses only the part above)
-    const int64_t nblk = (cap + kSortTile - 1) / kSortTile;
-    L.keys_a = o;    o += align256(sizeof(unsigned long long) * size_t(cap));
-    L.keys_b = o;    o += align256(sizeof(unsigned long long) * size_t(cap));
-    L.vals_tmp = o;  o += align256(sizeof(uint32_t) * size_t(cap));
+    L.dkey_a = o;    o += align256(sizeof(uint32_t) * nn);
+    L.dkey_b = o;    o += align256(sizeof(uint32_t) * nn);
+    L.dval_a = o;    o += align256(sizeof(uint32_t) * nn);
+    L.dval_b = o;    o += align256(sizeof(uint32_t) * nn);
+    L.offs = o;      o += align256(sizeof(unsigned long long) * nn);
+    L.tkey_a = o;    o += align256(sizeof(uint32_t) * cc);
+    L.tkey_b = o;    o += align256(sizeof(uint32_t) * cc);
+    L.vals_tmp = o;  o += align256(sizeof(uint32_t) * cc);
+    const int64_t nblk = ((n > cap ? n : cap) + kSortTile - 1) / kSortTile;
     L.hist = o;      o += align256(sizeof(uint32_t) * size_t(kRadix) * size_t(nblk > 0 ? nblk : 1));
     L.end = o;
     return L;
@@ -83,8 +104,39 @@ __device__ T block_exclusive_scan(T v, T *s_wave, T &total) {
 }
 
 // ------------------------------------------------------------------------------- device scan
-// Exclusive prefix sum in three launches: per-block sums, a single-block scan of those, then a
-// per-block scan with the block's offset. `in` and `out` may alias.
+// Exclusive prefix sum. Short arrays: one block walks the array in chunks with a running carry.
+// Long arrays: per-block sums, a single-block scan of those, then a per-block scan with the
+// block's offset. `in` and `out` may alias. The total goes to *total_a / *total_b if given.
+template <typename T>
+__global__ __launch_bounds__(kScanTopThreads) void k_scan_small(T *data, int64_t m,
+                                                                unsigned long long *total_a,
+                                                                long long *total_b) {
+    constexpr int kItems = 16;
+    __shared__ T s_wave[kScanTopThreads / 64];
+    T carry = 0;
+    for (int64_t base = 0; base < m; base += int64_t(kScanTopThreads) * kItems) {
+        const int64_t b = base + int64_t(threadIdx.x) * kItems;
+        T v[kItems], sum = 0;
+#pragma unroll
+        for (int k = 0; k < kItems; ++k) {
+            v[k] = (b + k < m) ? data[b + k] : T(0);
+            sum += v[k];
+        }
+        T tot;
+        T run = block_exclusive_scan<T>(sum, s_wave, tot) + carry;
+#pragma unroll
+        for (int k = 0; k < kItems; ++k) {
+            if (b + k < m) data[b + k] = run;
+            run += v[k];
+        }
+        carry += tot;
+    }
+    if (threadIdx.x == 0) {
+        if (total_a) *total_a = (unsigned long long)carry;
+        if (total_b) *total_b = (long long)carry;
+    }
+}
+
 template <typename T>
 __global__ __launch_bounds__(kScanThreads) void k_scan_reduce(const T *in, int64_t m, T *partial) {
     __shared__ T s_wave[kScanThreads / 64];
@@ -143,13 +195,18 @@ __global__ __launch_bounds__(kScanThreads) void k_scan_down(const T *in, T *out,
     }
 }
 
+// scan (down = true) or total only (down = false)
 template <typename T>
 void launch_scan(T *data, int64_t m, T *partial, unsigned long long *total_a, long long *total_b,
-                 hipStream_t s) {
+                 hipStream_t s, bool down = true) {
     const int64_t nb = (m + kScanTile - 1) / kScanTile;
+    if (down && nb <= kScanSmallBlocks) {
+        k_scan_small<T><<<1, kScanTopThreads, 0, s>>>(data, m, total_a, total_b);
+        return;
+    }
     if (nb > 0) k_scan_reduce<T><<<dim3(unsigned(nb)), kScanThreads, 0, s>>>(data, m, partial);
     k_scan_top<T><<<1, kScanTopThreads, 0, s>>>(partial, nb, total_a, total_b);
-    if (nb > 0) k_scan_down<T><<<dim3(unsigned(nb)), kScanThreads, 0, s>>>(data, data, m, partial);
+    if (down && nb > 0) k_scan_down<T><<<dim3(unsigned(nb)), kScanThreads, 0, s>>>(data, data, m, partial);
 }
 
 // ------------------------------------------------------------------------------- tile rectangle
@@ -183,46 +240,134 @@ __global__ __launch_bounds__(256) void k_bin_count(const float2 *means, const in
     counts[i] = (unsigned long long)(R.tx1 - R.tx0) * (unsigned long long)(R.ty1 - R.ty0);
 }
 
-// One thread per Gaussian writes its keys at its prefix-sum offset, row-major over its tiles.
-__global__ __launch_bounds__(256) void k_bin_fill(const float2 *means, const int32_t *radii,
-                                                  const float *depths, int64_t n, int32_t gx,
-                                                  int32_t gy, const unsigned long long *offsets,
-                                                  BinHeader *hdr, int64_t cap,
-                                                  unsigned long long *keys, uint32_t *vals,
-                                                  int32_t *status) {
+// Depth keys: the float's bits, made order-preserving for any sign (a no-op flip of the sign bit
+// for the positive depths of the contract), and the Gaussian index as value.
+__global__ __launch_bounds__(256) void k_depth_keys(const float *depths, int64_t n, uint32_t *keys,
+                                                    uint32_t *vals, BinHeader *hdr) {
     const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-    if (i == 0) {
+    if (i == 0) hdr->gaussians = (unsigned long long)n;
+    if (i >= n) return;
+    const uint32_t b = __float_as_uint(depths[i]);
+    keys[i] = (b & 0x80000000u) ? ~b : (b | 0x80000000u);
+    vals[i] = uint32_t(i);
+}
+
+// Counts in depth-rank order (scanned next into each rank's output offset).
+__global__ __launch_bounds__(256) void k_rank_counts(const uint32_t *sorted_idx,
+                                                     const unsigned long long *counts, int64_t n,
+                                                     unsigned long long *offs) {
+    const int64_t j = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (j < n) offs[j] = counts[sorted_idx[j]];
+}
+
+// Emits the pairs of the Gaussian of rank j at offs[j]: tile id as key, Gaussian index as value.
+// The block's 256 consecutive ranks own one contiguous output segment; when it fits in LDS the
+// pairs are assembled there and written out in order (coalesced), otherwise straight to memory.
+// A thread emits its own rectangle when it is small; larger ones are emitted by the whole
+// wavefront together, one after the other.
+constexpr int kFillStage = 4096;   // pairs staged per block
+
+struct PairSink {
+    uint32_t *keys, *vals;           // global
+    uint32_t *skey, *sval;           // LDS segment, or null
+    unsigned long long seg0, cap;    // first output index of the block, capacity
+    __device__ inline void put(unsigned long long o, uint32_t key, uint32_t val) const {
+        if (skey) {
+            skey[o - seg0] = key;
+            sval[o - seg0] = val;
+        } else if (o < cap) {
+            keys[o] = key;
+            vals[o] = val;
+        }
+    }
+};
+
+__global__ __launch_bounds__(256) void k_bin_fill(const float2 *means, const int32_t *radii,
+                                                  const uint32_t *sorted_idx, int64_t n,
+                                                  int32_t gx, int32_t gy,
+                                                  const unsigned long long *offs,
+                                                  const unsigned long long *counts, BinHeader *hdr,
+                                                  int64_t cap, uint32_t *keys, uint32_t *vals,
+                                                  int32_t *status) {
+    __shared__ uint32_t s_key[kFillStage], s_val[kFillStage];
+    const int64_t j = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (j == 0) {
         const unsigned long long total = hdr->total;
         hdr->pairs = total < (unsigned long long)cap ? total : (unsigned long long)cap;
         *status = total > (unsigned long long)cap ? GSB_ERR_CAPACITY : GSB_OK;
     }
-    if (i >= n) return;
-    const float2 m = means[i];
-    const Rect R = tile_rect(m.x, m.y, radii[i], gx, gy);
-    const unsigned long long dbits = __float_as_uint(depths[i]);
-    unsigned long long o = offsets[i];
-    for (int32_t ty = R.ty0; ty < R.ty1; ++ty)
-        for (int32_t tx = R.tx0; tx < R.tx1; ++tx, ++o) {
-            if (o >= (unsigned long long)cap) return;
-            keys[o] = ((unsigned long long)(int64_t(ty) * gx + tx) << 32) | dbits;
-            vals[o] = uint32_t(i);
+    const int64_t j0 = int64_t(blockIdx.x) * blockDim.x;
+    if (j0 >= n) return;   // block-uniform (only the single block of an empty launch)
+    const bool valid = j < n;
+    const uint32_t i = valid ? sorted_idx[j] : 0u;
+    Rect R{0, 0, 0, 0};
+    unsigned long long base = 0;
+    if (valid) {
+        const float2 m = means[i];
+        R = tile_rect(m.x, m.y, radii[i], gx, gy);
+        base = offs[j];
+    }
+    // the block's segment: [first rank's offset, last rank's offset + its count)
+    const int64_t jl = (j0 + int64_t(blockDim.x) < n ? j0 + int64_t(blockDim.x) : n) - 1;
+    const unsigned long long seg0 = offs[j0];
+    const unsigned long long seg1 = offs[jl] + counts[sorted_idx[jl]];
+    const unsigned long long ucap = (unsigned long long)cap;
+    const bool staged = (seg1 - seg0) <= (unsigned long long)kFillStage && seg1 <= ucap;
+    const PairSink sink{keys, vals, staged ? s_key : nullptr, staged ? s_val : nullptr, seg0, ucap};
+
+    const int w = R.tx1 - R.tx0;
+    const int area = w * (R.ty1 - R.ty0);
+    const bool big = area > kBigRect;
+    if (!big) {
+        unsigned long long o = base;
+        for (int32_t ty = R.ty0; ty < R.ty1; ++ty)
+            for (int32_t tx = R.tx0; tx < R.tx1; ++tx, ++o)
+                sink.put(o, uint32_t(int64_t(ty) * gx + tx), i);
+    }
+    unsigned long long todo = __ballot(big);
+    const int lane = threadIdx.x & 63;
+    while (todo) {
+        const int src = __ffsll((long long)todo) - 1;
+        todo &= todo - 1;
+        const int stx0 = __builtin_amdgcn_readlane(R.tx0, src);
+        const int sty0 = __builtin_amdgcn_readlane(R.ty0, src);
+        const int sw = __builtin_amdgcn_readlane(w, src);
+        const int sarea = __builtin_amdgcn_readlane(area, src);
+        const uint32_t si = __builtin_amdgcn_readlane(i, src);
+        const unsigned long long sbase =
+            ((unsigned long long)(uint32_t)__builtin_amdgcn_readlane(uint32_t(base >> 32), src) << 32) |
+            (uint32_t)__builtin_amdgcn_readlane(uint32_t(base), src);
+        for (int k = lane; k < sarea; k += 64) {
+            const int ty = sty0 + k / sw, tx = stx0 + k % sw;
+            sink.put(sbase + k, uint32_t(int64_t(ty) * gx + tx), si);
         }
+    }
+    if (staged) {   // block-uniform
+        __syncthreads();
+        const int len = int(seg1 - seg0);
+        for (int k = threadIdx.x; k < len; k += blockDim.x) {
+            keys[seg0 + k] = s_key[k];
+            vals[seg0 + k] = s_val[k];
+        }
+    }
 }
 
 // ------------------------------------------------------------------------------- radix sort
-// One pass of a stable LSD radix sort on an 8-bit digit, in three steps: per-block digit
-// histograms (digit-major, so one exclusive scan yields every block's output offset per digit),
-// the scan, and a scatter in which each block ranks its keys stably in LDS and writes them out
-// in digit order (contiguous runs, so the global writes coalesce).
+// One pass of a stable LSD radix sort of (u32 key, u32 value) on an 8-bit digit, in three steps:
+// per-block digit histograms (digit-major, so one exclusive scan yields every block's output
+// offset per digit), the scan, and a scatter in which each block ranks its keys stably in LDS and
+// writes them out in digit order (contiguous runs, so the global writes coalesce). The element
+// count is read from device memory (*count).
 
-__global__ __launch_bounds__(kSortThreads) void k_radix_hist(const unsigned long long *keys,
-                                                             const BinHeader *hdr, int shift,
-                                                             uint32_t *hist, int64_t nblk) {
+__global__ __launch_bounds__(kSortThreads) void k_radix_hist(const uint32_t *keys,
+                                                             const unsigned long long *count,
+                                                             int shift, uint32_t *hist,
+                                                             int64_t nblk) {
     __shared__ uint32_t s_h[kRadix];
     const int t = threadIdx.x;
     s_h[t] = 0;
     __syncthreads();
-    const int64_t P = int64_t(hdr->pairs);
+    const int64_t P = int64_t(*count);
     const int64_t base = int64_t(blockIdx.x) * kSortTile;
 #pragma unroll 4
     for (int k = 0; k < kSortItems; ++k) {
@@ -234,16 +379,16 @@ __global__ __launch_bounds__(kSortThreads) void k_radix_hist(const unsigned long
 }
 
 __global__ __launch_bounds__(kSortThreads) void k_radix_scatter(
-    const unsigned long long *kin, const uint32_t *vin, unsigned long long *kout, uint32_t *vout,
-    const BinHeader *hdr, int shift, const uint32_t *hist_off, int64_t nblk) {
+    const uint32_t *kin, const uint32_t *vin, uint32_t *kout, uint32_t *vout,
+    const unsigned long long *count, int shift, const uint32_t *hist_off, int64_t nblk) {
     __shared__ uint32_t s_wcnt[kSortThreads / 64][kRadix];  // per-wave digit counts, then prefixes
     __shared__ uint32_t s_dstart[kRadix];                     // block-local start of each digit
     __shared__ uint32_t s_gofs[kRadix];                       // global start of each digit
     __shared__ uint32_t s_wave[kSortThreads / 64];
-    __shared__ unsigned long long s_key[kSortTile];
+    __shared__ uint32_t s_key[kSortTile];
     __shared__ uint32_t s_val[kSortTile];
 
-    const int64_t P = int64_t(hdr->pairs);
+    const int64_t P = int64_t(*count);
     const int64_t base = int64_t(blockIdx.x) * kSortTile;
     if (base >= P) return;
     const int t = threadIdx.x, lane = t & 63, w = t >> 6;
@@ -255,15 +400,14 @@ __global__ __launch_bounds__(kSortThreads) void k_radix_scatter(
     // Wave w ranks keys [base + 1024 w, base + 1024 (w + 1)) in 16 steps of 64 consecutive keys,
     // so rank order within the wave is index order.
     const unsigned long long lt_mask = (1ull << lane) - 1ull;
-    unsigned long long key[kSortItems];
-    uint32_t val[kSortItems], loc[kSortItems];
+    uint32_t key[kSortItems], val[kSortItems], loc[kSortItems];
 #pragma unroll
     for (int k = 0; k < kSortItems; ++k) {
         const int64_t idx = base + int64_t(w) * (kSortItems * 64) + k * 64 + lane;
         const bool valid = idx < P;
-        key[k] = valid ? kin[idx] : 0ull;
+        key[k] = valid ? kin[idx] : 0u;
         val[k] = valid ? vin[idx] : 0u;
-        const uint32_t d = uint32_t(key[k] >> shift) & (kRadix - 1);
+        const uint32_t d = (key[k] >> shift) & (kRadix - 1);
         // lanes holding the same digit: intersect the ballots of every digit bit
         unsigned long long peers = __ballot(valid);
 #pragma unroll
@@ -294,7 +438,7 @@ __global__ __launch_bounds__(kSortThreads) void k_radix_scatter(
     for (int k = 0; k < kSortItems; ++k) {
         const int64_t idx = base + int64_t(w) * (kSortItems * 64) + k * 64 + lane;
         if (idx < P) {
-            const uint32_t d = uint32_t(key[k] >> shift) & (kRadix - 1);
+            const uint32_t d = (key[k] >> shift) & (kRadix - 1);
             const uint32_t r = s_dstart[d] + s_wcnt[w][d] + loc[k];
             s_key[r] = key[k];
             s_val[r] = val[k];
@@ -303,12 +447,34 @@ __global__ __launch_bounds__(kSortThreads) void k_radix_scatter(
     __syncthreads();
     const int64_t nvalid = (P - base) < kSortTile ? (P - base) : kSortTile;
     for (int64_t j = t; j < nvalid; j += kSortThreads) {
-        const unsigned long long k = s_key[j];
-        const uint32_t d = uint32_t(k >> shift) & (kRadix - 1);
+        const uint32_t k = s_key[j];
+        const uint32_t d = (k >> shift) & (kRadix - 1);
         const int64_t pos = int64_t(s_gofs[d]) + (j - int64_t(s_dstart[d]));
         kout[pos] = k;
         vout[pos] = s_val[j];
     }
+}
+
+// Sorts up to cap elements (count on the device) on key bits [0, bits). The data starts in
+// (ka, va) and ends in (ka, va) after an even number of passes, in (kb, vb) after an odd one;
+// returns the number of passes.
+int radix_sort(uint32_t *ka, uint32_t *kb, uint32_t *va, uint32_t *vb,
+               const unsigned long long *count, int64_t cap, int bits, uint32_t *hist,
+               uint32_t *partial, hipStream_t s) {
+    const int64_t nblk = (cap + kSortTile - 1) / kSortTile;
+    const int passes = (bits + kRadixBits - 1) / kRadixBits;
+    if (nblk == 0) return passes;
+    uint32_t *kin = ka, *kout = kb, *vin = va, *vout = vb;
+    for (int p = 0; p < passes; ++p) {
+        const int shift = p * kRadixBits;
+        k_radix_hist<<<dim3(unsigned(nblk)), kSortThreads, 0, s>>>(kin, count, shift, hist, nblk);
+        launch_scan<uint32_t>(hist, int64_t(kRadix) * nblk, partial, nullptr, nullptr, s);
+        k_radix_scatter<<<dim3(unsigned(nblk)), kSortThreads, 0, s>>>(kin, vin, kout, vout, count,
+                                                                      shift, hist, nblk);
+        std::swap(kin, kout);
+        std::swap(vin, vout);
+    }
+    return passes;
 }
 
 __global__ __launch_bounds__(256) void k_fill_u32(uint32_t *p, int64_t m, uint32_t v) {
@@ -316,14 +482,14 @@ __global__ __launch_bounds__(256) void k_fill_u32(uint32_t *p, int64_t m, uint32
     if (i < m) p[i] = v;
 }
 
-__global__ __launch_bounds__(256) void k_ranges(const unsigned long long *keys,
-                                                const BinHeader *hdr, uint32_t *ranges) {
+__global__ __launch_bounds__(256) void k_ranges(const uint32_t *tiles, const BinHeader *hdr,
+                                                uint32_t *ranges) {
     const int64_t P = int64_t(hdr->pairs);
     const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
     if (i >= P) return;
-    const uint32_t t = uint32_t(keys[i] >> 32);
-    if (i == 0 || uint32_t(keys[i - 1] >> 32) != t) ranges[2 * int64_t(t)] = uint32_t(i);
-    if (i == P - 1 || uint32_t(keys[i + 1] >> 32) != t) ranges[2 * int64_t(t) + 1] = uint32_t(i + 1);
+    const uint32_t t = tiles[i];
+    if (i == 0 || tiles[i - 1] != t) ranges[2 * int64_t(t)] = uint32_t(i);
+    if (i == P - 1 || tiles[i + 1] != t) ranges[2 * int64_t(t) + 1] = uint32_t(i + 1);
 }
 
 int ceil_log2(int64_t v) {
@@ -335,6 +501,7 @@ int ceil_log2(int64_t v) {
 }  // namespace
 
 size_t bin_workspace_bytes(int64_t n, int64_t pair_capacity, int64_t /*n_tiles*/) {
+    // bin_count uses the leading part, which does not depend on the capacity; bin_fill all of it
     return layout(n, pair_capacity).end;
 }
 
@@ -345,14 +512,15 @@ gsb_status bin_count(const float *means2d, const int32_t *radii, int64_t n, int3
                      void *ws, int64_t *n_pairs_dev, hipStream_t s) {
     const Layout L = layout(n, 0);
     auto *hdr = at<BinHeader>(ws, L.hdr);
-    auto *offsets = at<unsigned long long>(ws, L.offsets);
+    auto *counts = at<unsigned long long>(ws, L.counts);
     auto *partial = at<unsigned long long>(ws, L.partials);
     const int32_t gx = int32_t(grid_x(W)), gy = int32_t(grid_y(H));
     if (n > 0)
         k_bin_count<<<dim3(unsigned((n + 255) / 256)), 256, 0, s>>>(
-            reinterpret_cast<const float2 *>(means2d), radii, n, gx, gy, offsets);
-    launch_scan<unsigned long long>(offsets, n, partial, &hdr->total,
-                                    reinterpret_cast<long long *>(n_pairs_dev), s);
+            reinterpret_cast<const float2 *>(means2d), radii, n, gx, gy, counts);
+    // the total only: offsets are formed in depth order by bin_fill
+    launch_scan<unsigned long long>(counts, n, partial, &hdr->total,
+                                    reinterpret_cast<long long *>(n_pairs_dev), s, false);
     return check_launch("bin_count");
 }
 
@@ -361,39 +529,39 @@ gsb_status bin_fill(const float *means2d, const int32_t *radii, const float *dep
                     uint32_t *ranges, int32_t *status_dev, hipStream_t s) {
     const Layout L = layout(n, cap);
     auto *hdr = at<BinHeader>(ws, L.hdr);
-    auto *offsets = at<unsigned long long>(ws, L.offsets);
-    auto *keys_a = at<unsigned long long>(ws, L.keys_a);
-    auto *keys_b = at<unsigned long long>(ws, L.keys_b);
-    auto *vals_tmp = at<uint32_t>(ws, L.vals_tmp);
+    auto *counts = at<unsigned long long>(ws, L.counts);
+    auto *partial64 = at<unsigned long long>(ws, L.partials);
+    auto *partial32 = at<uint32_t>(ws, L.partials);
     auto *hist = at<uint32_t>(ws, L.hist);
-    auto *partial = at<uint32_t>(ws, L.partials);
+    uint32_t *dka = at<uint32_t>(ws, L.dkey_a), *dkb = at<uint32_t>(ws, L.dkey_b);
+    uint32_t *dva = at<uint32_t>(ws, L.dval_a), *dvb = at<uint32_t>(ws, L.dval_b);
+    auto *offs = at<unsigned long long>(ws, L.offs);
+    uint32_t *tka = at<uint32_t>(ws, L.tkey_a), *tkb = at<uint32_t>(ws, L.tkey_b);
+    uint32_t *vtmp = at<uint32_t>(ws, L.vals_tmp);
     const int32_t gx = int32_t(grid_x(W)), gy = int32_t(grid_y(H));
     const int64_t n_tiles = int64_t(gx) * gy;
-    const int key_bits = 32 + (ceil_log2(n_tiles) > 0 ? ceil_log2(n_tiles) : 1);
-    const int passes = (key_bits + kRadixBits - 1) / kRadixBits;
-    // the last pass must land the values in point_list
-    uint32_t *v_first = (passes % 2 == 0) ? point_list : vals_tmp;
-    uint32_t *v_second = (passes % 2 == 0) ? vals_tmp : point_list;
+    const unsigned gn = unsigned(n > 0 ? (n + 255) / 256 : 1);
 
     k_fill_u32<<<dim3(unsigned((2 * n_tiles + 255) / 256)), 256, 0, s>>>(ranges, 2 * n_tiles, 0u);
-    k_bin_fill<<<dim3(unsigned(n > 0 ? (n + 255) / 256 : 1)), 256, 0, s>>>(
-        reinterpret_cast<const float2 *>(means2d), radii, depths, n, gx, gy, offsets, hdr, cap,
-        keys_a, v_first, status_dev);
-    const int64_t nblk = (cap + kSortTile - 1) / kSortTile;
-    if (nblk > 0) {
-        unsigned long long *kin = keys_a, *kout = keys_b;
-        uint32_t *vin = v_first, *vout = v_second;
-        for (int p = 0; p < passes; ++p) {
-            const int shift = p * kRadixBits;
-            k_radix_hist<<<dim3(unsigned(nblk)), kSortThreads, 0, s>>>(kin, hdr, shift, hist, nblk);
-            launch_scan<uint32_t>(hist, int64_t(kRadix) * nblk, partial, nullptr, nullptr, s);
-            k_radix_scatter<<<dim3(unsigned(nblk)), kSortThreads, 0, s>>>(kin, vin, kout, vout, hdr,
-                                                                          shift, hist, nblk);
-            std::swap(kin, kout);
-            std::swap(vin, vout);
-        }
-        k_ranges<<<dim3(unsigned((cap + 255) / 256)), 256, 0, s>>>(kin, hdr, ranges);
-    }
+    // 1. Gaussians by depth (ties by index: the sort is stable over index order)
+    k_depth_keys<<<gn, 256, 0, s>>>(depths, n, dka, dva, hdr);
+    const int dp = radix_sort(dka, dkb, dva, dvb, &hdr->gaussians, n, 32, hist, partial32, s);
+    const uint32_t *sorted_idx = (dp % 2 == 0) ? dva : dvb;
+    // 2. offsets in rank order; pairs emitted in rank order
+    if (n > 0) k_rank_counts<<<gn, 256, 0, s>>>(sorted_idx, counts, n, offs);
+    launch_scan<unsigned long long>(offs, n, partial64, nullptr, nullptr, s);
+    const int tile_bits = ceil_log2(n_tiles) > 0 ? ceil_log2(n_tiles) : 1;
+    const int tp = (tile_bits + kRadixBits - 1) / kRadixBits;
+    // the last pass must land the values in point_list
+    uint32_t *v_first = (tp % 2 == 0) ? point_list : vtmp;
+    uint32_t *v_second = (tp % 2 == 0) ? vtmp : point_list;
+    k_bin_fill<<<gn, 256, 0, s>>>(reinterpret_cast<const float2 *>(means2d), radii, sorted_idx, n,
+                                  gx, gy, offs, counts, hdr, cap, tka, v_first, status_dev);
+    // 3. stable sort of the pairs on the tile id
+    radix_sort(tka, tkb, v_first, v_second, &hdr->pairs, cap, tile_bits, hist, partial32, s);
+    const uint32_t *tiles_sorted = (tp % 2 == 0) ? tka : tkb;
+    if (cap > 0)
+        k_ranges<<<dim3(unsigned((cap + 255) / 256)), 256, 0, s>>>(tiles_sorted, hdr, ranges);
     return check_launch("bin_fill");
 }
 

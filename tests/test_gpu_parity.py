@@ -38,6 +38,11 @@ def scenes():
         "ragged": ragged_scene(),
         "ties": gsinputs.make_scene("C1", seed=42, n=3000, width=96, height=80, depth_levels=4),
         "lognormal": gsinputs.make_scene("C2", seed=43, n=12000, width=200, height=120),
+        # large footprints: ~150 tiles per Gaussian, so a block's output segment exceeds what
+        # the fill kernel stages in LDS and most rectangles are emitted wavefront-cooperatively
+        "bigrects": gsinputs.make_scene(
+            gsinputs.SceneConfig("bigrects", 1024, 1024, 3000, "loguniform", 8.0, 64.0,
+                                 "uniform", 44)),
     }
 
 
