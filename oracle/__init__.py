@@ -43,6 +43,8 @@ def _load():
         lib.orc_bin_count.restype = i64
         lib.orc_bin.argtypes = [P, P, P, i64, i32, i32, i64, P, P]
         lib.orc_bin.restype = i64
+        lib.orc_bin_tile.argtypes = [P, P, P, i64, i32, i32, i64, i64, P]
+        lib.orc_bin_tile.restype = i64
         lib.orc_forward.argtypes = [i32, i32, P, P, P, P, P, P, P, P, P, P, P, P, P]
         lib.orc_forward.restype = None
         lib.orc_backward.argtypes = [i32, i32, P, P, P, P, P, P, P, i64, P, P, P, P, P]
@@ -86,6 +88,33 @@ def bin_tiles(means2d, radii, depths, W: int, H: int) -> tuple[np.ndarray, np.nd
     got = lib.orc_bin(_ptr(m), _ptr(r), _ptr(d), n, W, H, total, _ptr(point_list), _ptr(ranges))
     assert got == total
     return point_list[:total], ranges
+
+
+def bin_tile(means2d, radii, depths, W: int, H: int, t: int) -> np.ndarray:
+    """Sorted list (u32) of tile t alone."""
+    lib = _load()
+    m, d = _f64(means2d), _f64(depths)
+    r = np.ascontiguousarray(radii, dtype=np.int32)
+    n = r.shape[0]
+    k = lib.orc_bin_tile(_ptr(m), _ptr(r), _ptr(d), n, W, H, t, 0, None)
+    out = np.zeros(max(k, 1), np.uint32)
+    lib.orc_bin_tile(_ptr(m), _ptr(r), _ptr(d), n, W, H, t, k, _ptr(out))
+    return out[:k]
+
+
+def sampled_bins(means2d, radii, depths, W: int, H: int, tiles) -> tuple[np.ndarray, np.ndarray]:
+    """(point_list, ranges) in which only the given tiles hold their lists (every other tile is
+    empty): the binning of a frame restricted to a sample of its tiles."""
+    gx, gy = grid(W, H)
+    ranges = np.zeros((gx * gy, 2), np.uint32)
+    lists, pos = [], 0
+    for t in sorted(int(t) for t in tiles):
+        lst = bin_tile(means2d, radii, depths, W, H, t)
+        ranges[t] = (pos, pos + len(lst)) if len(lst) else (0, 0)
+        lists.append(lst)
+        pos += len(lst)
+    pl = np.concatenate(lists) if lists else np.zeros(0, np.uint32)
+    return pl.astype(np.uint32), ranges
 
 
 def forward(W: int, H: int, ranges, point_list, means2d, conics, opacity, colors,

@@ -137,6 +137,35 @@ int64_t orc_bin(const double *means2d, const int32_t *radii, const double *depth
     return total;
 }
 
+/* The sorted list of one tile alone: every Gaussian whose rectangle covers tile t, ordered by
+ * (depth, index). Writes up to cap indices; returns the full count. (Used to check single tiles of
+ * frames too large to bin whole on the CPU.) */
+int64_t orc_bin_tile(const double *means2d, const int32_t *radii, const double *depths, int64_t n,
+                     int32_t W, int32_t H, int64_t t, int64_t cap, uint32_t *out) {
+    int64_t gx = (W + ORC_TILE - 1) / ORC_TILE, gy = (H + ORC_TILE - 1) / ORC_TILE;
+    const int64_t tx = t % gx, ty = t / gx;
+    int64_t k = 0;
+    orc_pair *pairs = (orc_pair *)malloc(sizeof(orc_pair) * 1024);
+    int64_t room = 1024;
+    for (int64_t i = 0; i < n; ++i) {
+        int64_t tx0, tx1, ty0, ty1;
+        tile_rect(means2d[2 * i], means2d[2 * i + 1], radii[i], gx, gy, &tx0, &tx1, &ty0, &ty1);
+        if (tx < tx0 || tx >= tx1 || ty < ty0 || ty >= ty1) continue;
+        if (k == room) {
+            room *= 2;
+            pairs = (orc_pair *)realloc(pairs, sizeof(orc_pair) * (size_t)room);
+        }
+        pairs[k].tile = t;
+        pairs[k].depth = depths[i];
+        pairs[k].idx = i;
+        ++k;
+    }
+    qsort(pairs, (size_t)k, sizeof(orc_pair), pair_less);
+    for (int64_t p = 0; p < k && p < cap; ++p) out[p] = (uint32_t)pairs[p].idx;
+    free(pairs);
+    return k;
+}
+
 /* Exponent of Eq. (power): -1/2 A dx^2 - B dx dy - 1/2 C dy^2, dx = x_g - x_p, dy = y_g - y_p. */
 static double gauss_power(const double *conic, double dx, double dy) {
     return -0.5 * (conic[0] * dx * dx + conic[2] * dy * dy) - conic[1] * dx * dy;

@@ -423,3 +423,17 @@ def test_work_counters():
     assert f0["n_contrib"].sum() == 0
     c = oracle.work_counts(f, f["ranges"])
     assert c["K"] == int(f["n_contrib"].sum()) and c["Eb"] == int(f["last_contrib"].sum())
+
+
+def test_bin_tile_matches_bruteforce():
+    s = small_scene(14, depth_levels=3)
+    W, H = s["width"], s["height"]
+    gx, gy = oracle.grid(W, H)
+    m = s["means2d"].astype(float)
+    for t in range(gx * gy):
+        want = sorted((float(s["depths"][i]), i) for i in range(len(s["radii"]))
+                      if (t % gx, t // gx) in bf_covered(m[i, 0], m[i, 1], int(s["radii"][i]), W, H))
+        got = oracle.bin_tile(s["means2d"], s["radii"], s["depths"], W, H, t)
+        assert got.tolist() == [i for _, i in want]
+    pl, rg = oracle.sampled_bins(s["means2d"], s["radii"], s["depths"], W, H, [0, 3, 5])
+    assert np.count_nonzero(rg[:, 1] - rg[:, 0]) <= 3
