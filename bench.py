@@ -265,7 +265,7 @@ def cpu_baseline_and_accuracy(fr: Frame, gpu_results: dict) -> tuple[dict, dict]
         img, T, last, grads = out
         a = {"psnr_db": round(psnr(img, ref["image"]), 2),
              "max_abs_per_channel": [float(np.abs(img[c] - ref["image"][c]).max()) for c in range(3)]}
-        ok = ref["margin"] > 1e-5
+        ok = ref["margin"] > 1e-4      # the parity tests' decision margin
         a["max_abs_nonmarginal"] = float(np.abs(img - ref["image"])[:, ok].max())
         a["last_contrib_mismatch_nonmarginal"] = int((last != ref["last_contrib"])[ok].sum())
         for k, g in zip(("dmeans2d", "dconics", "dopacity", "dcolors"), grads):
@@ -278,8 +278,8 @@ def cpu_baseline_and_accuracy(fr: Frame, gpu_results: dict) -> tuple[dict, dict]
 def main():
     args = parse()
     if args.gpus != 1:
-        print("bench.py measures one GPU: this build has no multi-GPU path (the sharding design "
-              "is described in DESIGN.md); run with --gpus 1.", file=sys.stderr)
+        print("bench.py measures one GPU: the library has no multi-GPU path; run with --gpus 1.",
+              file=sys.stderr)
         sys.exit(2)
     dev = torch.device("cuda:0")
     if args.calib_copy_mib:

@@ -5,7 +5,7 @@
 //          multiplication) on the matrix cores (MFMA), FP16 or BF16 operands, FP32 accumulation.
 //
 // Launch shape: one 256-thread block (4 wavefronts) per 16x16 tile, one pixel per lane; wave w
-// owns tile rows 4w..4w+3. The tile's sorted list is walked in batches of 256 Gaussians: every
+// owns the 8x8 quadrant (w mod 2, w div 2) of the tile. The tile's sorted list is walked in batches of 256 Gaussians: every
 // thread stages one Gaussian into LDS (double-buffered; the next batch's global loads are issued
 // before the current batch is composited), then each wave composites the batch for its pixels.
 //
@@ -216,7 +216,10 @@ struct Lane {
 __device__ inline Lane lane_setup(int64_t tile, int gx, int W, int H) {
     Lane L;
     L.t = threadIdx.x; L.w = L.t >> 6; L.l = L.t & 63;
-    L.col = L.l & 15; L.row = 4 * L.w + (L.l >> 4);
+    // wave w owns the 8x8 quadrant (w & 1, w >> 1) of the tile: compact footprints touch fewer
+    // waves than with 4-row strips, so fewer (Gaussian, wave) pairs have work
+    L.col = 8 * (L.w & 1) + (L.l & 7);
+    L.row = 8 * (L.w >> 1) + (L.l >> 3);
     const int x0 = int(tile % gx) * kTile, y0 = int(tile / gx) * kTile;
     L.px = float(x0 + L.col); L.py = float(y0 + L.row);
     L.inside = (x0 + L.col < W) && (y0 + L.row < H);
@@ -384,9 +387,12 @@ struct BwdState {
 // over each row of 16 lanes and the row totals are added into the Gaussian's LDS accumulator
 // (`acc`), which the block flushes to global memory once per batch. Raw sums: S_xx, S_xy, S_yy,
 // S_x, S_y (times dL/dpower), dL/do, and the three colour gradients.
+// kRanged = false: the caller has checked that the whole group lies before every lane's last
+// contributor, so the skip test alone decides (one compare, whose mask is the ballot).
+template <bool kRanged>
 __device__ inline void reverse_pair(float q, bool in_range, const float4 *attr_p,
                                     const float4 *bw_p, const Lane &L, BwdState &st, float *acc) {
-    const bool alive = in_range && (q >= kQCull);
+    const bool alive = kRanged ? (in_range && q >= kQCull) : (q >= kQCull);
     const unsigned long long live = __builtin_amdgcn_ballot_w64(alive);
     if (live == 0ull) return;
     float s[kGrad] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
@@ -406,11 +412,11 @@ __device__ inline void reverse_pair(float q, bool in_range, const float4 *attr_p
         const bool clamp_p = q > attr.x;   // power > 0
         if (!clamp_a) {
             const float4 bw = *bw_p;
-            s[5] = a * bw.z * dLda;        // d alpha / d o = alpha / o
+            const float da = a * dLda;     // dL/dpower (d alpha / d power = alpha)
+            s[5] = da * bw.z;              // dL/do = alpha / o * dL/dalpha
             if (!clamp_p) {
-                const float dP = a * dLda;  // d alpha / d power = alpha
                 const float dx = bw.x - L.px, dy = bw.y - L.py;
-                const float tx = dP * dx, ty = dP * dy;
+                const float tx = da * dx, ty = da * dy;
                 s[0] = tx * dx; s[1] = tx * dy; s[2] = ty * dy;
                 s[3] = tx; s[4] = ty;
             }
@@ -493,17 +499,32 @@ __device__ inline void bwd_tile(const ViewDesc &v, int64_t tile, Stage<M, NB> &S
             const float4 *bw = &SB.bwd[buf][g * kGroup];
             float *acc = &s_acc[g * kGroup][0];
             const int rel = st.last - (base + g * kGroup);   // positions < last are in range
+            // the whole group is in range for every lane (the common case once past the lanes'
+            // last contributors; never for a partial tile, whose outside lanes have last = 0)
+            const bool whole = __builtin_amdgcn_ballot_w64(rel < kGroup) == 0ull;
             if constexpr (M == Mode::Plain) {
+                if (whole) {
 #pragma unroll
-                for (int u = kGroup - 1; u >= 0; --u) {
-                    const float q = plain_q(S, buf, g * kGroup + u, L);
-                    reverse_pair(q, u < rel, attr + u, bw + u, L, st, acc + u * kGrad);
+                    for (int u = kGroup - 1; u >= 0; --u)
+                        reverse_pair<false>(plain_q(S, buf, g * kGroup + u, L), true, attr + u,
+                                            bw + u, L, st, acc + u * kGrad);
+                } else {
+#pragma unroll
+                    for (int u = kGroup - 1; u >= 0; --u)
+                        reverse_pair<true>(plain_q(S, buf, g * kGroup + u, L), u < rel, attr + u,
+                                           bw + u, L, st, acc + u * kGrad);
                 }
             } else {
                 const f16x q = group_q_mfma<M, NB>(S, buf, g, L, bhi, blo);
+                if (whole) {
 #pragma unroll
-                for (int u = kGroup - 1; u >= 0; --u)
-                    reverse_pair(q[u], u < rel, attr + u, bw + u, L, st, acc + u * kGrad);
+                    for (int u = kGroup - 1; u >= 0; --u)
+                        reverse_pair<false>(q[u], true, attr + u, bw + u, L, st, acc + u * kGrad);
+                } else {
+#pragma unroll
+                    for (int u = kGroup - 1; u >= 0; --u)
+                        reverse_pair<true>(q[u], u < rel, attr + u, bw + u, L, st, acc + u * kGrad);
+                }
             }
         }
         // flush: thread t owns staged Gaussian t's sums (a Gaussian with no live pair in this

@@ -13,7 +13,8 @@ import torch
 
 import gsinputs
 import oracle
-from gpu_util import (GEMM_GRAD, PLAIN_GRAD, check_gemm, check_plain, gpu_forward, normwise,
+from gpu_util import (GEMM_GRAD, GEMM_PSNR, MARGIN, PLAIN_ABS, PLAIN_GRAD, check_gemm, check_plain,
+                      gpu_forward, normwise,
                       say, upload, upload_bins)
 from paper_2604_02120_amd import api
 from paper_2604_02120_amd.autograd import blend
@@ -239,3 +240,68 @@ def test_backward_c3_full_size(gpu):
             e = normwise(got[k], ref[k])
             say(f"  {k}: {e:.3e}")
             assert e <= bound, (k, e)
+
+
+# ----------------------------------------------------------------------------- 4K, sampled tiles
+def c5_sample_tiles(gx, gy, k=40, seed=5):
+    rng = np.random.default_rng(seed)
+    corners = [0, gx - 1, (gy - 1) * gx, gx * gy - 1]
+    return sorted(set(corners) | set(rng.choice(gx * gy, size=k, replace=False).tolist()))
+
+
+def test_c5_4k_sampled_tiles(gpu):
+    """The largest workload (3840x2160, 3M Gaussians) at full size in the benchmark's launch
+    configuration: GPU binning of the whole frame, checked bit-exactly against the oracle's lists of
+    a sample of tiles (each built on its own from every Gaussian); the whole-frame forward of every
+    precision checked on those tiles' pixels; the backward run on the sampled tiles' lists only
+    (every other tile empty) against the oracle's gradients of that same restricted frame."""
+    s = gsinputs.make_scene("C5")
+    W, H = s["width"], s["height"]
+    gx, gy = oracle.grid(W, H)
+    tiles = c5_sample_tiles(gx, gy)
+    say(f"[c5] 3840x2160 n=3e6, {len(tiles)} sampled tiles: oracle")
+    pl_ref, rg_ref = oracle.sampled_bins(s["means2d"], s["radii"], s["depths"], W, H, tiles)
+    sd = upload(s, gpu)
+    pl, rg = api.bin_tiles(sd["means2d"], sd["radii"], sd["depths"], W, H)
+    pl, rg = pl.cpu().numpy().astype(np.uint32), rg.cpu().numpy().astype(np.uint32)
+    for t in tiles:
+        a, b = rg[t]
+        np.testing.assert_array_equal(pl[a:b], pl_ref[rg_ref[t, 0]:rg_ref[t, 1]], err_msg=str(t))
+    mask = np.zeros((H, W), bool)
+    for t in tiles:
+        tx, ty = t % gx, t // gx
+        mask[16 * ty:16 * ty + 16, 16 * tx:16 * tx + 16] = True
+    ref = oracle.forward(W, H, rg_ref, pl_ref, s["means2d"], s["conics"], s["opacity"], s["colors"])
+    pl_t = torch.from_numpy(pl.astype(np.int32)).to(gpu)
+    rg_t = torch.from_numpy(rg.astype(np.int32)).to(gpu)
+    for prec in PRECS:
+        img, T, last = gpu_forward(sd, pl_t, rg_t, prec)
+        d_img = np.abs(img - ref["image"])[:, mask]
+        if prec == "fp32":
+            ok = mask & (ref["margin"] > MARGIN)
+            assert 1.0 - ok.sum() / mask.sum() < 0.01
+            mism = int((last != ref["last_contrib"])[ok].sum())
+            e_img = np.abs(img - ref["image"])[:, ok].max()
+            e_T = np.abs(T - ref["final_T"])[ok].max()
+            say(f"  fp32: max|d image| {e_img:.3e} max|d T| {e_T:.3e} last mismatches {mism}")
+            assert mism == 0 and e_img <= PLAIN_ABS and e_T <= PLAIN_ABS
+        else:
+            p = 10.0 * np.log10(1.0 / max(float(np.mean(d_img ** 2)), 1e-300))
+            say(f"  {prec}: psnr on sampled tiles {p:.1f} dB")
+            assert p >= GEMM_PSNR
+    g = gsinputs.make_dloss(W, H, 1005)
+    gref = oracle.backward(W, H, rg_ref, pl_ref, s["means2d"], s["conics"], s["opacity"],
+                           s["colors"], g)
+    pl_s, rg_s = upload_bins(pl_ref, rg_ref, gpu)
+    gd = torch.from_numpy(g).to(gpu)
+    for prec in PRECS:
+        img, T, last = api.blend_forward(sd["means2d"], sd["conics"], sd["opacity"], sd["colors"],
+                                         rg_s, pl_s, W, H, (0.0, 0.0, 0.0), prec)
+        out = api.blend_backward(sd["means2d"], sd["conics"], sd["opacity"], sd["colors"], rg_s,
+                                 pl_s, W, H, T, last, gd, (0.0, 0.0, 0.0), prec)
+        torch.cuda.synchronize()
+        bound = PLAIN_GRAD if prec == "fp32" else GEMM_GRAD
+        for k, v in zip(["dmeans2d", "dconics", "dopacity", "dcolors"], out):
+            e = normwise(v.cpu().numpy().astype(np.float64), gref[k])
+            say(f"  bwd {prec} {k}: {e:.3e}")
+            assert e <= bound, (prec, k, e)
