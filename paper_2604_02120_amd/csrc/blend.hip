@@ -118,6 +118,19 @@ struct StageBwd {
     float4 bwd[2][NB];         // (x, y, 1/o, index bits)
 };
 
+constexpr int kGrad = 9;   // per-Gaussian sums kept per batch
+constexpr int kRows = 4;   // 16-lane rows of a wavefront
+
+// Per-Gaussian gradient sums of the current batch. Each 16-lane row of a wavefront adds into its
+// own copy, and the copies sit one LDS bank apart, so the four row leaders of one LDS add never
+// hit the same address or bank; the flush sums the copies.
+template <int NB>
+struct BwdAcc {
+    static constexpr int kStride = NB * kGrad + 1;
+    float v[kRows * kStride];
+    __device__ float *row(int r) { return v + r * kStride; }
+};
+
 // Raw attributes of one list entry, fetched in the prefetch step.
 struct GRaw {
     float x, y, A, B, C, o, r, g, b;
@@ -278,19 +291,42 @@ struct FwdState {
     int last;
 };
 
-__device__ inline void composite(float q, const float4 *attr, int idx, int pos, FwdState &st) {
-    if (q >= st.thr) {
-        const float4 at = attr[idx];
-        const float a = fminf(__builtin_amdgcn_exp2f(fminf(q, at.x)), kAlphaMax);
-        const float Tn = st.T * (1.0f - a);
-        if (Tn < kTStop) {
-            st.thr = INFINITY;
-        } else {
-            const float wgt = a * st.T;
-            st.r += wgt * at.y; st.g += wgt * at.z; st.b += wgt * at.w;
-            st.T = Tn;
-            st.last = pos + 1;
-        }
+// Per-Gaussian values of a group of 16 are read from LDS once per group, one Gaussian per lane
+// (lane l holds Gaussian l % 16); a Gaussian's value is then broadcast from its lane to a scalar
+// register. This keeps LDS reads out of the per-Gaussian dependency chain.
+__device__ inline float from_lane(float v, int u) {
+    return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), u));
+}
+
+// One front-to-back step (Alg. 1 / Alg. 2 inner loop) for this lane's pixel, without branches:
+// a skipped pair or a finished pixel leaves the state unchanged.
+__device__ inline void composite(float q, float lo2o, float cr, float cg, float cb, int pos,
+                                 FwdState &st) {
+    const bool hit = q >= st.thr;
+    const float a = fminf(__builtin_amdgcn_exp2f(fminf(q, lo2o)), kAlphaMax);
+    const float Tn = st.T * (1.0f - a);
+    const bool stop = Tn < kTStop;
+    const bool blend = hit && !stop;
+    const float wgt = blend ? a * st.T : 0.f;
+    st.r = fmaf(wgt, cr, st.r);
+    st.g = fmaf(wgt, cg, st.g);
+    st.b = fmaf(wgt, cb, st.b);
+    st.T = blend ? Tn : st.T;
+    st.last = blend ? pos + 1 : st.last;
+    st.thr = (hit && stop) ? INFINITY : st.thr;
+}
+
+// Composites the 16 Gaussians of one group; q(u) gives Gaussian u's exponent for this lane.
+template <typename QFn>
+__device__ inline void composite_group(const float4 *attr, int base, const Lane &L, FwdState &st,
+                                       QFn q_of) {
+    const float4 ga = attr[L.l & (kGroup - 1)];   // (log2 o, r, g, b) of Gaussian l % 16
+#pragma unroll
+    for (int u = 0; u < kGroup; ++u) {
+        const float q = q_of(u);
+        if (__builtin_amdgcn_ballot_w64(q >= st.thr) == 0ull) continue;   // no lane takes it
+        composite(q, from_lane(ga.x, u), from_lane(ga.y, u), from_lane(ga.z, u),
+                  from_lane(ga.w, u), base + u, st);
     }
 }
 
@@ -334,17 +370,13 @@ __device__ inline void fwd_tile(const ViewDesc &v, int64_t tile, Stage<M, NB> &S
                            ? int((len - base + kGroup - 1) / kGroup) : kGroups;
         for (int g = 0; g < ng; ++g) {
             if (__ballot(st.thr != INFINITY) == 0) break;
+            const float4 *attr = &S.attr[buf][g * kGroup];
             if constexpr (M == Mode::Plain) {
-#pragma unroll
-                for (int u = 0; u < kGroup; ++u) {
-                    const int idx = g * kGroup + u;
-                    composite(plain_q(S, buf, idx, L), S.attr[buf], idx, base + idx, st);
-                }
+                composite_group(attr, base + g * kGroup, L, st,
+                                [&](int u) { return plain_q(S, buf, g * kGroup + u, L); });
             } else {
                 const f16x q = group_q_mfma<M, NB>(S, buf, g, L, bhi, blo);
-#pragma unroll
-                for (int u = 0; u < kGroup; ++u)
-                    composite(q[u], S.attr[buf], g * kGroup + u, base + g * kGroup + u, st);
+                composite_group(attr, base + g * kGroup, L, st, [&](int u) { return q[u]; });
             }
         }
     }
@@ -360,22 +392,37 @@ __device__ inline void fwd_tile(const ViewDesc &v, int64_t tile, Stage<M, NB> &S
 }
 
 // ------------------------------------------------------------------------------- backward
-// Sum over each row of 16 lanes with DPP row shifts; lane 15 of every row (lanes 15, 31, 47, 63)
-// ends up holding its row's total. Call with every lane active.
+// One step of a sum over each row of 16 lanes with DPP row shifts (after row_shr 1, 2, 4 and 8,
+// lane 15 of every row, i.e. lanes 15, 31, 47, 63, holds its row's total). Every lane active.
 template <int Ctrl>
 __device__ inline float dpp_add(float x) {
-    const int y = __builtin_amdgcn_update_dpp(0, __float_as_int(x), Ctrl, 0xf, 0xf, false);
+    // bound_ctrl: lanes shifted in from outside the row read 0 (no `old` operand to set up)
+    const int y = __builtin_amdgcn_update_dpp(0, __float_as_int(x), Ctrl, 0xf, 0xf, true);
     return x + __int_as_float(y);
 }
-__device__ inline float row_sum16(float x) {
-    x = dpp_add<0x111>(x);  // row_shr:1
-    x = dpp_add<0x112>(x);  // row_shr:2
-    x = dpp_add<0x114>(x);  // row_shr:4
-    x = dpp_add<0x118>(x);  // row_shr:8
-    return x;
+
+// Materialise the 9 values in registers at this point: stops the compiler from folding a product
+// into the first shift-and-add (which would need an extra move) or from sinking the last one into
+// the leaders' branch (where it could no longer be a single DPP add).
+__device__ inline void pin9(float (&s)[kGrad]) {
+    asm volatile("" : "+v"(s[0]), "+v"(s[1]), "+v"(s[2]), "+v"(s[3]), "+v"(s[4]), "+v"(s[5]),
+                      "+v"(s[6]), "+v"(s[7]), "+v"(s[8]));
 }
 
-constexpr int kGrad = 9;   // per-Gaussian sums kept per batch
+// Sum each of the 9 values over every row of 16 lanes (the total lands in the row's lane 15);
+// the four shift steps are interleaved across the values so no DPP read waits on its producer.
+__device__ inline void row_sum16x9(float (&s)[kGrad]) {
+    pin9(s);
+#pragma unroll
+    for (int k = 0; k < kGrad; ++k) s[k] = dpp_add<0x111>(s[k]);   // row_shr:1
+#pragma unroll
+    for (int k = 0; k < kGrad; ++k) s[k] = dpp_add<0x112>(s[k]);
+#pragma unroll
+    for (int k = 0; k < kGrad; ++k) s[k] = dpp_add<0x114>(s[k]);
+#pragma unroll
+    for (int k = 0; k < kGrad; ++k) s[k] = dpp_add<0x118>(s[k]);   // row_shr:8
+    pin9(s);
+}
 
 struct BwdState {
     float T, Tfin, behind, gr, gg, gb, bgg;
@@ -383,47 +430,44 @@ struct BwdState {
 };
 
 // Reverse step for one (Gaussian, pixel) pair. Nothing but a compare and a scalar branch is
-// spent when no lane of the wave has a live pair. Otherwise the pair's 9 gradient terms are summed
-// over each row of 16 lanes and the row totals are added into the Gaussian's LDS accumulator
-// (`acc`), which the block flushes to global memory once per batch. Raw sums: S_xx, S_xy, S_yy,
-// S_x, S_y (times dL/dpower), dL/do, and the three colour gradients.
+// spent when no lane of the wave has a live pair. Otherwise every lane evaluates the step without
+// branches (a dead lane's terms are forced to zero by selects, and its state is left unchanged),
+// the pair's 9 gradient terms are summed over each row of 16 lanes, and the row totals are added
+// into the Gaussian's LDS accumulator (`acc`), which the block flushes to global memory once per
+// batch. Raw sums: S_xx, S_xy, S_yy, S_x, S_y (times dL/dpower), dL/do, and the three colour
+// gradients.
 // kRanged = false: the caller has checked that the whole group lies before every lane's last
 // contributor, so the skip test alone decides (one compare, whose mask is the ballot).
 template <bool kRanged>
-__device__ inline void reverse_pair(float q, bool in_range, const float4 *attr_p,
-                                    const float4 *bw_p, const Lane &L, BwdState &st, float *acc) {
+__device__ inline void reverse_pair(float q, bool in_range, const float4 &ga, const float4 &gb,
+                                    int u, const Lane &L, BwdState &st, float *acc) {
     const bool alive = kRanged ? (in_range && q >= kQCull) : (q >= kQCull);
     const unsigned long long live = __builtin_amdgcn_ballot_w64(alive);
     if (live == 0ull) return;
-    float s[kGrad] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
-    if (alive) {
-        const float4 attr = *attr_p;
-        const float araw = __builtin_amdgcn_exp2f(fminf(q, attr.x));
-        const float a = fminf(araw, kAlphaMax);
-        const float r = __builtin_amdgcn_rcpf(1.0f - a);
-        const float Tb = st.T * r;                       // T in front of this Gaussian
-        const float gc = st.gr * attr.y + st.gg * attr.z + st.gb * attr.w;
-        const float dLda = Tb * gc - (st.behind + st.Tfin * st.bgg) * r;
-        const float wc = a * Tb;
-        st.behind = fmaf(wc, gc, st.behind);
-        st.T = Tb;
-        s[6] = wc * st.gr; s[7] = wc * st.gg; s[8] = wc * st.gb;
-        const bool clamp_a = araw >= kAlphaMax;
-        const bool clamp_p = q > attr.x;   // power > 0
-        if (!clamp_a) {
-            const float4 bw = *bw_p;
-            const float da = a * dLda;     // dL/dpower (d alpha / d power = alpha)
-            s[5] = da * bw.z;              // dL/do = alpha / o * dL/dalpha
-            if (!clamp_p) {
-                const float dx = bw.x - L.px, dy = bw.y - L.py;
-                const float tx = da * dx, ty = da * dy;
-                s[0] = tx * dx; s[1] = tx * dy; s[2] = ty * dy;
-                s[3] = tx; s[4] = ty;
-            }
-        }
-    }
-#pragma unroll
-    for (int k = 0; k < kGrad; ++k) s[k] = row_sum16(s[k]);
+    const float4 attr = make_float4(from_lane(ga.x, u), from_lane(ga.y, u), from_lane(ga.z, u),
+                                    from_lane(ga.w, u));
+    const float4 bw = make_float4(from_lane(gb.x, u), from_lane(gb.y, u), from_lane(gb.z, u), 0.f);
+    // a dead lane has q < log2(1/255) or is past its last contributor: its alpha is finite and
+    // below 1/255 or belongs to a pair it never blended; either way its terms are selected away
+    const float araw = __builtin_amdgcn_exp2f(fminf(q, attr.x));
+    const float a = fminf(araw, kAlphaMax);
+    const float r = __builtin_amdgcn_rcpf(1.0f - a);
+    const float Tb = st.T * r;                           // T in front of this Gaussian
+    const float gc = st.gr * attr.y + st.gg * attr.z + st.gb * attr.w;
+    const float dLda = Tb * gc - (st.behind + st.Tfin * st.bgg) * r;
+    const float wc = alive ? a * Tb : 0.f;
+    st.behind = fmaf(wc, gc, st.behind);
+    st.T = alive ? Tb : st.T;
+    // dL/dpower = alpha * dL/dalpha unless the 0.99 clamp is active
+    const float da = (alive && araw < kAlphaMax) ? a * dLda : 0.f;
+    // no gradient reaches the geometry through a clamped (positive) power
+    const float dg = q > attr.x ? 0.f : da;
+    const float dx = bw.x - L.px, dy = bw.y - L.py;
+    const float tx = dg * dx, ty = dg * dy;
+    float s[kGrad] = {tx * dx, tx * dy, ty * dy, tx, ty, da * bw.z,   // dL/do = alpha/o * dL/dalpha
+                      wc * st.gr, wc * st.gg, wc * st.gb};
+    row_sum16x9(s);
+    // only rows with a live lane add (each active leader is one more LDS operation)
     const bool row_live = ((live >> (L.l & 48)) & 0xffffull) != 0ull;
     if ((L.l & 15) == 15 && row_live) {
 #pragma unroll
@@ -434,7 +478,7 @@ __device__ inline void reverse_pair(float q, bool in_range, const float4 *attr_p
 // Backward of one tile of one view.
 template <Mode M, int NB>
 __device__ inline void bwd_tile(const ViewDesc &v, int64_t tile, Stage<M, NB> &S, StageBwd<NB> &SB,
-                                float (*s_acc)[kGrad], int &s_maxlast) {
+                                BwdAcc<NB> &s_acc, int &s_maxlast) {
     static_assert(NB % kGroup == 0 && NB <= kBlock, "batch must be whole groups, <= block");
     constexpr int kGroups = NB / kGroup;
     const uint32_t *plist = v.point_list;
@@ -482,7 +526,7 @@ __device__ inline void bwd_tile(const ViewDesc &v, int64_t tile, Stage<M, NB> &S
         if (L.t < NB) {
             stage<M, NB, true>(nxt, buf, L.t, xc, yc, S, &SB);
 #pragma unroll
-            for (int k = 0; k < kGrad; ++k) s_acc[L.t][k] = 0.f;
+            for (int k = 0; k < kRows * kGrad; ++k) s_acc.row(k / kGrad)[L.t * kGrad + k % kGrad] = 0.f;
         }
         __syncthreads();
         if (b > 0) {
@@ -495,9 +539,9 @@ __device__ inline void bwd_tile(const ViewDesc &v, int64_t tile, Stage<M, NB> &S
         for (int g = ng - 1; g >= 0; --g) {
             // nothing to do for this wave unless one of its pixels blended past the group start
             if (__ballot(st.last > base + g * kGroup) == 0) continue;
-            const float4 *attr = &S.attr[buf][g * kGroup];
-            const float4 *bw = &SB.bwd[buf][g * kGroup];
-            float *acc = &s_acc[g * kGroup][0];
+            const float4 ga = S.attr[buf][g * kGroup + (L.l & (kGroup - 1))];
+            const float4 gb = SB.bwd[buf][g * kGroup + (L.l & (kGroup - 1))];
+            float *acc = s_acc.row(L.l >> 4) + g * kGroup * kGrad;   // this lane's row copy
             const int rel = st.last - (base + g * kGroup);   // positions < last are in range
             // the whole group is in range for every lane (the common case once past the lanes'
             // last contributors; never for a partial tile, whose outside lanes have last = 0)
@@ -506,24 +550,24 @@ __device__ inline void bwd_tile(const ViewDesc &v, int64_t tile, Stage<M, NB> &S
                 if (whole) {
 #pragma unroll
                     for (int u = kGroup - 1; u >= 0; --u)
-                        reverse_pair<false>(plain_q(S, buf, g * kGroup + u, L), true, attr + u,
-                                            bw + u, L, st, acc + u * kGrad);
+                        reverse_pair<false>(plain_q(S, buf, g * kGroup + u, L), true, ga, gb, u,
+                                            L, st, acc + u * kGrad);
                 } else {
 #pragma unroll
                     for (int u = kGroup - 1; u >= 0; --u)
-                        reverse_pair<true>(plain_q(S, buf, g * kGroup + u, L), u < rel, attr + u,
-                                           bw + u, L, st, acc + u * kGrad);
+                        reverse_pair<true>(plain_q(S, buf, g * kGroup + u, L), u < rel, ga, gb, u,
+                                           L, st, acc + u * kGrad);
                 }
             } else {
                 const f16x q = group_q_mfma<M, NB>(S, buf, g, L, bhi, blo);
                 if (whole) {
 #pragma unroll
                     for (int u = kGroup - 1; u >= 0; --u)
-                        reverse_pair<false>(q[u], true, attr + u, bw + u, L, st, acc + u * kGrad);
+                        reverse_pair<false>(q[u], true, ga, gb, u, L, st, acc + u * kGrad);
                 } else {
 #pragma unroll
                     for (int u = kGroup - 1; u >= 0; --u)
-                        reverse_pair<true>(q[u], u < rel, attr + u, bw + u, L, st, acc + u * kGrad);
+                        reverse_pair<true>(q[u], u < rel, ga, gb, u, L, st, acc + u * kGrad);
                 }
             }
         }
@@ -535,7 +579,8 @@ __device__ inline void bwd_tile(const ViewDesc &v, int64_t tile, Stage<M, NB> &S
             bool any = false;
 #pragma unroll
             for (int k = 0; k < kGrad; ++k) {
-                a9[k] = s_acc[L.t][k];
+                a9[k] = s_acc.row(0)[L.t * kGrad + k] + s_acc.row(1)[L.t * kGrad + k] +
+                        s_acc.row(2)[L.t * kGrad + k] + s_acc.row(3)[L.t * kGrad + k];
                 any |= a9[k] != 0.f;
             }
             if (any) {
@@ -559,7 +604,7 @@ __device__ inline void bwd_tile(const ViewDesc &v, int64_t tile, Stage<M, NB> &S
 // ------------------------------------------------------------------------------- kernels
 // Single view: block b renders tile xcd_tile(b).
 template <Mode M, int NB>
-__global__ __launch_bounds__(kBlock) void k_blend_fwd(ViewDesc v) {
+__global__ __launch_bounds__(kBlock, M == Mode::Plain ? 8 : 6) void k_blend_fwd(ViewDesc v) {
     __shared__ Stage<M, NB> S;
     const int64_t tile = xcd_tile(blockIdx.x, v.n_tiles);
     if (tile >= v.n_tiles) return;
@@ -570,7 +615,7 @@ template <Mode M, int NB>
 __global__ __launch_bounds__(kBlock) void k_blend_bwd(ViewDesc v) {
     __shared__ Stage<M, NB> S;
     __shared__ StageBwd<NB> SB;
-    __shared__ float s_acc[NB][kGrad];   // per-Gaussian gradient sums of the current batch
+    __shared__ BwdAcc<NB> s_acc;   // per-Gaussian gradient sums of the current batch
     __shared__ int s_maxlast;
     const int64_t tile = xcd_tile(blockIdx.x, v.n_tiles);
     if (tile >= v.n_tiles) return;
@@ -657,7 +702,7 @@ template <Mode M, int NB>
 __global__ __launch_bounds__(kBlock, waves_bwd<M>()) void k_blend_bwd_batched(Queues Q) {
     __shared__ Stage<M, NB> S;
     __shared__ StageBwd<NB> SB;
-    __shared__ float s_acc[NB][kGrad];
+    __shared__ BwdAcc<NB> s_acc;
     __shared__ int s_maxlast;
     __shared__ int s_view;
     __shared__ int64_t s_tile;
@@ -714,7 +759,7 @@ template <Mode M, int NB>
 __global__ __launch_bounds__(kBlock) void k_blend_bwd_grid(Queues Q) {
     __shared__ Stage<M, NB> S;
     __shared__ StageBwd<NB> SB;
-    __shared__ float s_acc[NB][kGrad];
+    __shared__ BwdAcc<NB> s_acc;
     __shared__ int s_maxlast;
     int view;
     int64_t tile;
