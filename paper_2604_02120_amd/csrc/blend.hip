@@ -122,13 +122,16 @@ constexpr int kGrad = 9;   // per-Gaussian sums kept per batch
 constexpr int kRows = 4;   // 16-lane rows of a wavefront
 
 // Per-Gaussian gradient sums of the current batch. Each 16-lane row of a wavefront adds into its
-// own copy, and the copies sit one LDS bank apart, so the four row leaders of one LDS add never
-// hit the same address or bank; the flush sums the copies.
+// own copy of the Gaussian's sums; the four copies of one Gaussian are adjacent, 10 words apart, so
+// the four row leaders of one LDS add hit four different banks, and the flush reads one
+// Gaussian's copies as ten 16-byte words and sums them.
+constexpr int kRowSlot = 10;                  // words per row copy (9 used)
+constexpr int kSlot = kRows * kRowSlot;       // words per Gaussian
 template <int NB>
 struct BwdAcc {
-    static constexpr int kStride = NB * kGrad + 1;
-    float v[kRows * kStride];
-    __device__ float *row(int r) { return v + r * kStride; }
+    float4 v[NB * kSlot / 4];
+    __device__ float *slot(int t) { return reinterpret_cast<float *>(v) + t * kSlot; }
+    __device__ float4 *slot4(int t) { return v + t * (kSlot / 4); }
 };
 
 // Raw attributes of one list entry, fetched in the prefetch step.
@@ -526,7 +529,7 @@ __device__ inline void bwd_tile(const ViewDesc &v, int64_t tile, Stage<M, NB> &S
         if (L.t < NB) {
             stage<M, NB, true>(nxt, buf, L.t, xc, yc, S, &SB);
 #pragma unroll
-            for (int k = 0; k < kRows * kGrad; ++k) s_acc.row(k / kGrad)[L.t * kGrad + k % kGrad] = 0.f;
+            for (int k = 0; k < kSlot / 4; ++k) s_acc.slot4(L.t)[k] = make_float4(0.f, 0.f, 0.f, 0.f);
         }
         __syncthreads();
         if (b > 0) {
@@ -541,7 +544,7 @@ __device__ inline void bwd_tile(const ViewDesc &v, int64_t tile, Stage<M, NB> &S
             if (__ballot(st.last > base + g * kGroup) == 0) continue;
             const float4 ga = S.attr[buf][g * kGroup + (L.l & (kGroup - 1))];
             const float4 gb = SB.bwd[buf][g * kGroup + (L.l & (kGroup - 1))];
-            float *acc = s_acc.row(L.l >> 4) + g * kGroup * kGrad;   // this lane's row copy
+            float *acc = s_acc.slot(g * kGroup) + (L.l >> 4) * kRowSlot;   // this lane's row copy
             const int rel = st.last - (base + g * kGroup);   // positions < last are in range
             // the whole group is in range for every lane (the common case once past the lanes'
             // last contributors; never for a partial tile, whose outside lanes have last = 0)
@@ -551,23 +554,23 @@ __device__ inline void bwd_tile(const ViewDesc &v, int64_t tile, Stage<M, NB> &S
 #pragma unroll
                     for (int u = kGroup - 1; u >= 0; --u)
                         reverse_pair<false>(plain_q(S, buf, g * kGroup + u, L), true, ga, gb, u,
-                                            L, st, acc + u * kGrad);
+                                            L, st, acc + u * kSlot);
                 } else {
 #pragma unroll
                     for (int u = kGroup - 1; u >= 0; --u)
                         reverse_pair<true>(plain_q(S, buf, g * kGroup + u, L), u < rel, ga, gb, u,
-                                           L, st, acc + u * kGrad);
+                                           L, st, acc + u * kSlot);
                 }
             } else {
                 const f16x q = group_q_mfma<M, NB>(S, buf, g, L, bhi, blo);
                 if (whole) {
 #pragma unroll
                     for (int u = kGroup - 1; u >= 0; --u)
-                        reverse_pair<false>(q[u], true, ga, gb, u, L, st, acc + u * kGrad);
+                        reverse_pair<false>(q[u], true, ga, gb, u, L, st, acc + u * kSlot);
                 } else {
 #pragma unroll
                     for (int u = kGroup - 1; u >= 0; --u)
-                        reverse_pair<true>(q[u], u < rel, ga, gb, u, L, st, acc + u * kGrad);
+                        reverse_pair<true>(q[u], u < rel, ga, gb, u, L, st, acc + u * kSlot);
                 }
             }
         }
@@ -575,14 +578,19 @@ __device__ inline void bwd_tile(const ViewDesc &v, int64_t tile, Stage<M, NB> &S
         // tile has all-zero sums and costs no atomics)
         __syncthreads();
         if (L.t < NB) {
+            float w[kSlot];
+#pragma unroll
+            for (int j = 0; j < kSlot / 4; ++j) {
+                const float4 t4 = s_acc.slot4(L.t)[j];
+                w[4 * j] = t4.x; w[4 * j + 1] = t4.y; w[4 * j + 2] = t4.z; w[4 * j + 3] = t4.w;
+            }
             float a9[kGrad];
+#pragma unroll
+            for (int k = 0; k < kGrad; ++k)
+                a9[k] = (w[k] + w[kRowSlot + k]) + (w[2 * kRowSlot + k] + w[3 * kRowSlot + k]);
             bool any = false;
 #pragma unroll
-            for (int k = 0; k < kGrad; ++k) {
-                a9[k] = s_acc.row(0)[L.t * kGrad + k] + s_acc.row(1)[L.t * kGrad + k] +
-                        s_acc.row(2)[L.t * kGrad + k] + s_acc.row(3)[L.t * kGrad + k];
-                any |= a9[k] != 0.f;
-            }
+            for (int k = 0; k < kGrad; ++k) any |= a9[k] != 0.f;
             if (any) {
                 const uint32_t id = __float_as_uint(SB.bwd[buf][L.t].w);
                 unsafeAtomicAdd(&v.dL_dconics[3 * id + 0], a9[0]);
