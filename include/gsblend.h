@@ -44,6 +44,8 @@ typedef int32_t gsb_status;
 #define GSB_ERR_CAPACITY 2     /* pair list larger than the caller's capacity */
 #define GSB_ERR_UNSUPPORTED 3  /* device is not gfx950 */
 #define GSB_ERR_HIP 4          /* HIP runtime error (message from hipGetErrorString) */
+#define GSB_ERR_INTERNAL 5     /* a device-side consistency check failed (a bounded wait of the
+                                  pair sort expired); the outputs are unspecified */
 
 typedef int32_t gsb_precision;
 #define GSB_FP32_PLAIN 0  /* exponent per pixel in FP32 on the vector ALUs (Alg. 1, Eq. (power)) */
@@ -74,8 +76,8 @@ const char *gsb_last_error(void);
  * ------------------------------------------------------------------------------------------- */
 
 /* Workspace size in bytes for n Gaussians, up to pair_capacity pairs, on a W x H image.
- * Errors: INVALID if n < 0, pair_capacity < 0 or > 2^31 - 1, W or H not in [1, 2^16], or
- * bytes == NULL. */
+ * Errors: INVALID if n < 0 or > 2^24, pair_capacity < 0 or > 2^28, W or H not in [1, 2^16],
+ * or bytes == NULL. */
 gsb_status gsb_bin_workspace_bytes(int64_t n, int64_t pair_capacity, int32_t W, int32_t H,
                                    size_t *bytes);
 
@@ -97,8 +99,8 @@ gsb_status gsb_bin_count(const float *means2d, const int32_t *radii, int64_t n, 
  * ranges:     device u32[gx*gy][2], receives [start, end) of each tile in point_list, [0, 0) for
  *             an empty tile.
  * status_dev: device int32, receives GSB_OK, or GSB_ERR_CAPACITY when the pair count exceeds
- *             pair_capacity; in that case nothing past pair_capacity is written and the contents
- *             of point_list/ranges are unspecified.
+ *             pair_capacity (then nothing past pair_capacity is written and the contents of
+ *             point_list/ranges are unspecified), or GSB_ERR_INTERNAL (see above).
  * ws_bytes must be >= gsb_bin_workspace_bytes(n, pair_capacity, W, H).
  * Errors: INVALID for null pointers, bad sizes, too-small workspace; HIP for launch failures. */
 gsb_status gsb_bin_fill(const float *means2d, const int32_t *radii, const float *depths, int64_t n,

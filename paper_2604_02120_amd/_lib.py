@@ -19,6 +19,7 @@ GSB_ERR_INVALID = 1
 GSB_ERR_CAPACITY = 2
 GSB_ERR_UNSUPPORTED = 3
 GSB_ERR_HIP = 4
+GSB_ERR_INTERNAL = 5
 
 GSB_FP32_PLAIN = 0
 GSB_FP16_GEMM = 1

@@ -45,14 +45,25 @@ struct BinHeader {
     uint32_t pad[10];
 };
 
+// State of one radix sort: the global digit counts of every pass (from the histogram kernel) and
+// the ticket counter from which each pass's blocks draw their tile of keys.
+constexpr int kMaxPasses = 4;
+struct SortState {
+    uint32_t hist[kMaxPasses][kRadix];
+    uint32_t ticket[kMaxPasses];
+    uint32_t pad[64 - kMaxPasses];
+};
+
 size_t align256(size_t b) { return (b + 255) & ~size_t(255); }
 
 struct Layout {
     // bin_count's part (depends on n only)
     size_t hdr, counts, partials;
     // bin_fill's part
-    size_t dkey_a, dkey_b, dval_a, dval_b, offs, tkey_a, tkey_b, vals_tmp, hist, end;
+    size_t sorts, dkey_a, dkey_b, dval_a, dval_b, offs, tkey_a, tkey_b, vals_tmp, sortbuf, end;
 };
+
+int64_t sort_blocks(int64_t m) { return (m + kSortTile - 1) / kSortTile; }
 
 Layout layout(int64_t n, int64_t cap) {
     Layout L;
@@ -61,6 +72,7 @@ Layout layout(int64_t n, int64_t cap) {
     L.hdr = o;       o += align256(sizeof(BinHeader));
     L.counts = o;    o += align256(sizeof(unsigned long long) * nn);
     L.partials = o;  o += align256(sizeof(unsigned long long) * kScanMaxBlocks);
+    L.sorts = o;     o += align256(sizeof(SortState));
     L.dkey_a = o;    o += align256(sizeof(uint32_t) * nn);
     L.dkey_b = o;    o += align256(sizeof(uint32_t) * nn);
     L.dval_a = o;    o += align256(sizeof(uint32_t) * nn);
@@ -69,8 +81,11 @@ Layout layout(int64_t n, int64_t cap) {
     L.tkey_a = o;    o += align256(sizeof(uint32_t) * cc);
     L.tkey_b = o;    o += align256(sizeof(uint32_t) * cc);
     L.vals_tmp = o;  o += align256(sizeof(uint32_t) * cc);
-    const int64_t nblk = ((n > cap ? n : cap) + kSortTile - 1) / kSortTile;
-    L.hist = o;      o += align256(sizeof(uint32_t) * size_t(kRadix) * size_t(nblk > 0 ? nblk : 1));
+    // depth sort: look-back words of every pass, [pass][block][digit]; tile sort, afterwards:
+    // the per-block digit histograms of one pass, [digit][block]
+    const int64_t lb_d = int64_t(kMaxPasses) * sort_blocks(n > 0 ? n : 1);
+    const int64_t lb_t = sort_blocks(cap > 0 ? cap : 1);
+    L.sortbuf = o;   o += align256(sizeof(uint32_t) * kRadix * size_t(lb_d > lb_t ? lb_d : lb_t));
     L.end = o;
     return L;
 }
@@ -241,23 +256,10 @@ __global__ __launch_bounds__(256) void k_bin_count(const float2 *means, const in
 }
 
 // Depth keys: the float's bits, made order-preserving for any sign (a no-op flip of the sign bit
-// for the positive depths of the contract), and the Gaussian index as value.
-__global__ __launch_bounds__(256) void k_depth_keys(const float *depths, int64_t n, uint32_t *keys,
-                                                    uint32_t *vals, BinHeader *hdr) {
-    const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-    if (i == 0) hdr->gaussians = (unsigned long long)n;
-    if (i >= n) return;
-    const uint32_t b = __float_as_uint(depths[i]);
-    keys[i] = (b & 0x80000000u) ? ~b : (b | 0x80000000u);
-    vals[i] = uint32_t(i);
-}
-
-// Counts in depth-rank order (scanned next into each rank's output offset).
-__global__ __launch_bounds__(256) void k_rank_counts(const uint32_t *sorted_idx,
-                                                     const unsigned long long *counts, int64_t n,
-                                                     unsigned long long *offs) {
-    const int64_t j = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-    if (j < n) offs[j] = counts[sorted_idx[j]];
+// for the positive depths of the contract).
+__device__ inline uint32_t depth_key(float d) {
+    const uint32_t b = __float_as_uint(d);
+    return (b & 0x80000000u) ? ~b : (b | 0x80000000u);
 }
 
 // Emits the pairs of the Gaussian of rank j at offs[j]: tile id as key, Gaussian index as value.
@@ -294,7 +296,7 @@ __global__ __launch_bounds__(256) void k_bin_fill(const float2 *means, const int
     if (j == 0) {
         const unsigned long long total = hdr->total;
         hdr->pairs = total < (unsigned long long)cap ? total : (unsigned long long)cap;
-        *status = total > (unsigned long long)cap ? GSB_ERR_CAPACITY : GSB_OK;
+        if (total > (unsigned long long)cap) *status = GSB_ERR_CAPACITY;
     }
     const int64_t j0 = int64_t(blockIdx.x) * blockDim.x;
     if (j0 >= n) return;   // block-uniform (only the single block of an empty launch)
@@ -353,13 +355,74 @@ __global__ __launch_bounds__(256) void k_bin_fill(const float2 *means, const int
 }
 
 // ------------------------------------------------------------------------------- radix sort
-// One pass of a stable LSD radix sort of (u32 key, u32 value) on an 8-bit digit, in three steps:
-// per-block digit histograms (digit-major, so one exclusive scan yields every block's output
-// offset per digit), the scan, and a scatter in which each block ranks its keys stably in LDS and
-// writes them out in digit order (contiguous runs, so the global writes coalesce). The element
-// count is read from device memory (*count).
+// Stable LSD radix sort of (u32 key, u32 value) on 8-bit digits, one kernel per pass plus one
+// histogram kernel per sort (a "onesweep" organisation with decoupled look-back):
+//   * k_sort_hist reads the keys once and accumulates the global digit counts of every pass (at
+//     most 256 blocks, so few blocks add into each global count); it also clears the look-back
+//     words of every pass.
+//   * k_onesweep, one launch per pass: each block draws the index of its tile of 4096 keys from
+//     a ticket counter (so a block only ever waits on tiles whose blocks are already running),
+//     ranks its keys stably in LDS, publishes its per-digit counts, and walks back over the
+//     preceding tiles' published words (16 per step) until it meets an inclusive prefix. A digit's global
+//     start is the exclusive scan of the pass's digit counts plus that prefix. Keys are then
+//     written out in digit order (contiguous runs, so the global writes coalesce).
+// A look-back word is flag << 30 | value: flag 1 = the tile's own count, 2 = inclusive prefix.
+// Every wait is bounded; an expired wait reports GSB_ERR_INTERNAL in the status word instead of
+// hanging. The element count is read from device memory (*count).
+constexpr uint32_t kFlagAgg = 1u << 30, kFlagInc = 2u << 30, kValMask = (1u << 30) - 1u;
+constexpr uint32_t kSpinLimit = 1u << 22;
+constexpr int kLookback = 16;           // preceding tiles read per look-back step
+constexpr int kHistBlocks = 256;        // histogram kernel: at most this many blocks
 
-__global__ __launch_bounds__(kSortThreads) void k_radix_hist(const uint32_t *keys,
+__global__ void k_zero_u32(uint32_t *p, int64_t m) {
+    const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i < m) p[i] = 0u;
+}
+
+// kDepth: the keys are made here from the depths (and written with the identity values);
+// otherwise they are read from keys_io.
+template <bool kDepth>
+__global__ __launch_bounds__(kSortThreads) void k_sort_hist(const float *depths, uint32_t *keys_io,
+                                                            uint32_t *vals_out,
+                                                            const unsigned long long *count,
+                                                            int passes, SortState *st,
+                                                            uint32_t *lookback, int64_t nblk) {
+    __shared__ uint32_t s_h[kMaxPasses][kRadix];
+    const int t = threadIdx.x;
+    for (int p = 0; p < passes; ++p) s_h[p][t] = 0u;
+    // this block's tiles: blockIdx.x, + gridDim.x, ... (their look-back words are cleared here)
+    for (int64_t b = blockIdx.x; b < nblk; b += gridDim.x)
+        for (int p = 0; p < passes; ++p) lookback[(int64_t(p) * nblk + b) * kRadix + t] = 0u;
+    __syncthreads();
+    const int64_t P = int64_t(*count);
+    for (int64_t b = blockIdx.x; b < nblk; b += gridDim.x) {
+        const int64_t base = b * kSortTile;
+        if (base >= P) break;
+#pragma unroll 4
+        for (int k = 0; k < kSortItems; ++k) {
+            const int64_t idx = base + int64_t(k) * kSortThreads + t;
+            if (idx < P) {
+                uint32_t key;
+                if constexpr (kDepth) {
+                    key = depth_key(depths[idx]);
+                    keys_io[idx] = key;
+                    vals_out[idx] = uint32_t(idx);
+                } else {
+                    key = keys_io[idx];
+                }
+                for (int p = 0; p < passes; ++p)
+                    atomicAdd(&s_h[p][(key >> (kRadixBits * p)) & (kRadix - 1)], 1u);
+            }
+        }
+    }
+    __syncthreads();
+    for (int p = 0; p < passes; ++p)
+        if (s_h[p][t]) atomicAdd(&st->hist[p][t], s_h[p][t]);
+}
+
+// Per-block digit histogram of one pass, stored digit-major ([digit][block]) so that one
+// exclusive scan yields every block's output offset per digit.
+__global__ __launch_bounds__(kSortThreads) void k_block_hist(const uint32_t *keys,
                                                              const unsigned long long *count,
                                                              int shift, uint32_t *hist,
                                                              int64_t nblk) {
@@ -378,24 +441,41 @@ __global__ __launch_bounds__(kSortThreads) void k_radix_hist(const uint32_t *key
     hist[int64_t(t) * nblk + blockIdx.x] = s_h[t];
 }
 
-__global__ __launch_bounds__(kSortThreads) void k_radix_scatter(
+__device__ inline void lb_publish(uint32_t *w, uint32_t v) {
+    __hip_atomic_store(w, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ inline uint32_t lb_read(const uint32_t *w) {
+    return __hip_atomic_load(w, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// kRankCounts (last pass of the depth sort): also writes, at each Gaussian's rank, the number of
+// pairs it emits (counts_by_idx[value]) into rank_counts.
+// kChained: the block's tile comes from `ticket` and its digit offsets from the look-back over
+// `lookback` plus the pass's digit counts `ghist`; otherwise tile = blockIdx.x and the offsets are
+// read from `hist_off` ([digit][block], the exclusive scan of the per-block histograms).
+template <bool kChained, bool kRankCounts>
+__global__ __launch_bounds__(kSortThreads) void k_radix_pass(
     const uint32_t *kin, const uint32_t *vin, uint32_t *kout, uint32_t *vout,
-    const unsigned long long *count, int shift, const uint32_t *hist_off, int64_t nblk) {
+    const unsigned long long *count, int shift, const uint32_t *ghist, uint32_t *lookback,
+    uint32_t *ticket, int32_t *status, const uint32_t *hist_off, int64_t nblk,
+    const unsigned long long *counts_by_idx, unsigned long long *rank_counts) {
     __shared__ uint32_t s_wcnt[kSortThreads / 64][kRadix];  // per-wave digit counts, then prefixes
     __shared__ uint32_t s_dstart[kRadix];                     // block-local start of each digit
     __shared__ uint32_t s_gofs[kRadix];                       // global start of each digit
     __shared__ uint32_t s_wave[kSortThreads / 64];
     __shared__ uint32_t s_key[kSortTile];
     __shared__ uint32_t s_val[kSortTile];
+    __shared__ uint32_t s_tile;
 
-    const int64_t P = int64_t(*count);
-    const int64_t base = int64_t(blockIdx.x) * kSortTile;
-    if (base >= P) return;
     const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+    if (kChained && t == 0) s_tile = atomicAdd(ticket, 1u);
 #pragma unroll
     for (int d = 0; d < kSortThreads / 64; ++d) s_wcnt[d][t] = 0;
-    s_gofs[t] = hist_off[int64_t(t) * nblk + blockIdx.x];
     __syncthreads();
+    const int64_t tile = kChained ? int64_t(s_tile) : int64_t(blockIdx.x);
+    const int64_t P = int64_t(*count);
+    const int64_t base = tile * kSortTile;
+    if (base >= P) return;   // block-uniform; every later ticket is empty too
 
     // Wave w ranks keys [base + 1024 w, base + 1024 (w + 1)) in 16 steps of 64 consecutive keys,
     // so rank order within the wave is index order.
@@ -423,7 +503,7 @@ __global__ __launch_bounds__(kSortThreads) void k_radix_scatter(
         loc[k] = prior + rank;
     }
     __syncthreads();
-    // thread t = digit t: exclusive prefix over waves, then over digits
+    // thread t = digit t: exclusive prefix over waves, then the tile's count of digit t
     uint32_t c[kSortThreads / 64], run = 0;
 #pragma unroll
     for (int i = 0; i < kSortThreads / 64; ++i) {
@@ -431,7 +511,47 @@ __global__ __launch_bounds__(kSortThreads) void k_radix_scatter(
         s_wcnt[i][t] = run;
         run += c[i];
     }
+    uint32_t excl = 0;
+    uint32_t *my = kChained ? lookback + tile * kRadix + t : nullptr;
+    if (kChained) lb_publish(my, (tile == 0 ? kFlagInc : kFlagAgg) | run);
+    if (kChained && tile > 0) {
+        // walk back over the preceding tiles kLookback at a time (independent loads), summing
+        // their counts up to the first inclusive prefix; a tile that has published nothing yet is
+        // waited for
+        int64_t j = tile - 1;
+        uint32_t spins = 0;
+        bool done = false;
+        while (!done) {
+            uint32_t wv[kLookback];
+#pragma unroll
+            for (int k = 0; k < kLookback; ++k)
+                wv[k] = (j - k >= 0) ? lb_read(lookback + (j - k) * kRadix + t) : kFlagInc;
+            int k = 0;
+            for (; k < kLookback; ++k) {
+                const uint32_t flag = wv[k] & ~kValMask;
+                if (flag == 0u) break;              // not published yet: re-read from here
+                excl += wv[k] & kValMask;
+                if (flag == kFlagInc) { done = true; break; }
+            }
+            if (done) break;
+            j -= k;
+            if (k < kLookback) {
+                if (++spins > kSpinLimit) {         // never expected: report instead of hanging
+                    *status = GSB_ERR_INTERNAL;
+                    break;
+                }
+                __builtin_amdgcn_s_sleep(1);
+            }
+        }
+        lb_publish(my, kFlagInc | (excl + run));
+    }
     uint32_t tot;
+    if constexpr (kChained) {
+        const uint32_t dglob = block_exclusive_scan<uint32_t>(ghist[t], s_wave, tot);
+        s_gofs[t] = dglob + excl;
+    } else {
+        s_gofs[t] = hist_off[int64_t(t) * nblk + tile];
+    }
     s_dstart[t] = block_exclusive_scan<uint32_t>(run, s_wave, tot);
     __syncthreads();
 #pragma unroll
@@ -452,34 +572,78 @@ __global__ __launch_bounds__(kSortThreads) void k_radix_scatter(
         const int64_t pos = int64_t(s_gofs[d]) + (j - int64_t(s_dstart[d]));
         kout[pos] = k;
         vout[pos] = s_val[j];
+        if constexpr (kRankCounts) rank_counts[pos] = counts_by_idx[s_val[j]];
     }
 }
 
-// Sorts up to cap elements (count on the device) on key bits [0, bits). The data starts in
-// (ka, va) and ends in (ka, va) after an even number of passes, in (kb, vb) after an odd one;
-// returns the number of passes.
-int radix_sort(uint32_t *ka, uint32_t *kb, uint32_t *va, uint32_t *vb,
+// Depth sort of the n Gaussians (count on the device): keys made from `depths`, values the
+// indices, 4 chained passes; the last one also writes each Gaussian's pair count at its rank
+// (rank_counts). The sorted indices end in va (4 passes, an even number).
+void sort_depth(const float *depths, uint32_t *ka, uint32_t *kb, uint32_t *va, uint32_t *vb,
+                const unsigned long long *count, int64_t n, SortState *st, uint32_t *lookback,
+                int32_t *status, const unsigned long long *counts_by_idx,
+                unsigned long long *rank_counts, hipStream_t s) {
+    constexpr int passes = 32 / kRadixBits;
+    const int64_t nblk = sort_blocks(n);
+    if (nblk == 0) return;
+    const int64_t hb = nblk < kHistBlocks ? nblk : kHistBlocks;
+    k_sort_hist<true><<<dim3(unsigned(hb)), kSortThreads, 0, s>>>(depths, ka, va, count, passes,
+                                                                  st, lookback, nblk);
+    uint32_t *kin = ka, *kout = kb, *vin = va, *vout = vb;
+    for (int p = 0; p < passes; ++p) {
+        const int shift = p * kRadixBits;
+        uint32_t *lb = lookback + int64_t(p) * nblk * kRadix;
+        if (p == passes - 1)
+            k_radix_pass<true, true><<<dim3(unsigned(nblk)), kSortThreads, 0, s>>>(
+                kin, vin, kout, vout, count, shift, st->hist[p], lb, &st->ticket[p], status,
+                nullptr, nblk, counts_by_idx, rank_counts);
+        else
+            k_radix_pass<true, false><<<dim3(unsigned(nblk)), kSortThreads, 0, s>>>(
+                kin, vin, kout, vout, count, shift, st->hist[p], lb, &st->ticket[p], status,
+                nullptr, nblk, nullptr, nullptr);
+        std::swap(kin, kout);
+        std::swap(vin, vout);
+    }
+}
+
+// Tile sort of up to cap pairs (count on the device) on key bits [0, bits): per pass a per-block
+// histogram, its exclusive scan and the scatter. (With thousands of tiles of keys the chained
+// passes wait on long look-back chains; the three-step pass does not.) The data ends in (ka, va)
+// after an even number of passes, in (kb, vb) after an odd one; returns the number of passes.
+int sort_tiles(uint32_t *ka, uint32_t *kb, uint32_t *va, uint32_t *vb,
                const unsigned long long *count, int64_t cap, int bits, uint32_t *hist,
-               uint32_t *partial, hipStream_t s) {
-    const int64_t nblk = (cap + kSortTile - 1) / kSortTile;
+               uint32_t *partial, int32_t *status, hipStream_t s) {
+    const int64_t nblk = sort_blocks(cap);
     const int passes = (bits + kRadixBits - 1) / kRadixBits;
     if (nblk == 0) return passes;
     uint32_t *kin = ka, *kout = kb, *vin = va, *vout = vb;
     for (int p = 0; p < passes; ++p) {
         const int shift = p * kRadixBits;
-        k_radix_hist<<<dim3(unsigned(nblk)), kSortThreads, 0, s>>>(kin, count, shift, hist, nblk);
+        k_block_hist<<<dim3(unsigned(nblk)), kSortThreads, 0, s>>>(kin, count, shift, hist, nblk);
         launch_scan<uint32_t>(hist, int64_t(kRadix) * nblk, partial, nullptr, nullptr, s);
-        k_radix_scatter<<<dim3(unsigned(nblk)), kSortThreads, 0, s>>>(kin, vin, kout, vout, count,
-                                                                      shift, hist, nblk);
+        k_radix_pass<false, false><<<dim3(unsigned(nblk)), kSortThreads, 0, s>>>(
+            kin, vin, kout, vout, count, shift, nullptr, nullptr, nullptr, status, hist, nblk,
+            nullptr, nullptr);
         std::swap(kin, kout);
         std::swap(vin, vout);
     }
     return passes;
 }
 
-__global__ __launch_bounds__(256) void k_fill_u32(uint32_t *p, int64_t m, uint32_t v) {
+// Start of bin_fill: empty ranges, zeroed sort states, the Gaussian count for the depth sort and
+// a clean status word (later kernels only ever write error codes into it).
+__global__ __launch_bounds__(256) void k_bin_init(uint32_t *ranges, int64_t m, SortState *sorts,
+                                                  BinHeader *hdr, int64_t n, int32_t *status) {
     const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-    if (i < m) p[i] = v;
+    if (i < m) ranges[i] = 0u;
+    if (blockIdx.x == 0) {
+        uint32_t *w = reinterpret_cast<uint32_t *>(sorts);
+        for (int k = threadIdx.x; k < int(sizeof(SortState) / 4); k += blockDim.x) w[k] = 0u;
+        if (threadIdx.x == 0) {
+            hdr->gaussians = (unsigned long long)n;
+            *status = GSB_OK;
+        }
+    }
 }
 
 __global__ __launch_bounds__(256) void k_ranges(const uint32_t *tiles, const BinHeader *hdr,
@@ -506,6 +670,7 @@ size_t bin_workspace_bytes(int64_t n, int64_t pair_capacity, int64_t /*n_tiles*/
 }
 
 int64_t bin_max_gaussians() { return kScanMaxLen; }
+// the tile sort scans [256][blocks] histograms with the single-top-level scan
 int64_t bin_max_pairs() { return int64_t(kScanMaxLen / kRadix) * kSortTile; }
 
 gsb_status bin_count(const float *means2d, const int32_t *radii, int64_t n, int32_t W, int32_t H,
@@ -532,7 +697,8 @@ gsb_status bin_fill(const float *means2d, const int32_t *radii, const float *dep
     auto *counts = at<unsigned long long>(ws, L.counts);
     auto *partial64 = at<unsigned long long>(ws, L.partials);
     auto *partial32 = at<uint32_t>(ws, L.partials);
-    auto *hist = at<uint32_t>(ws, L.hist);
+    auto *sorts = at<SortState>(ws, L.sorts);
+    auto *sortbuf = at<uint32_t>(ws, L.sortbuf);
     uint32_t *dka = at<uint32_t>(ws, L.dkey_a), *dkb = at<uint32_t>(ws, L.dkey_b);
     uint32_t *dva = at<uint32_t>(ws, L.dval_a), *dvb = at<uint32_t>(ws, L.dval_b);
     auto *offs = at<unsigned long long>(ws, L.offs);
@@ -542,13 +708,14 @@ gsb_status bin_fill(const float *means2d, const int32_t *radii, const float *dep
     const int64_t n_tiles = int64_t(gx) * gy;
     const unsigned gn = unsigned(n > 0 ? (n + 255) / 256 : 1);
 
-    k_fill_u32<<<dim3(unsigned((2 * n_tiles + 255) / 256)), 256, 0, s>>>(ranges, 2 * n_tiles, 0u);
-    // 1. Gaussians by depth (ties by index: the sort is stable over index order)
-    k_depth_keys<<<gn, 256, 0, s>>>(depths, n, dka, dva, hdr);
-    const int dp = radix_sort(dka, dkb, dva, dvb, &hdr->gaussians, n, 32, hist, partial32, s);
-    const uint32_t *sorted_idx = (dp % 2 == 0) ? dva : dvb;
+    k_bin_init<<<dim3(unsigned((2 * n_tiles + 255) / 256)), 256, 0, s>>>(ranges, 2 * n_tiles,
+                                                                       sorts, hdr, n, status_dev);
+    // 1. Gaussians by depth (ties by index: the sort is stable over index order); the last pass
+    //    also lays out each Gaussian's pair count in rank order
+    sort_depth(depths, dka, dkb, dva, dvb, &hdr->gaussians, n, sorts, sortbuf, status_dev,
+               counts, offs, s);
+    const uint32_t *sorted_idx = dva;
     // 2. offsets in rank order; pairs emitted in rank order
-    if (n > 0) k_rank_counts<<<gn, 256, 0, s>>>(sorted_idx, counts, n, offs);
     launch_scan<unsigned long long>(offs, n, partial64, nullptr, nullptr, s);
     const int tile_bits = ceil_log2(n_tiles) > 0 ? ceil_log2(n_tiles) : 1;
     const int tp = (tile_bits + kRadixBits - 1) / kRadixBits;
@@ -558,7 +725,8 @@ gsb_status bin_fill(const float *means2d, const int32_t *radii, const float *dep
     k_bin_fill<<<gn, 256, 0, s>>>(reinterpret_cast<const float2 *>(means2d), radii, sorted_idx, n,
                                   gx, gy, offs, counts, hdr, cap, tka, v_first, status_dev);
     // 3. stable sort of the pairs on the tile id
-    radix_sort(tka, tkb, v_first, v_second, &hdr->pairs, cap, tile_bits, hist, partial32, s);
+    sort_tiles(tka, tkb, v_first, v_second, &hdr->pairs, cap, tile_bits, sortbuf, partial32,
+               status_dev, s);
     const uint32_t *tiles_sorted = (tp % 2 == 0) ? tka : tkb;
     if (cap > 0)
         k_ranges<<<dim3(unsigned((cap + 255) / 256)), 256, 0, s>>>(tiles_sorted, hdr, ranges);
