@@ -119,19 +119,13 @@ struct StageBwd {
 };
 
 constexpr int kGrad = 9;   // per-Gaussian sums kept per batch
-constexpr int kRows = 4;   // 16-lane rows of a wavefront
 
-// Per-Gaussian gradient sums of the current batch. Each 16-lane row of a wavefront adds into its
-// own copy of the Gaussian's sums; the four copies of one Gaussian are adjacent, 10 words apart, so
-// the four row leaders of one LDS add hit four different banks, and the flush reads one
-// Gaussian's copies as ten 16-byte words and sums them.
-constexpr int kRowSlot = 10;                  // words per row copy (9 used)
-constexpr int kSlot = kRows * kRowSlot;       // words per Gaussian
+// Per-Gaussian gradient sums of the current batch: 9 words per staged Gaussian (an odd stride,
+// so the flush's per-thread reads of one word index hit distinct banks).
 template <int NB>
 struct BwdAcc {
-    float4 v[NB * kSlot / 4];
-    __device__ float *slot(int t) { return reinterpret_cast<float *>(v) + t * kSlot; }
-    __device__ float4 *slot4(int t) { return v + t * (kSlot / 4); }
+    float v[NB * kGrad];
+    __device__ float *slot(int t) { return v + t * kGrad; }
 };
 
 // Raw attributes of one list entry, fetched in the prefetch step.
@@ -404,27 +398,39 @@ __device__ inline float dpp_add(float x) {
     return x + __int_as_float(y);
 }
 
-// Materialise the 9 values in registers at this point: stops the compiler from folding a product
-// into the first shift-and-add (which would need an extra move) or from sinking the last one into
-// the leaders' branch (where it could no longer be a single DPP add).
-__device__ inline void pin9(float (&s)[kGrad]) {
-    asm volatile("" : "+v"(s[0]), "+v"(s[1]), "+v"(s[2]), "+v"(s[3]), "+v"(s[4]), "+v"(s[5]),
-                      "+v"(s[6]), "+v"(s[7]), "+v"(s[8]));
+// Sum of 9 values over the whole wavefront, transposed so that the 9 totals land in distinct
+// lanes (two values share each swap-and-add, so the wavefront is halved per value pair, not per
+// value):
+//   permlane32_swap + add on the pairs (s0,s1) (s2,s3) (s4,s5) (s6,s7), and s8 with itself:
+//       lanes 0-31 hold the first value's 32 partial sums, lanes 32-63 the second's;
+//   permlane16_swap + add on the register pairs: rows (16 lanes) hold (s0, s2, s1, s3) and
+//       (s4, s6, s5, s7), every row of the third register s8;
+//   row_shr 1, 2, 4, 8: lane 15 of each row holds its row's total.
+// Result: lane 16r + 15 of a holds s[{0,2,1,3}[r]], of b s[4 + {0,2,1,3}[r]]; lane 15 of c
+// holds s8. Every lane must be active.
+__device__ inline float swap_add32(float &x, float y) {   // returns [x.lo + x.hi | y.lo + y.hi]
+    const auto r = __builtin_amdgcn_permlane32_swap(__float_as_uint(x), __float_as_uint(y), false, false);
+    return __uint_as_float(r[0]) + __uint_as_float(r[1]);
 }
-
-// Sum each of the 9 values over every row of 16 lanes (the total lands in the row's lane 15);
-// the four shift steps are interleaved across the values so no DPP read waits on its producer.
-__device__ inline void row_sum16x9(float (&s)[kGrad]) {
-    pin9(s);
-#pragma unroll
-    for (int k = 0; k < kGrad; ++k) s[k] = dpp_add<0x111>(s[k]);   // row_shr:1
-#pragma unroll
-    for (int k = 0; k < kGrad; ++k) s[k] = dpp_add<0x112>(s[k]);
-#pragma unroll
-    for (int k = 0; k < kGrad; ++k) s[k] = dpp_add<0x114>(s[k]);
-#pragma unroll
-    for (int k = 0; k < kGrad; ++k) s[k] = dpp_add<0x118>(s[k]);   // row_shr:8
-    pin9(s);
+__device__ inline float swap_add16(float x, float y) {    // rows: [x0+x1, y0+y1, x2+x3, y2+y3]
+    const auto r = __builtin_amdgcn_permlane16_swap(__float_as_uint(x), __float_as_uint(y), false, false);
+    return __uint_as_float(r[0]) + __uint_as_float(r[1]);
+}
+__device__ inline void wave_sum9(const float (&s)[kGrad], float &a, float &b, float &c) {
+    float x0 = s[0], x2 = s[2], x4 = s[4], x6 = s[6], x8 = s[8];
+    const float p01 = swap_add32(x0, s[1]), p23 = swap_add32(x2, s[3]);
+    const float p45 = swap_add32(x4, s[5]), p67 = swap_add32(x6, s[7]);
+    const float p88 = swap_add32(x8, s[8]);
+    a = swap_add16(p01, p23);
+    b = swap_add16(p45, p67);
+    c = swap_add16(p88, p88);
+    a = dpp_add<0x111>(a); b = dpp_add<0x111>(b); c = dpp_add<0x111>(c);   // row_shr:1
+    a = dpp_add<0x112>(a); b = dpp_add<0x112>(b); c = dpp_add<0x112>(c);
+    a = dpp_add<0x114>(a); b = dpp_add<0x114>(b); c = dpp_add<0x114>(c);
+    a = dpp_add<0x118>(a); b = dpp_add<0x118>(b); c = dpp_add<0x118>(c);   // row_shr:8
+    // keep the last shift-and-add here, where it is one DPP add, not moved into the callers'
+    // leader branch (where it would need a separate move)
+    asm volatile("" : "+v"(a), "+v"(b), "+v"(c));
 }
 
 struct BwdState {
@@ -435,9 +441,8 @@ struct BwdState {
 // Reverse step for one (Gaussian, pixel) pair. Nothing but a compare and a scalar branch is
 // spent when no lane of the wave has a live pair. Otherwise every lane evaluates the step without
 // branches (a dead lane's terms are forced to zero by selects, and its state is left unchanged),
-// the pair's 9 gradient terms are summed over each row of 16 lanes, and the row totals are added
-// into the Gaussian's LDS accumulator (`acc`), which the block flushes to global memory once per
-// batch. Raw sums: S_xx, S_xy, S_yy, S_x, S_y (times dL/dpower), dL/do, and the three colour
+// the pair's 9 gradient terms are summed over the wavefront, and the totals are added into the
+// Gaussian's LDS accumulator (`acc`), which the block flushes to global memory once per batch. Raw sums: S_xx, S_xy, S_yy, S_x, S_y (times dL/dpower), dL/do, and the three colour
 // gradients.
 // kRanged = false: the caller has checked that the whole group lies before every lane's last
 // contributor, so the skip test alone decides (one compare, whose mask is the ballot).
@@ -467,14 +472,15 @@ __device__ inline void reverse_pair(float q, bool in_range, const float4 &ga, co
     const float dg = q > attr.x ? 0.f : da;
     const float dx = bw.x - L.px, dy = bw.y - L.py;
     const float tx = dg * dx, ty = dg * dy;
-    float s[kGrad] = {tx * dx, tx * dy, ty * dy, tx, ty, da * bw.z,   // dL/do = alpha/o * dL/dalpha
-                      wc * st.gr, wc * st.gg, wc * st.gb};
-    row_sum16x9(s);
-    // only rows with a live lane add (each active leader is one more LDS operation)
-    const bool row_live = ((live >> (L.l & 48)) & 0xffffull) != 0ull;
-    if ((L.l & 15) == 15 && row_live) {
-#pragma unroll
-        for (int k = 0; k < kGrad; ++k) atomicAdd(&acc[k], s[k]);
+    const float s[kGrad] = {tx * dx, tx * dy, ty * dy, tx, ty, da * bw.z,   // dL/do = alpha/o dL/dalpha
+                            wc * st.gr, wc * st.gg, wc * st.gb};
+    float ra, rb, rc;
+    wave_sum9(s, ra, rb, rc);
+    if ((L.l & 15) == 15) {
+        const int r = L.l >> 4, k = 2 * (r & 1) + (r >> 1);   // row r holds s[{0,2,1,3}[r]]
+        atomicAdd(&acc[k], ra);
+        atomicAdd(&acc[4 + k], rb);
+        if (r == 0) atomicAdd(&acc[8], rc);
     }
 }
 
@@ -529,7 +535,7 @@ __device__ inline void bwd_tile(const ViewDesc &v, int64_t tile, Stage<M, NB> &S
         if (L.t < NB) {
             stage<M, NB, true>(nxt, buf, L.t, xc, yc, S, &SB);
 #pragma unroll
-            for (int k = 0; k < kSlot / 4; ++k) s_acc.slot4(L.t)[k] = make_float4(0.f, 0.f, 0.f, 0.f);
+            for (int k = 0; k < kGrad; ++k) s_acc.slot(L.t)[k] = 0.f;
         }
         __syncthreads();
         if (b > 0) {
@@ -544,7 +550,7 @@ __device__ inline void bwd_tile(const ViewDesc &v, int64_t tile, Stage<M, NB> &S
             if (__ballot(st.last > base + g * kGroup) == 0) continue;
             const float4 ga = S.attr[buf][g * kGroup + (L.l & (kGroup - 1))];
             const float4 gb = SB.bwd[buf][g * kGroup + (L.l & (kGroup - 1))];
-            float *acc = s_acc.slot(g * kGroup) + (L.l >> 4) * kRowSlot;   // this lane's row copy
+            float *acc = s_acc.slot(g * kGroup);
             const int rel = st.last - (base + g * kGroup);   // positions < last are in range
             // the whole group is in range for every lane (the common case once past the lanes'
             // last contributors; never for a partial tile, whose outside lanes have last = 0)
@@ -554,23 +560,23 @@ __device__ inline void bwd_tile(const ViewDesc &v, int64_t tile, Stage<M, NB> &S
 #pragma unroll
                     for (int u = kGroup - 1; u >= 0; --u)
                         reverse_pair<false>(plain_q(S, buf, g * kGroup + u, L), true, ga, gb, u,
-                                            L, st, acc + u * kSlot);
+                                            L, st, acc + u * kGrad);
                 } else {
 #pragma unroll
                     for (int u = kGroup - 1; u >= 0; --u)
                         reverse_pair<true>(plain_q(S, buf, g * kGroup + u, L), u < rel, ga, gb, u,
-                                           L, st, acc + u * kSlot);
+                                           L, st, acc + u * kGrad);
                 }
             } else {
                 const f16x q = group_q_mfma<M, NB>(S, buf, g, L, bhi, blo);
                 if (whole) {
 #pragma unroll
                     for (int u = kGroup - 1; u >= 0; --u)
-                        reverse_pair<false>(q[u], true, ga, gb, u, L, st, acc + u * kSlot);
+                        reverse_pair<false>(q[u], true, ga, gb, u, L, st, acc + u * kGrad);
                 } else {
 #pragma unroll
                     for (int u = kGroup - 1; u >= 0; --u)
-                        reverse_pair<true>(q[u], u < rel, ga, gb, u, L, st, acc + u * kSlot);
+                        reverse_pair<true>(q[u], u < rel, ga, gb, u, L, st, acc + u * kGrad);
                 }
             }
         }
@@ -578,16 +584,9 @@ __device__ inline void bwd_tile(const ViewDesc &v, int64_t tile, Stage<M, NB> &S
         // tile has all-zero sums and costs no atomics)
         __syncthreads();
         if (L.t < NB) {
-            float w[kSlot];
-#pragma unroll
-            for (int j = 0; j < kSlot / 4; ++j) {
-                const float4 t4 = s_acc.slot4(L.t)[j];
-                w[4 * j] = t4.x; w[4 * j + 1] = t4.y; w[4 * j + 2] = t4.z; w[4 * j + 3] = t4.w;
-            }
             float a9[kGrad];
 #pragma unroll
-            for (int k = 0; k < kGrad; ++k)
-                a9[k] = (w[k] + w[kRowSlot + k]) + (w[2 * kRowSlot + k] + w[3 * kRowSlot + k]);
+            for (int k = 0; k < kGrad; ++k) a9[k] = s_acc.slot(L.t)[k];
             bool any = false;
 #pragma unroll
             for (int k = 0; k < kGrad; ++k) any |= a9[k] != 0.f;
@@ -620,7 +619,7 @@ __global__ __launch_bounds__(kBlock, M == Mode::Plain ? 8 : 6) void k_blend_fwd(
 }
 
 template <Mode M, int NB>
-__global__ __launch_bounds__(kBlock) void k_blend_bwd(ViewDesc v) {
+__global__ __launch_bounds__(kBlock, M == Mode::Plain ? 7 : 5) void k_blend_bwd(ViewDesc v) {
     __shared__ Stage<M, NB> S;
     __shared__ StageBwd<NB> SB;
     __shared__ BwdAcc<NB> s_acc;   // per-Gaussian gradient sums of the current batch
@@ -676,7 +675,7 @@ __device__ inline bool next_item(const Queues &Q, int &q, int &tried, int &view,
 // Register budgets for the persistent kernels (waves per SIMD): left alone the compiler spreads
 // their registers over the loop and gives up a wave or more against the single-view kernels;
 // these are the highest targets reached without spilling.
-template <Mode M> constexpr int waves_fwd() { return M == Mode::Plain ? 7 : 5; }
+template <Mode M> constexpr int waves_fwd() { return M == Mode::Plain ? 7 : 4; }
 template <Mode M> constexpr int waves_bwd() { return M == Mode::Plain ? 5 : 4; }
 
 template <Mode M, int NB>
@@ -754,7 +753,7 @@ __device__ inline bool grid_item(const Queues &Q, int64_t b, int &view, int64_t 
 }
 
 template <Mode M, int NB>
-__global__ __launch_bounds__(kBlock) void k_blend_fwd_grid(Queues Q) {
+__global__ __launch_bounds__(kBlock, M == Mode::Plain ? 8 : 6) void k_blend_fwd_grid(Queues Q) {
     __shared__ Stage<M, NB> S;
     int view;
     int64_t tile;
@@ -764,7 +763,7 @@ __global__ __launch_bounds__(kBlock) void k_blend_fwd_grid(Queues Q) {
 }
 
 template <Mode M, int NB>
-__global__ __launch_bounds__(kBlock) void k_blend_bwd_grid(Queues Q) {
+__global__ __launch_bounds__(kBlock, M == Mode::Plain ? 7 : 5) void k_blend_bwd_grid(Queues Q) {
     __shared__ Stage<M, NB> S;
     __shared__ StageBwd<NB> SB;
     __shared__ BwdAcc<NB> s_acc;

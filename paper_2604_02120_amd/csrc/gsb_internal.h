@@ -74,8 +74,7 @@ struct Tuning {
 constexpr int kLaunchPersistent = 0;
 constexpr int kLaunchGrid = 1;
 constexpr int kDefaultBatchFwd = 256;
-// backward LDS batch: the plain form's per-pair exponent leaves it bound by LDS occupancy at 128
-constexpr int default_batch_bwd(gsb_precision prec) { return prec == GSB_FP32_PLAIN ? 64 : 128; }
+constexpr int kDefaultBatchBwd = 128;
 
 gsb_status blend_forward(const ViewDesc &v, gsb_precision prec, int batch, hipStream_t s);
 gsb_status blend_backward(const ViewDesc &v, gsb_precision prec, int batch, hipStream_t s);
