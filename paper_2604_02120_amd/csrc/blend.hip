@@ -5,9 +5,11 @@
 //          multiplication) on the matrix cores (MFMA), FP16 or BF16 operands, FP32 accumulation.
 //
 // Launch shape: one 256-thread block (4 wavefronts) per 16x16 tile, one pixel per lane; wave w
-// owns the 8x8 quadrant (w mod 2, w div 2) of the tile. The tile's sorted list is walked in batches of 256 Gaussians: every
-// thread stages one Gaussian into LDS (double-buffered; the next batch's global loads are issued
-// before the current batch is composited), then each wave composites the batch for its pixels.
+// owns the 8x8 quadrant (w mod 2, w div 2) of the tile. The tile's sorted list is walked in
+// batches of NB Gaussians (a template parameter: 64, 128 or 256): every thread below NB stages
+// one Gaussian into LDS (double-buffered; the next batch's global loads are issued before the
+// current batch is composited), then each wave composites the batch for its pixels, 16 Gaussians
+// (one MFMA group) at a time.
 //
 // Exponent in log2 units. With L = log2(e), every path evaluates
 //     q = L * power + log2(o),   alpha = min(0.99, 2^min(q, log2 o))  (= min(0.99, o e^min(power,0)))
@@ -51,9 +53,6 @@ namespace {
 enum class Mode { Plain, F16, BF16 };
 
 constexpr int kGroup = 16;                  // Gaussians per MFMA group
-// Gaussians staged per batch (at most one per thread): forward and backward defaults.
-constexpr int kBatchFwd = 256;
-constexpr int kBatchBwd = 128;
 constexpr float kLog2e = 0x1.715476p+0f;    // log2(e) rounded to FP32
 constexpr float kQCull = -0x1.ffa37cp+2f;   // log2(fp32(1/255)) rounded to FP32
 constexpr float kTauCull = 1.0f / 255.0f;
@@ -611,7 +610,7 @@ __device__ inline void bwd_tile(const ViewDesc &v, int64_t tile, Stage<M, NB> &S
 // ------------------------------------------------------------------------------- kernels
 // Single view: block b renders tile xcd_tile(b).
 template <Mode M, int NB>
-__global__ __launch_bounds__(kBlock, M == Mode::Plain ? 8 : 6) void k_blend_fwd(ViewDesc v) {
+__global__ __launch_bounds__(kBlock, M == Mode::Plain ? 8 : 7) void k_blend_fwd(ViewDesc v) {
     __shared__ Stage<M, NB> S;
     const int64_t tile = xcd_tile(blockIdx.x, v.n_tiles);
     if (tile >= v.n_tiles) return;
@@ -753,7 +752,7 @@ __device__ inline bool grid_item(const Queues &Q, int64_t b, int &view, int64_t 
 }
 
 template <Mode M, int NB>
-__global__ __launch_bounds__(kBlock, M == Mode::Plain ? 8 : 6) void k_blend_fwd_grid(Queues Q) {
+__global__ __launch_bounds__(kBlock, M == Mode::Plain ? 8 : 7) void k_blend_fwd_grid(Queues Q) {
     __shared__ Stage<M, NB> S;
     int view;
     int64_t tile;

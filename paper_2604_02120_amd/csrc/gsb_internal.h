@@ -73,7 +73,7 @@ struct Tuning {
 };
 constexpr int kLaunchPersistent = 0;
 constexpr int kLaunchGrid = 1;
-constexpr int kDefaultBatchFwd = 256;
+constexpr int kDefaultBatchFwd = 128;
 constexpr int kDefaultBatchBwd = 128;
 
 gsb_status blend_forward(const ViewDesc &v, gsb_precision prec, int batch, hipStream_t s);
