@@ -39,11 +39,11 @@ def _load():
         lib = ctypes.CDLL(build())
         P = ctypes.c_void_p
         i64, i32 = ctypes.c_int64, ctypes.c_int32
-        lib.orc_bin_count.argtypes = [P, P, i64, i32, i32]
+        lib.orc_bin_count.argtypes = [P, P, P, P, i32, i64, i32, i32]
         lib.orc_bin_count.restype = i64
-        lib.orc_bin.argtypes = [P, P, P, i64, i32, i32, i64, P, P]
+        lib.orc_bin.argtypes = [P, P, P, P, i32, P, i64, i32, i32, i64, P, P]
         lib.orc_bin.restype = i64
-        lib.orc_bin_tile.argtypes = [P, P, P, i64, i32, i32, i64, i64, P]
+        lib.orc_bin_tile.argtypes = [P, P, P, P, i32, P, i64, i32, i32, i64, i64, P]
         lib.orc_bin_tile.restype = i64
         lib.orc_forward.argtypes = [i32, i32, P, P, P, P, P, P, P, P, P, P, P, P, P]
         lib.orc_forward.restype = None
@@ -75,41 +75,65 @@ def grid(W: int, H: int) -> tuple[int, int]:
     return (W + TILE - 1) // TILE, (H + TILE - 1) // TILE
 
 
-def bin_tiles(means2d, radii, depths, W: int, H: int) -> tuple[np.ndarray, np.ndarray]:
+# Binning modes: 0 = every tile of the 3-sigma square (the rule of the method); 1 = only the tiles
+# of that square on which the Gaussian can reach alpha >= 1/255 (the opacity-aware extent, a
+# tighter binning that leaves images unchanged; rule in gsoracle.c).
+BIN_RECT, BIN_VISIBLE = 0, 1
+
+
+def _bin_args(means2d, radii, conics, opacity, mode):
+    m = _f64(means2d)
+    r = np.ascontiguousarray(radii, dtype=np.int32)
+    if mode == BIN_RECT:
+        return m, r, None, None
+    if conics is None or opacity is None:
+        raise ValueError("binning mode 1 needs conics and opacity")
+    return m, r, _f64(conics), _f64(opacity)
+
+
+def _p(a):
+    return None if a is None else _ptr(a)
+
+
+def bin_tiles(means2d, radii, depths, W: int, H: int, conics=None, opacity=None,
+              mode: int = BIN_RECT) -> tuple[np.ndarray, np.ndarray]:
     """(point_list u32[P], ranges u32[n_tiles][2]) sorted by (tile, depth, index)."""
     lib = _load()
-    m, d = _f64(means2d), _f64(depths)
-    r = np.ascontiguousarray(radii, dtype=np.int32)
+    m, r, c, o = _bin_args(means2d, radii, conics, opacity, mode)
+    d = _f64(depths)
     n = r.shape[0]
-    total = lib.orc_bin_count(_ptr(m), _ptr(r), n, W, H)
+    total = lib.orc_bin_count(_ptr(m), _ptr(r), _p(c), _p(o), mode, n, W, H)
     gx, gy = grid(W, H)
     point_list = np.zeros(max(total, 1), np.uint32)
     ranges = np.zeros((gx * gy, 2), np.uint32)
-    got = lib.orc_bin(_ptr(m), _ptr(r), _ptr(d), n, W, H, total, _ptr(point_list), _ptr(ranges))
+    got = lib.orc_bin(_ptr(m), _ptr(r), _p(c), _p(o), mode, _ptr(d), n, W, H, total,
+                      _ptr(point_list), _ptr(ranges))
     assert got == total
     return point_list[:total], ranges
 
 
-def bin_tile(means2d, radii, depths, W: int, H: int, t: int) -> np.ndarray:
+def bin_tile(means2d, radii, depths, W: int, H: int, t: int, conics=None, opacity=None,
+             mode: int = BIN_RECT) -> np.ndarray:
     """Sorted list (u32) of tile t alone."""
     lib = _load()
-    m, d = _f64(means2d), _f64(depths)
-    r = np.ascontiguousarray(radii, dtype=np.int32)
+    m, r, c, o = _bin_args(means2d, radii, conics, opacity, mode)
+    d = _f64(depths)
     n = r.shape[0]
-    k = lib.orc_bin_tile(_ptr(m), _ptr(r), _ptr(d), n, W, H, t, 0, None)
+    k = lib.orc_bin_tile(_ptr(m), _ptr(r), _p(c), _p(o), mode, _ptr(d), n, W, H, t, 0, None)
     out = np.zeros(max(k, 1), np.uint32)
-    lib.orc_bin_tile(_ptr(m), _ptr(r), _ptr(d), n, W, H, t, k, _ptr(out))
+    lib.orc_bin_tile(_ptr(m), _ptr(r), _p(c), _p(o), mode, _ptr(d), n, W, H, t, k, _ptr(out))
     return out[:k]
 
 
-def sampled_bins(means2d, radii, depths, W: int, H: int, tiles) -> tuple[np.ndarray, np.ndarray]:
+def sampled_bins(means2d, radii, depths, W: int, H: int, tiles, conics=None, opacity=None,
+                 mode: int = BIN_RECT) -> tuple[np.ndarray, np.ndarray]:
     """(point_list, ranges) in which only the given tiles hold their lists (every other tile is
     empty): the binning of a frame restricted to a sample of its tiles."""
     gx, gy = grid(W, H)
     ranges = np.zeros((gx * gy, 2), np.uint32)
     lists, pos = [], 0
     for t in sorted(int(t) for t in tiles):
-        lst = bin_tile(means2d, radii, depths, W, H, t)
+        lst = bin_tile(means2d, radii, depths, W, H, t, conics, opacity, mode)
         ranges[t] = (pos, pos + len(lst)) if len(lst) else (0, 0)
         lists.append(lst)
         pos += len(lst)

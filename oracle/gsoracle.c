@@ -83,13 +83,86 @@ static void tile_rect(double x, double y, int32_t r, int64_t gx, int64_t gy,
     *ty1 = clamp_i64((int64_t)floor((y + r + ORC_TILE - 1) / ORC_TILE), 0, gy);
 }
 
-/* Number of (tile, Gaussian) pairs. */
-int64_t orc_bin_count(const double *means2d, const int32_t *radii, int64_t n, int32_t W, int32_t H) {
+/* ---- Binning mode 1: tiles on which the Gaussian can be visible (the opacity-aware extent of
+ * a tighter binning; the paper's method is unchanged by it, see below).
+ *
+ * alpha = o exp(-Q/2) with Q = d^T Sigma^-1 d reaches 1/255 only where Q <= 2 ln(255 o). A pair
+ * (tile, Gaussian) of the 3-sigma rectangle is kept iff o >= fp32(1/255) and the minimum of Q over
+ * the rectangle spanned by the tile's pixels inside the image is <= theta, where theta is an upper
+ * bound of 2 ln(255 o) that needs no logarithm, plus a margin:
+ *     255 o = m 2^e (m in [1, 2)),  ln(255 o) <= e ln2 + (m - 1),
+ *     theta = 2 (e * LN2_UP + (m - 1)) + 0.1   (LN2_UP: the double just above ln 2).
+ * A dropped pair has alpha < (1/255) e^-0.05 on every pixel of its tile, so any evaluation whose
+ * exponent error is far below 0.05 (every path here) skips it anyway: images and final T are
+ * unchanged; only positions within the lists (last_contrib) move.
+ * Q's minimum over a rectangle of d = (x - px, y - py) is 0 when the rectangle contains d = 0,
+ * else it lies on one of the four edges, each a 1D quadratic minimised at an interior point or at
+ * an end. Every test is written without division, with this fixed sequence of IEEE double
+ * operations (no contraction), so the decision is reproducible bit for bit. */
+#define ORC_LN2_UP 0x1.62e42fefa39fp-1
+#define ORC_CULL_MARGIN 0.1
+
+static double vis_theta(double o) {
+    const double z = 255.0 * o;                 /* exact: o is an fp32 value */
+    uint64_t bits;
+    memcpy(&bits, &z, sizeof bits);
+    const int64_t e = (int64_t)((bits >> 52) & 0x7ff) - 1023;
+    const uint64_t mb = (bits & 0x000fffffffffffffull) | 0x3ff0000000000000ull;
+    double m;
+    memcpy(&m, &mb, sizeof m);
+    const double t1 = (double)e * ORC_LN2_UP;
+    const double t2 = m - 1.0;
+    return 2.0 * (t1 + t2) + ORC_CULL_MARGIN;
+}
+
+/* one edge: u fixed at a, v in [c, d]; Q = P a^2 + 2 B a v + R v^2 (P, R = A, C or C, A) */
+static int vis_edge(double P, double R, double B, double det, double theta, double a, double c,
+                    double d) {
+    const double ba = B * a;
+    const double nba = -ba;
+    if (c * R <= nba && nba <= d * R) {           /* interior minimum a^2 det / R */
+        const double lhs = (a * a) * det;
+        const double rhs = theta * R;
+        return lhs <= rhs;
+    }
+    const double pa2 = P * (a * a);
+    const double qc = (pa2 + (2.0 * ba) * c) + R * (c * c);
+    const double qd = (pa2 + (2.0 * ba) * d) + R * (d * d);
+    return qc <= theta || qd <= theta;
+}
+
+static int tile_visible(double x, double y, const double *conic, double o, int64_t tx, int64_t ty,
+                        int32_t W, int32_t H) {
+    if (o < (double)(1.0f / 255.0f)) return 0;
+    const double A = conic[0], B = conic[1], C = conic[2];
+    const double x0 = (double)(tx * ORC_TILE), y0 = (double)(ty * ORC_TILE);
+    const double x1 = (double)(tx * ORC_TILE + ORC_TILE - 1 < W - 1 ? tx * ORC_TILE + ORC_TILE - 1 : W - 1);
+    const double y1 = (double)(ty * ORC_TILE + ORC_TILE - 1 < H - 1 ? ty * ORC_TILE + ORC_TILE - 1 : H - 1);
+    const double dxl = x - x1, dxh = x - x0, dyl = y - y1, dyh = y - y0;
+    if (dxl <= 0.0 && 0.0 <= dxh && dyl <= 0.0 && 0.0 <= dyh) return 1;
+    const double theta = vis_theta(o);
+    const double det = A * C - B * B;
+    return vis_edge(A, C, B, det, theta, dxl, dyl, dyh) || vis_edge(A, C, B, det, theta, dxh, dyl, dyh) ||
+           vis_edge(C, A, B, det, theta, dyl, dxl, dxh) || vis_edge(C, A, B, det, theta, dyh, dxl, dxh);
+}
+
+/* whether pair (tile (tx, ty), Gaussian i) is emitted under `mode` (0: the 3-sigma rectangle alone) */
+static int pair_kept(int mode, const double *means2d, const double *conics, const double *opacity,
+                     int64_t i, int64_t tx, int64_t ty, int32_t W, int32_t H) {
+    if (mode == 0) return 1;
+    return tile_visible(means2d[2 * i], means2d[2 * i + 1], conics + 3 * i, opacity[i], tx, ty, W, H);
+}
+
+/* Number of (tile, Gaussian) pairs. conics/opacity are read in mode 1 only. */
+int64_t orc_bin_count(const double *means2d, const int32_t *radii, const double *conics,
+                      const double *opacity, int32_t mode, int64_t n, int32_t W, int32_t H) {
     int64_t gx = (W + ORC_TILE - 1) / ORC_TILE, gy = (H + ORC_TILE - 1) / ORC_TILE, total = 0;
     for (int64_t i = 0; i < n; ++i) {
-        int64_t a, b, c, d;
-        tile_rect(means2d[2 * i], means2d[2 * i + 1], radii[i], gx, gy, &a, &b, &c, &d);
-        total += (b - a) * (d - c);
+        int64_t tx0, tx1, ty0, ty1;
+        tile_rect(means2d[2 * i], means2d[2 * i + 1], radii[i], gx, gy, &tx0, &tx1, &ty0, &ty1);
+        for (int64_t ty = ty0; ty < ty1; ++ty)
+            for (int64_t tx = tx0; tx < tx1; ++tx)
+                total += pair_kept(mode, means2d, conics, opacity, i, tx, ty, W, H);
     }
     return total;
 }
@@ -107,10 +180,11 @@ static int pair_less(const void *pa, const void *pb) {
 /* Duplicate, sort by (tile, depth, index), extract ranges.
  * point_list: u32[capacity]; ranges: u32[gx*gy][2] as [start, end), [0, 0) when empty.
  * Returns the pair count, or -1 if it exceeds capacity (nothing written then). */
-int64_t orc_bin(const double *means2d, const int32_t *radii, const double *depths, int64_t n,
-                int32_t W, int32_t H, int64_t capacity, uint32_t *point_list, uint32_t *ranges) {
+int64_t orc_bin(const double *means2d, const int32_t *radii, const double *conics,
+                const double *opacity, int32_t mode, const double *depths, int64_t n, int32_t W,
+                int32_t H, int64_t capacity, uint32_t *point_list, uint32_t *ranges) {
     int64_t gx = (W + ORC_TILE - 1) / ORC_TILE, gy = (H + ORC_TILE - 1) / ORC_TILE;
-    int64_t total = orc_bin_count(means2d, radii, n, W, H);
+    int64_t total = orc_bin_count(means2d, radii, conics, opacity, mode, n, W, H);
     if (total > capacity) return -1;
     orc_pair *pairs = (orc_pair *)malloc(sizeof(orc_pair) * (size_t)(total > 0 ? total : 1));
     int64_t k = 0;
@@ -119,6 +193,7 @@ int64_t orc_bin(const double *means2d, const int32_t *radii, const double *depth
         tile_rect(means2d[2 * i], means2d[2 * i + 1], radii[i], gx, gy, &tx0, &tx1, &ty0, &ty1);
         for (int64_t ty = ty0; ty < ty1; ++ty)
             for (int64_t tx = tx0; tx < tx1; ++tx) {
+                if (!pair_kept(mode, means2d, conics, opacity, i, tx, ty, W, H)) continue;
                 pairs[k].tile = ty * gx + tx;
                 pairs[k].depth = depths[i];
                 pairs[k].idx = i;
@@ -140,7 +215,8 @@ int64_t orc_bin(const double *means2d, const int32_t *radii, const double *depth
 /* The sorted list of one tile alone: every Gaussian whose rectangle covers tile t, ordered by
  * (depth, index). Writes up to cap indices; returns the full count. (Used to check single tiles of
  * frames too large to bin whole on the CPU.) */
-int64_t orc_bin_tile(const double *means2d, const int32_t *radii, const double *depths, int64_t n,
+int64_t orc_bin_tile(const double *means2d, const int32_t *radii, const double *conics,
+                     const double *opacity, int32_t mode, const double *depths, int64_t n,
                      int32_t W, int32_t H, int64_t t, int64_t cap, uint32_t *out) {
     int64_t gx = (W + ORC_TILE - 1) / ORC_TILE, gy = (H + ORC_TILE - 1) / ORC_TILE;
     const int64_t tx = t % gx, ty = t / gx;
@@ -151,6 +227,7 @@ int64_t orc_bin_tile(const double *means2d, const int32_t *radii, const double *
         int64_t tx0, tx1, ty0, ty1;
         tile_rect(means2d[2 * i], means2d[2 * i + 1], radii[i], gx, gy, &tx0, &tx1, &ty0, &ty1);
         if (tx < tx0 || tx >= tx1 || ty < ty0 || ty >= ty1) continue;
+        if (!pair_kept(mode, means2d, conics, opacity, i, tx, ty, W, H)) continue;
         if (k == room) {
             room *= 2;
             pairs = (orc_pair *)realloc(pairs, sizeof(orc_pair) * (size_t)room);

@@ -437,3 +437,101 @@ def test_bin_tile_matches_bruteforce():
         assert got.tolist() == [i for _, i in want]
     pl, rg = oracle.sampled_bins(s["means2d"], s["radii"], s["depths"], W, H, [0, 3, 5])
     assert np.count_nonzero(rg[:, 1] - rg[:, 0]) <= 3
+
+
+# ----------------------------------------------------------------------------- binning mode 1
+def bf_tile_max_alpha(scene, i, tx, ty):
+    """Largest alpha = min(0.99, o exp(min(P, 0))) of Gaussian i over the pixels of tile (tx, ty)
+    that lie inside the image, by direct evaluation of the quadratic form at every pixel."""
+    W, H = scene["width"], scene["height"]
+    px = np.arange(16 * tx, min(16 * tx + 16, W), dtype=float)
+    py = np.arange(16 * ty, min(16 * ty + 16, H), dtype=float)
+    X, Y = np.meshgrid(px, py)
+    m = scene["means2d"][i].astype(float)
+    a, b, c = scene["conics"][i].astype(float)
+    dx, dy = m[0] - X, m[1] - Y
+    P = -0.5 * (a * dx * dx + 2.0 * b * dx * dy + c * dy * dy)
+    return float(np.max(np.minimum(A_MAX, float(scene["opacity"][i]) * np.exp(np.minimum(P, 0.0)))))
+
+
+def needle_scene(seed=61, n=60, W=56, H=40):
+    """Strongly anisotropic Gaussians (axis ratio up to 64) at all angles, opacities down to
+    just above 1/255: the case where the 3-sigma square overstates the footprint most."""
+    rng = np.random.default_rng(seed)
+    s = gsinputs.make_scene("C1", seed=seed, n=n, width=W, height=H)
+    th = rng.uniform(0, np.pi, n)
+    s1 = rng.uniform(0.5, 1.0, n)
+    s2 = rng.uniform(4.0, 32.0, n)
+    s["conics"] = gsinputs.conic_from_axes(th, s1, s2).astype(np.float32)
+    s["radii"] = np.ceil(3.0 * np.maximum(s1, s2)).astype(np.int32)
+    s["opacity"] = rng.uniform(1.0 / 255.0, 0.99, n).astype(np.float32)
+    return s
+
+
+VIS_SCENES = {"C1": lambda: gsinputs.make_scene("C1"), "small": lambda: small_scene(21),
+              "needles": needle_scene}
+
+
+@pytest.mark.parametrize("name", list(VIS_SCENES))
+def test_visible_binning_drops_only_invisible_pairs(name):
+    """Mode 1 keeps every pair whose Gaussian reaches alpha >= 1/255 on an image pixel of the tile,
+    and every pair it drops stays below (1/255) e^-0.05 on the whole tile (the stated margin)."""
+    s = VIS_SCENES[name]()
+    W, H = s["width"], s["height"]
+    gx, gy = oracle.grid(W, H)
+    pl0, rg0 = oracle.bin_tiles(s["means2d"], s["radii"], s["depths"], W, H)
+    pl1, rg1 = oracle.bin_tiles(s["means2d"], s["radii"], s["depths"], W, H, s["conics"],
+                                s["opacity"], oracle.BIN_VISIBLE)
+    dropped = 0
+    for t in range(gx * gy):
+        full = pl0[rg0[t, 0]:rg0[t, 1]].tolist()
+        kept = pl1[rg1[t, 0]:rg1[t, 1]].tolist()
+        assert kept == [i for i in full if i in set(kept)]     # a subsequence, same order
+        for i in set(full) - set(kept):
+            amax = bf_tile_max_alpha(s, i, t % gx, t // gx)
+            assert amax < TAU * math.exp(-0.05), (name, t, i, amax)
+            dropped += 1
+    assert dropped > 0.2 * len(pl0), (name, dropped, len(pl0))
+
+
+@pytest.mark.parametrize("name", list(VIS_SCENES))
+def test_visible_binning_keeps_images(name):
+    """The forward over mode-1 lists equals the forward over the 3-sigma lists exactly (image and
+    final T), and each pixel's last contributor is the same Gaussian."""
+    s = VIS_SCENES[name]()
+    W, H = s["width"], s["height"]
+    gx, gy = oracle.grid(W, H)
+    pl0, rg0 = oracle.bin_tiles(s["means2d"], s["radii"], s["depths"], W, H)
+    pl1, rg1 = oracle.bin_tiles(s["means2d"], s["radii"], s["depths"], W, H, s["conics"],
+                                s["opacity"], oracle.BIN_VISIBLE)
+    args = (s["means2d"], s["conics"], s["opacity"], s["colors"], (0.2, 0.1, 0.3))
+    r0 = oracle.forward(W, H, rg0, pl0, *args)
+    r1 = oracle.forward(W, H, rg1, pl1, *args)
+    assert np.array_equal(r0["image"], r1["image"]) and np.array_equal(r0["final_T"], r1["final_T"])
+    for py in range(H):
+        for px in range(W):
+            t = (py // 16) * gx + px // 16
+            l0, l1 = r0["last_contrib"][py, px], r1["last_contrib"][py, px]
+            assert (l0 == 0) == (l1 == 0)
+            if l0:
+                assert pl0[rg0[t, 0] + l0 - 1] == pl1[rg1[t, 0] + l1 - 1]
+
+
+def test_visible_binning_edge_cases():
+    """Opacity below 1/255 emits nothing; a Gaussian visible only beyond the image's right edge is
+    dropped from the partial edge tile; one centred on a tile is kept there."""
+    W, H = 40, 20                                   # last tile column holds pixels 32..39 only
+    s = gsinputs.stack_scene(3, 0.5, width=W, height=H, at=(8.0, 8.0))
+    s["means2d"][1] = (46.0, 8.0)                   # 6 px right of the last pixel column
+    s["conics"][1] = (4.0, 0.0, 4.0)                # sigma 0.5: alpha ~ 0.5 exp(-72) at x = 39
+    s["radii"][1] = 8
+    s["opacity"][2] = np.float32(1.0 / 255.0) * np.float32(0.999)
+    s["radii"][2] = 4
+    pl, rg = oracle.bin_tiles(s["means2d"], s["radii"], s["depths"], W, H, s["conics"],
+                              s["opacity"], oracle.BIN_VISIBLE)
+    assert 2 not in pl.tolist()
+    assert 1 not in pl.tolist()
+    gx, _ = oracle.grid(W, H)
+    assert 0 in pl[rg[0, 0]:rg[0, 1]].tolist()
+    pl0, _ = oracle.bin_tiles(s["means2d"], s["radii"], s["depths"], W, H)
+    assert 1 in pl0.tolist() and 2 in pl0.tolist()   # the 3-sigma square does emit them
