@@ -56,6 +56,8 @@ def parse():
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--no-batched", action="store_true",
                    help="skip the 16-view batched measurement")
+    p.add_argument("--no-visible", action="store_true",
+                   help="skip the step with visible-tile binning")
     p.add_argument("--calib-copy-mib", type=int, default=0,
                    help="also run one device-to-device copy of this many MiB (a known-size "
                         "kernel for scaling HBM byte counters)")
@@ -66,7 +68,8 @@ class Frame:
     """Device buffers of one frame: inputs, binning workspace sized for the exact pair count,
     outputs and gradients."""
 
-    def __init__(self, cfg, dev):
+    def __init__(self, cfg, dev, bin_mode="rect"):
+        self.bin_mode = bin_mode
         s = gsinputs.make_scene(cfg)
         self.scene = s
         self.W, self.H, self.n = s["width"], s["height"], len(s["radii"])
@@ -76,7 +79,9 @@ class Frame:
         self.dloss_np = gsinputs.make_dloss(self.W, self.H, cfg.dloss_seed)
         self.dloss = t(self.dloss_np)
         ws0 = api.BinWorkspace(self.n, 0, self.W, self.H, device=dev)
-        self.pairs = int(api.bin_count(self.means2d, self.radii, self.W, self.H, ws0).item())
+        self.pairs = int(api.bin_count(self.means2d, self.radii, self.W, self.H, ws0,
+                                       conics=self.conics, opacity=self.opacity,
+                                       mode=bin_mode).item())
         self.ws = api.BinWorkspace(self.n, self.pairs, self.W, self.H, device=dev)
         gx, gy = api.grid(self.W, self.H)
         self.point_list = torch.empty(self.pairs, dtype=torch.int32, device=dev)
@@ -91,9 +96,11 @@ class Frame:
     def step(self, prec, ev=None):
         if ev is not None:
             ev[0].record()
-        api.bin_count(self.means2d, self.radii, self.W, self.H, self.ws)
+        api.bin_count(self.means2d, self.radii, self.W, self.H, self.ws, conics=self.conics,
+                      opacity=self.opacity, mode=self.bin_mode)
         self.status = api.bin_fill(self.means2d, self.radii, self.depths, self.W, self.H, self.ws,
-                                   self.point_list, self.ranges)
+                                   self.point_list, self.ranges, conics=self.conics,
+                                   opacity=self.opacity, mode=self.bin_mode)
         if ev is not None:
             ev[1].record()
         img, T, last = api.blend_forward(self.means2d, self.conics, self.opacity, self.colors,
@@ -212,6 +219,22 @@ def time_batched(steps: int, warmup: int, dev) -> dict:
     return out
 
 
+def time_visible(cfg, dev, prec: str, steps: int, warmup: int, head: dict, ref_out) -> dict:
+    """The same step with binning mode "visible" (only tiles where alpha can reach 1/255): fewer
+    pairs, the same images. Reported beside the headline, which bins with the 3-sigma square."""
+    fr = Frame(cfg, dev, bin_mode="visible")
+    r = time_path(fr, prec, steps, warmup)
+    out = {"mode": "visible", "precision": prec, "pairs": fr.pairs,
+           **{k: (round(v, 4) if isinstance(v, float) else v) for k, v in r.items()},
+           "speedup_vs_rect_binning": {"step": round(head["ms_per_step"] / r["ms_per_step"], 3),
+                                       "blend": round(r["blend_mpix_s"] / head["blend_mpix_s"], 3)}}
+    if ref_out is not None:       # the images must be those of the 3-sigma binning, bit for bit
+        img, T, _ = (x.cpu().numpy() for x in fr.fwd_out)
+        out["image_identical_to_rect_binning"] = bool(
+            np.array_equal(img.astype(np.float64), ref_out[0]) and np.array_equal(T, ref_out[1]))
+    return out
+
+
 def kernel_hash() -> str:
     return hashlib.sha256(open(KERNEL_SRC, "rb").read()).hexdigest()[:16]
 
@@ -321,6 +344,9 @@ def main():
         line["speedup_vs_plain_fp32"] = {
             "step": round(results["fp32"]["ms_per_step"] / head["ms_per_step"], 3),
             "blend": round(head["blend_mpix_s"] / results["fp32"]["blend_mpix_s"], 3)}
+    if not args.no_visible:
+        line["visible_binning"] = time_visible(cfg, dev, precs[0], args.steps, args.warmup,
+                                               head, outputs.get(precs[0]))
     if not args.no_batched:
         line["batched_c4"] = time_batched(max(5, args.steps // 2), 2, dev)
     if not args.no_cpu_baseline:

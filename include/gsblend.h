@@ -52,7 +52,7 @@ typedef int32_t gsb_precision;
 #define GSB_FP16_GEMM 1   /* exponent as an MFMA product, FP16 hi+lo operands, FP32 accumulate */
 #define GSB_BF16_GEMM 2   /* same with BF16 hi+lo operands */
 
-#define GSB_ABI_VERSION 1
+#define GSB_ABI_VERSION 2
 
 /* Version of this interface (GSB_ABI_VERSION of the library that was loaded). */
 int32_t gsb_abi_version(void);
@@ -81,12 +81,30 @@ const char *gsb_last_error(void);
 gsb_status gsb_bin_workspace_bytes(int64_t n, int64_t pair_capacity, int32_t W, int32_t H,
                                    size_t *bytes);
 
+/* Binning modes.
+ * GSB_BIN_RECT:    every tile of the 3-sigma square above (the method's rule).
+ * GSB_BIN_VISIBLE: only the tiles of that square on which the Gaussian can reach alpha >= 1/255
+ *   at a pixel inside the image (an opacity-aware extent: the tighter binning that the paper
+ *   combines its blend with, Sec. 2.1(c) and the orthogonality study of Sec. 4). A pair is kept
+ *   iff o >= fp32(1/255) and the minimum of Q = d^T Sigma^-1 d over the tile's pixel rectangle is
+ *   <= 2 (e ln2 + m - 1) + 0.1 with 255 o = m 2^e, m in [1, 2) (an upper bound of 2 ln(255 o),
+ *   plus a margin), decided by division-free double-precision tests, reproducibly. A dropped pair
+ *   has alpha < (1/255) e^-0.05 on every pixel of its tile, so the blend would skip it: images
+ *   and final T are those of GSB_BIN_RECT; last_contrib positions refer to the shorter lists.
+ *   Needs conics and opacity (same layouts as for the blend). */
+typedef int32_t gsb_bin_mode;
+#define GSB_BIN_RECT 0
+#define GSB_BIN_VISIBLE 1
+
 /* Counts the pairs each Gaussian emits (kept in `ws`) and writes the total to the device int64
  * *n_pairs_dev. Asynchronous on `stream`.
+ * conics, opacity: device f32[n][3], f32[n], read in GSB_BIN_VISIBLE only (may be NULL in
+ *            GSB_BIN_RECT). gsb_bin_fill must then be called with the same mode and arrays.
  * ws: device workspace of ws_bytes >= gsb_bin_workspace_bytes(n, 0, W, H) bytes.
- * Errors: INVALID for null pointers (means2d/radii may be null only when n == 0), bad sizes or a
- * too-small workspace; HIP for launch failures. */
-gsb_status gsb_bin_count(const float *means2d, const int32_t *radii, int64_t n, int32_t W,
+ * Errors: INVALID for null pointers (means2d/radii may be null only when n == 0), an unknown mode,
+ * bad sizes or a too-small workspace; HIP for launch failures. */
+gsb_status gsb_bin_count(const float *means2d, const int32_t *radii, const float *conics,
+                         const float *opacity, gsb_bin_mode mode, int64_t n, int32_t W,
                          int32_t H, void *ws, size_t ws_bytes, int64_t *n_pairs_dev,
                          void *stream);
 
@@ -103,7 +121,8 @@ gsb_status gsb_bin_count(const float *means2d, const int32_t *radii, int64_t n, 
  *             point_list/ranges are unspecified), or GSB_ERR_INTERNAL (see above).
  * ws_bytes must be >= gsb_bin_workspace_bytes(n, pair_capacity, W, H).
  * Errors: INVALID for null pointers, bad sizes, too-small workspace; HIP for launch failures. */
-gsb_status gsb_bin_fill(const float *means2d, const int32_t *radii, const float *depths, int64_t n,
+gsb_status gsb_bin_fill(const float *means2d, const int32_t *radii, const float *conics,
+                        const float *opacity, gsb_bin_mode mode, const float *depths, int64_t n,
                         int32_t W, int32_t H, void *ws, size_t ws_bytes, uint32_t *point_list,
                         int64_t pair_capacity, uint32_t *ranges, int32_t *status_dev,
                         void *stream);

@@ -20,6 +20,8 @@ GSB_ERR_CAPACITY = 2
 GSB_ERR_UNSUPPORTED = 3
 GSB_ERR_HIP = 4
 GSB_ERR_INTERNAL = 5
+GSB_BIN_RECT = 0
+GSB_BIN_VISIBLE = 1
 
 GSB_FP32_PLAIN = 0
 GSB_FP16_GEMM = 1
@@ -77,8 +79,8 @@ def load() -> ctypes.CDLL:
     lib.gsb_last_error.argtypes = []
     lib.gsb_last_error.restype = ctypes.c_char_p
     lib.gsb_bin_workspace_bytes.argtypes = [i64, i64, i32, i32, ctypes.POINTER(sz)]
-    lib.gsb_bin_count.argtypes = [P, P, i64, i32, i32, P, sz, P, P]
-    lib.gsb_bin_fill.argtypes = [P, P, P, i64, i32, i32, P, sz, P, i64, P, P, P]
+    lib.gsb_bin_count.argtypes = [P, P, P, P, i32, i64, i32, i32, P, sz, P, P]
+    lib.gsb_bin_fill.argtypes = [P, P, P, P, i32, P, i64, i32, i32, P, sz, P, i64, P, P, P]
     lib.gsb_blend_forward.argtypes = [i32, i32, P, P, P, P, P, P, i64, P, i32, P, P, P, P]
     lib.gsb_blend_backward.argtypes = [i32, i32, P, P, P, P, P, P, i64, P, i32, P, P, P, P, P,
                                        P, P, P]
@@ -120,15 +122,18 @@ def gsb_bin_workspace_bytes(n: int, pair_capacity: int, W: int, H: int) -> int:
 
 
 def gsb_bin_count(means2d: int, radii: int, n: int, W: int, H: int, ws: int, ws_bytes: int,
-                  n_pairs_dev: int, stream: int = 0) -> None:
-    _check(load().gsb_bin_count(means2d, radii, n, W, H, ws, ws_bytes, n_pairs_dev, stream))
+                  n_pairs_dev: int, stream: int = 0, conics: int = 0, opacity: int = 0,
+                  mode: int = 0) -> None:
+    _check(load().gsb_bin_count(means2d, radii, conics, opacity, mode, n, W, H, ws, ws_bytes,
+                                n_pairs_dev, stream))
 
 
 def gsb_bin_fill(means2d: int, radii: int, depths: int, n: int, W: int, H: int, ws: int,
                  ws_bytes: int, point_list: int, pair_capacity: int, ranges: int,
-                 status_dev: int, stream: int = 0) -> None:
-    _check(load().gsb_bin_fill(means2d, radii, depths, n, W, H, ws, ws_bytes, point_list,
-                               pair_capacity, ranges, status_dev, stream))
+                 status_dev: int, stream: int = 0, conics: int = 0, opacity: int = 0,
+                 mode: int = 0) -> None:
+    _check(load().gsb_bin_fill(means2d, radii, conics, opacity, mode, depths, n, W, H, ws,
+                               ws_bytes, point_list, pair_capacity, ranges, status_dev, stream))
 
 
 def gsb_blend_forward(W: int, H: int, ranges: int, point_list: int, means2d: int, conics: int,

@@ -49,44 +49,65 @@ class BinWorkspace:
         return self.buf.data_ptr()
 
 
-def bin_count(means2d, radii, W: int, H: int, ws: BinWorkspace, stream=None) -> torch.Tensor:
-    """Device int64[1] pair count; the per-Gaussian offsets stay in ``ws``."""
+BIN_MODES = {"rect": _lib.GSB_BIN_RECT, "visible": _lib.GSB_BIN_VISIBLE}
+
+
+def _bin_mode(mode, conics, opacity):
+    """(mode code, conics ptr, opacity ptr) for the binning calls."""
+    code = BIN_MODES[mode] if isinstance(mode, str) else int(mode)
+    if code == _lib.GSB_BIN_RECT:
+        return code, 0, 0
+    if conics is None or opacity is None:
+        raise ValueError("the 'visible' binning mode needs conics and opacity")
+    _req(conics, torch.float32, "conics")
+    _req(opacity, torch.float32, "opacity")
+    return code, conics.data_ptr(), opacity.data_ptr()
+
+
+def bin_count(means2d, radii, W: int, H: int, ws: BinWorkspace, stream=None, conics=None,
+              opacity=None, mode="rect") -> torch.Tensor:
+    """Device int64[1] pair count; the per-Gaussian offsets stay in ``ws``. ``mode``: "rect" (the
+    3-sigma square) or "visible" (only tiles where alpha can reach 1/255; needs conics, opacity)."""
     n = radii.shape[0]
     _req(means2d, torch.float32, "means2d")
     _req(radii, torch.int32, "radii")
+    code, cp, op = _bin_mode(mode, conics, opacity)
     n_pairs = torch.empty(1, dtype=torch.int64, device=means2d.device)
     _lib.gsb_bin_count(means2d.data_ptr(), radii.data_ptr(), n, W, H, ws.ptr(), ws.nbytes,
-                       n_pairs.data_ptr(), _stream(stream))
+                       n_pairs.data_ptr(), _stream(stream), cp, op, code)
     return n_pairs
 
 
 def bin_fill(means2d, radii, depths, W: int, H: int, ws: BinWorkspace, point_list, ranges,
-             stream=None) -> torch.Tensor:
-    """Fills point_list (i32[capacity]) and ranges (i32[gx*gy][2]); returns the device status."""
+             stream=None, conics=None, opacity=None, mode="rect") -> torch.Tensor:
+    """Fills point_list (i32[capacity]) and ranges (i32[gx*gy][2]); returns the device status.
+    ``mode`` (and conics/opacity) must be those of the preceding bin_count."""
     n = radii.shape[0]
     _req(depths, torch.float32, "depths")
     _req(point_list, torch.int32, "point_list")
     _req(ranges, torch.int32, "ranges")
+    code, cp, op = _bin_mode(mode, conics, opacity)
     status = torch.empty(1, dtype=torch.int32, device=means2d.device)
     _lib.gsb_bin_fill(means2d.data_ptr(), radii.data_ptr(), depths.data_ptr(), n, W, H, ws.ptr(),
                       ws.nbytes, point_list.data_ptr(), point_list.numel(), ranges.data_ptr(),
-                      status.data_ptr(), _stream(stream))
+                      status.data_ptr(), _stream(stream), cp, op, code)
     return status
 
 
-def bin_tiles(means2d, radii, depths, W: int, H: int, stream=None):
+def bin_tiles(means2d, radii, depths, W: int, H: int, stream=None, conics=None, opacity=None,
+              mode="rect"):
     """Count, then fill with an exactly sized list. Returns (point_list i32[P], ranges
     i32[gx*gy][2]). Synchronises once to read the pair count."""
     n = radii.shape[0]
     ws0 = BinWorkspace(n, 0, W, H, device=means2d.device)
-    n_pairs = int(bin_count(means2d, radii, W, H, ws0, stream).item())
+    n_pairs = int(bin_count(means2d, radii, W, H, ws0, stream, conics, opacity, mode).item())
     ws = BinWorkspace(n, n_pairs, W, H, device=means2d.device)
     ws.buf[: ws0.nbytes].copy_(ws0.buf)          # per-Gaussian offsets from the count
     gx, gy = grid(W, H)
     point_list = torch.empty(max(n_pairs, 1), dtype=torch.int32, device=means2d.device)
     ranges = torch.empty((gx * gy, 2), dtype=torch.int32, device=means2d.device)
     bin_fill(means2d, radii, depths, W, H, ws, point_list[:n_pairs] if n_pairs else point_list[:0],
-             ranges, stream)
+             ranges, stream, conics, opacity, mode)
     return point_list[:n_pairs], ranges
 
 
@@ -149,8 +170,9 @@ class BatchedViews:
     """
 
     def __init__(self, scenes, prec="fp16", tuning=None, bg=(0.0, 0.0, 0.0),
-                 capacity_slack: float = 1.0, stream=None):
+                 capacity_slack: float = 1.0, stream=None, bin_mode="rect"):
         self.prec = prec_code(prec)
+        self.bin_mode = bin_mode
         self.bg = tuple(float(v) for v in bg)
         self.views = []
         for sc in scenes:
@@ -158,7 +180,8 @@ class BatchedViews:
             n = sc["radii"].shape[0]
             dev = sc["means2d"].device
             ws0 = BinWorkspace(n, 0, W, H, device=dev)
-            pairs = int(bin_count(sc["means2d"], sc["radii"], W, H, ws0, stream).item())
+            pairs = int(bin_count(sc["means2d"], sc["radii"], W, H, ws0, stream, sc["conics"],
+                                  sc["opacity"], bin_mode).item())
             cap = max(1, int(pairs * capacity_slack))
             gx, gy = grid(W, H)
             v = dict(sc)
@@ -212,12 +235,13 @@ class BatchedViews:
         for v in self.views:
             W, H = v["width"], v["height"]
             ws = v["ws"]
+            code, cp, op = _bin_mode(self.bin_mode, v["conics"], v["opacity"])
             _lib.gsb_bin_count(v["means2d"].data_ptr(), v["radii"].data_ptr(), v["n"], W, H,
-                               ws.ptr(), ws.nbytes, v["n_pairs"].data_ptr(), s)
+                               ws.ptr(), ws.nbytes, v["n_pairs"].data_ptr(), s, cp, op, code)
             _lib.gsb_bin_fill(v["means2d"].data_ptr(), v["radii"].data_ptr(),
                               v["depths"].data_ptr(), v["n"], W, H, ws.ptr(), ws.nbytes,
                               v["point_list"].data_ptr(), v["point_list"].numel(),
-                              v["ranges"].data_ptr(), v["status"].data_ptr(), s)
+                              v["ranges"].data_ptr(), v["status"].data_ptr(), s, cp, op, code)
 
     def forward(self, stream=None):
         _lib.gsb_blend_batched_forward(self.plan, _stream(stream))

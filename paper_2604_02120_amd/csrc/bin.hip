@@ -245,14 +245,134 @@ __device__ inline Rect tile_rect(float x, float y, int32_t r, int32_t gx, int32_
     return R;
 }
 
+// ------------------------------------------------------------------------------- mode 1
+// Binning mode 1 keeps a pair (tile, Gaussian) of the 3-sigma rectangle only when the Gaussian can
+// reach alpha >= 1/255 on a pixel of the tile inside the image (opacity-aware extent, a tighter
+// binning; images and final T are unchanged because every dropped pair would be skipped):
+//   o >= fp32(1/255), and min over the tile's pixel rectangle of Q = d^T Sigma^-1 d <= theta,
+//   theta = 2 (e * ln2_up + (m - 1)) + 0.1 with 255 o = m 2^e, m in [1, 2)
+// (an upper bound of 2 ln(255 o) without a logarithm, plus a margin far above any exponent error
+// of the blend). The minimum of Q over the rectangle of d = (x - px, y - py) is 0 if the rectangle
+// contains 0, else it lies on an edge: a 1D quadratic minimised inside the edge or at an end.
+// Division-free double-precision tests in a fixed order with contraction off: the decision is
+// reproducible bit for bit by any implementation taking the same steps.
+constexpr double kLn2Up = 0x1.62e42fefa39fp-1;   // the double just above ln 2
+constexpr double kCullMargin = 0.1;
+
+__device__ inline double vis_theta(double o) {
+#pragma clang fp contract(off)
+    const double z = 255.0 * o;                   // exact: o is an fp32 value
+    const unsigned long long bits = (unsigned long long)__double_as_longlong(z);
+    const long long e = (long long)((bits >> 52) & 0x7ffull) - 1023;
+    const double m = __longlong_as_double(
+        (long long)((bits & 0x000fffffffffffffull) | 0x3ff0000000000000ull));
+    const double t1 = double(e) * kLn2Up;
+    const double t2 = m - 1.0;
+    return 2.0 * (t1 + t2) + kCullMargin;
+}
+
+// one edge: u fixed at a, v in [c, d]; Q = P a^2 + 2 B a v + R v^2
+__device__ inline bool vis_edge(double P, double R, double B, double det, double theta, double a,
+                                double c, double d) {
+#pragma clang fp contract(off)
+    const double ba = B * a;
+    const double nba = -ba;
+    if (c * R <= nba && nba <= d * R) {           // interior minimum a^2 det / R
+        const double lhs = (a * a) * det;
+        const double rhs = theta * R;
+        return lhs <= rhs;
+    }
+    const double pa2 = P * (a * a);
+    const double qc = (pa2 + (2.0 * ba) * c) + R * (c * c);
+    const double qd = (pa2 + (2.0 * ba) * d) + R * (d * d);
+    return qc <= theta || qd <= theta;
+}
+
+struct GaussVis {
+    double x, y, A, B, C, det, theta;
+    bool live;                                    // o >= fp32(1/255)
+};
+
+__device__ inline GaussVis vis_setup(float2 m, const float *conic, float o) {
+#pragma clang fp contract(off)
+    GaussVis g;
+    g.x = m.x; g.y = m.y;
+    g.A = conic[0]; g.B = conic[1]; g.C = conic[2];
+    g.live = o >= 1.0f / 255.0f;
+    g.det = g.A * g.C - g.B * g.B;
+    g.theta = vis_theta(double(o));
+    return g;
+}
+
+__device__ inline bool tile_visible(const GaussVis &g, int32_t tx, int32_t ty, int32_t W,
+                                    int32_t H) {
+#pragma clang fp contract(off)
+    if (!g.live) return false;
+    const int32_t px1 = tx * kTile + kTile - 1 < W - 1 ? tx * kTile + kTile - 1 : W - 1;
+    const int32_t py1 = ty * kTile + kTile - 1 < H - 1 ? ty * kTile + kTile - 1 : H - 1;
+    const double dxl = g.x - double(px1), dxh = g.x - double(tx * kTile);
+    const double dyl = g.y - double(py1), dyh = g.y - double(ty * kTile);
+    if (dxl <= 0.0 && 0.0 <= dxh && dyl <= 0.0 && 0.0 <= dyh) return true;
+    return vis_edge(g.A, g.C, g.B, g.det, g.theta, dxl, dyl, dyh) ||
+           vis_edge(g.A, g.C, g.B, g.det, g.theta, dxh, dyl, dyh) ||
+           vis_edge(g.C, g.A, g.B, g.det, g.theta, dyl, dxl, dxh) ||
+           vis_edge(g.C, g.A, g.B, g.det, g.theta, dyh, dxl, dxh);
+}
+
+// Pair counts per Gaussian. Mode 0: the rectangle's area. Mode 1: its visible tiles; a thread
+// counts its own rectangle when small, larger ones are counted by the whole wavefront together.
 __global__ __launch_bounds__(256) void k_bin_count(const float2 *means, const int32_t *radii,
-                                                   int64_t n, int32_t gx, int32_t gy,
+                                                   const float *conics, const float *opac,
+                                                   int32_t mode, int64_t n, int32_t gx,
+                                                   int32_t gy, int32_t W, int32_t H,
                                                    unsigned long long *counts) {
     const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    const float2 m = means[i];
-    const Rect R = tile_rect(m.x, m.y, radii[i], gx, gy);
-    counts[i] = (unsigned long long)(R.tx1 - R.tx0) * (unsigned long long)(R.ty1 - R.ty0);
+    if (mode == 0) {
+        if (i >= n) return;
+        const float2 m = means[i];
+        const Rect R = tile_rect(m.x, m.y, radii[i], gx, gy);
+        counts[i] = (unsigned long long)(R.tx1 - R.tx0) * (unsigned long long)(R.ty1 - R.ty0);
+        return;
+    }
+    if (int64_t(blockIdx.x) * blockDim.x >= n) return;   // block-uniform
+    const bool valid = i < n;
+    Rect R{0, 0, 0, 0};
+    GaussVis g{};
+    if (valid) {
+        const float2 m = means[i];
+        R = tile_rect(m.x, m.y, radii[i], gx, gy);
+        g = vis_setup(m, conics + 3 * i, opac[i]);
+    }
+    const int w = R.tx1 - R.tx0;
+    const int area = w * (R.ty1 - R.ty0);
+    const bool big = area > kBigRect;
+    unsigned long long cnt = 0;
+    if (!big && g.live)
+        for (int32_t ty = R.ty0; ty < R.ty1; ++ty)
+            for (int32_t tx = R.tx0; tx < R.tx1; ++tx) cnt += tile_visible(g, tx, ty, W, H);
+    unsigned long long todo = __ballot(big && g.live);
+    const int lane = threadIdx.x & 63;
+    while (todo) {
+        const int src = __ffsll((long long)todo) - 1;
+        todo &= todo - 1;
+        GaussVis sg;
+        sg.x = __shfl(g.x, src); sg.y = __shfl(g.y, src);
+        sg.A = __shfl(g.A, src); sg.B = __shfl(g.B, src); sg.C = __shfl(g.C, src);
+        sg.det = __shfl(g.det, src); sg.theta = __shfl(g.theta, src);
+        sg.live = true;
+        const int stx0 = __builtin_amdgcn_readlane(R.tx0, src);
+        const int sty0 = __builtin_amdgcn_readlane(R.ty0, src);
+        const int sw = __builtin_amdgcn_readlane(w, src);
+        const int sarea = __builtin_amdgcn_readlane(area, src);
+        unsigned long long total = 0;
+        for (int k0 = 0; k0 < sarea; k0 += 64) {
+            const int k = k0 + lane;
+            const bool v = k < sarea && tile_visible(sg, stx0 + k % sw, sty0 + k / sw, W, H);
+            total += __popcll(__ballot(v));
+        }
+        if (lane == src) cnt = total;
+    }
+    if (valid) counts[i] = cnt;
 }
 
 // Depth keys: the float's bits, made order-preserving for any sign (a no-op flip of the sign bit
@@ -275,6 +395,7 @@ struct PairSink {
     unsigned long long seg0, cap;    // first output index of the block, capacity
     __device__ inline void put(unsigned long long o, uint32_t key, uint32_t val) const {
         if (skey) {
+            if (o - seg0 >= (unsigned long long)kFillStage) return;   // never for consistent counts
             skey[o - seg0] = key;
             sval[o - seg0] = val;
         } else if (o < cap) {
@@ -285,6 +406,8 @@ struct PairSink {
 };
 
 __global__ __launch_bounds__(256) void k_bin_fill(const float2 *means, const int32_t *radii,
+                                                  const float *conics, const float *opac,
+                                                  int32_t mode, int32_t W, int32_t H,
                                                   const uint32_t *sorted_idx, int64_t n,
                                                   int32_t gx, int32_t gy,
                                                   const unsigned long long *offs,
@@ -303,11 +426,14 @@ __global__ __launch_bounds__(256) void k_bin_fill(const float2 *means, const int
     const bool valid = j < n;
     const uint32_t i = valid ? sorted_idx[j] : 0u;
     Rect R{0, 0, 0, 0};
+    GaussVis g{};
     unsigned long long base = 0;
     if (valid) {
         const float2 m = means[i];
         R = tile_rect(m.x, m.y, radii[i], gx, gy);
         base = offs[j];
+        if (mode != 0) g = vis_setup(m, conics + 3 * int64_t(i), opac[i]);
+        if (mode != 0 && !g.live) R = Rect{0, 0, 0, 0};   // emits nothing
     }
     // the block's segment: [first rank's offset, last rank's offset + its count)
     const int64_t jl = (j0 + int64_t(blockDim.x) < n ? j0 + int64_t(blockDim.x) : n) - 1;
@@ -323,11 +449,14 @@ __global__ __launch_bounds__(256) void k_bin_fill(const float2 *means, const int
     if (!big) {
         unsigned long long o = base;
         for (int32_t ty = R.ty0; ty < R.ty1; ++ty)
-            for (int32_t tx = R.tx0; tx < R.tx1; ++tx, ++o)
-                sink.put(o, uint32_t(int64_t(ty) * gx + tx), i);
+            for (int32_t tx = R.tx0; tx < R.tx1; ++tx) {
+                if (mode != 0 && !tile_visible(g, tx, ty, W, H)) continue;
+                sink.put(o++, uint32_t(int64_t(ty) * gx + tx), i);
+            }
     }
     unsigned long long todo = __ballot(big);
     const int lane = threadIdx.x & 63;
+    const unsigned long long lt_mask = (1ull << lane) - 1ull;
     while (todo) {
         const int src = __ffsll((long long)todo) - 1;
         todo &= todo - 1;
@@ -339,9 +468,26 @@ __global__ __launch_bounds__(256) void k_bin_fill(const float2 *means, const int
         const unsigned long long sbase =
             ((unsigned long long)(uint32_t)__builtin_amdgcn_readlane(uint32_t(base >> 32), src) << 32) |
             (uint32_t)__builtin_amdgcn_readlane(uint32_t(base), src);
-        for (int k = lane; k < sarea; k += 64) {
-            const int ty = sty0 + k / sw, tx = stx0 + k % sw;
-            sink.put(sbase + k, uint32_t(int64_t(ty) * gx + tx), si);
+        if (mode == 0) {
+            for (int k = lane; k < sarea; k += 64) {
+                const int ty = sty0 + k / sw, tx = stx0 + k % sw;
+                sink.put(sbase + k, uint32_t(int64_t(ty) * gx + tx), si);
+            }
+        } else {
+            GaussVis sg;
+            sg.x = __shfl(g.x, src); sg.y = __shfl(g.y, src);
+            sg.A = __shfl(g.A, src); sg.B = __shfl(g.B, src); sg.C = __shfl(g.C, src);
+            sg.det = __shfl(g.det, src); sg.theta = __shfl(g.theta, src);
+            sg.live = true;
+            unsigned long long o = sbase;       // visible tiles in row-major order
+            for (int k0 = 0; k0 < sarea; k0 += 64) {
+                const int k = k0 + lane;
+                const int ty = sty0 + k / sw, tx = stx0 + k % sw;
+                const bool v = k < sarea && tile_visible(sg, tx, ty, W, H);
+                const unsigned long long vb = __ballot(v);
+                if (v) sink.put(o + __popcll(vb & lt_mask), uint32_t(int64_t(ty) * gx + tx), si);
+                o += __popcll(vb);
+            }
         }
     }
     if (staged) {   // block-uniform
@@ -673,8 +819,9 @@ int64_t bin_max_gaussians() { return kScanMaxLen; }
 // the tile sort scans [256][blocks] histograms with the single-top-level scan
 int64_t bin_max_pairs() { return int64_t(kScanMaxLen / kRadix) * kSortTile; }
 
-gsb_status bin_count(const float *means2d, const int32_t *radii, int64_t n, int32_t W, int32_t H,
-                     void *ws, int64_t *n_pairs_dev, hipStream_t s) {
+gsb_status bin_count(const float *means2d, const int32_t *radii, const float *conics,
+                     const float *opacity, int32_t mode, int64_t n, int32_t W, int32_t H, void *ws,
+                     int64_t *n_pairs_dev, hipStream_t s) {
     const Layout L = layout(n, 0);
     auto *hdr = at<BinHeader>(ws, L.hdr);
     auto *counts = at<unsigned long long>(ws, L.counts);
@@ -682,16 +829,18 @@ gsb_status bin_count(const float *means2d, const int32_t *radii, int64_t n, int3
     const int32_t gx = int32_t(grid_x(W)), gy = int32_t(grid_y(H));
     if (n > 0)
         k_bin_count<<<dim3(unsigned((n + 255) / 256)), 256, 0, s>>>(
-            reinterpret_cast<const float2 *>(means2d), radii, n, gx, gy, counts);
+            reinterpret_cast<const float2 *>(means2d), radii, conics, opacity, mode, n, gx, gy, W,
+            H, counts);
     // the total only: offsets are formed in depth order by bin_fill
     launch_scan<unsigned long long>(counts, n, partial, &hdr->total,
                                     reinterpret_cast<long long *>(n_pairs_dev), s, false);
     return check_launch("bin_count");
 }
 
-gsb_status bin_fill(const float *means2d, const int32_t *radii, const float *depths, int64_t n,
-                    int32_t W, int32_t H, void *ws, uint32_t *point_list, int64_t cap,
-                    uint32_t *ranges, int32_t *status_dev, hipStream_t s) {
+gsb_status bin_fill(const float *means2d, const int32_t *radii, const float *conics,
+                    const float *opacity, int32_t mode, const float *depths, int64_t n, int32_t W,
+                    int32_t H, void *ws, uint32_t *point_list, int64_t cap, uint32_t *ranges,
+                    int32_t *status_dev, hipStream_t s) {
     const Layout L = layout(n, cap);
     auto *hdr = at<BinHeader>(ws, L.hdr);
     auto *counts = at<unsigned long long>(ws, L.counts);
@@ -722,8 +871,9 @@ gsb_status bin_fill(const float *means2d, const int32_t *radii, const float *dep
     // the last pass must land the values in point_list
     uint32_t *v_first = (tp % 2 == 0) ? point_list : vtmp;
     uint32_t *v_second = (tp % 2 == 0) ? vtmp : point_list;
-    k_bin_fill<<<gn, 256, 0, s>>>(reinterpret_cast<const float2 *>(means2d), radii, sorted_idx, n,
-                                  gx, gy, offs, counts, hdr, cap, tka, v_first, status_dev);
+    k_bin_fill<<<gn, 256, 0, s>>>(reinterpret_cast<const float2 *>(means2d), radii, conics, opacity,
+                                  mode, W, H, sorted_idx, n, gx, gy, offs, counts, hdr, cap, tka,
+                                  v_first, status_dev);
     // 3. stable sort of the pairs on the tile id
     sort_tiles(tka, tkb, v_first, v_second, &hdr->pairs, cap, tile_bits, sortbuf, partial32,
                status_dev, s);

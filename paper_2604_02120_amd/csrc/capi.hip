@@ -116,21 +116,36 @@ gsb_status gsb_bin_workspace_bytes(int64_t n, int64_t pair_capacity, int32_t W, 
     return GSB_OK;
 }
 
-gsb_status gsb_bin_count(const float *means2d, const int32_t *radii, int64_t n, int32_t W,
+namespace {
+gsb_status check_bin_mode(gsb_bin_mode mode, int64_t n, const float *conics, const float *opacity) {
+    GSB_REQUIRE(mode == GSB_BIN_RECT || mode == GSB_BIN_VISIBLE, "unknown binning mode %d", int(mode));
+    if (mode == GSB_BIN_VISIBLE && n > 0) {
+        GSB_REQUIRE(conics && opacity, "binning mode 1 needs non-null conics and opacity");
+        GSB_REQUIRE(aligned(conics, 4) && aligned(opacity, 4), "conics and opacity must be 4-byte aligned");
+    }
+    return GSB_OK;
+}
+}  // namespace
+
+gsb_status gsb_bin_count(const float *means2d, const int32_t *radii, const float *conics,
+                         const float *opacity, gsb_bin_mode mode, int64_t n, int32_t W,
                          int32_t H, void *ws, size_t ws_bytes, int64_t *n_pairs_dev,
                          void *stream) {
     size_t need = 0;
     GSB_TRY(gsb_bin_workspace_bytes(n, 0, W, H, &need));
     GSB_REQUIRE(n == 0 || (means2d && radii), "means2d and radii must be non-null");
     GSB_REQUIRE(aligned(means2d, 8), "means2d must be 8-byte aligned");
+    GSB_TRY(check_bin_mode(mode, n, conics, opacity));
     GSB_REQUIRE(ws != nullptr && aligned(ws, 256), "workspace must be non-null and 256-byte aligned");
     GSB_REQUIRE(ws_bytes >= need, "workspace of %zu bytes is smaller than the %zu needed", ws_bytes, need);
     GSB_REQUIRE(n_pairs_dev != nullptr && aligned(n_pairs_dev, 8), "n_pairs_dev must be a non-null, 8-byte aligned device pointer");
     GSB_TRY(check_device());
-    return bin_count(means2d, radii, n, W, H, ws, n_pairs_dev, static_cast<hipStream_t>(stream));
+    return bin_count(means2d, radii, conics, opacity, mode, n, W, H, ws, n_pairs_dev,
+                     static_cast<hipStream_t>(stream));
 }
 
-gsb_status gsb_bin_fill(const float *means2d, const int32_t *radii, const float *depths, int64_t n,
+gsb_status gsb_bin_fill(const float *means2d, const int32_t *radii, const float *conics,
+                        const float *opacity, gsb_bin_mode mode, const float *depths, int64_t n,
                         int32_t W, int32_t H, void *ws, size_t ws_bytes, uint32_t *point_list,
                         int64_t pair_capacity, uint32_t *ranges, int32_t *status_dev,
                         void *stream) {
@@ -138,13 +153,14 @@ gsb_status gsb_bin_fill(const float *means2d, const int32_t *radii, const float 
     GSB_TRY(gsb_bin_workspace_bytes(n, pair_capacity, W, H, &need));
     GSB_REQUIRE(n == 0 || (means2d && radii && depths), "means2d, radii and depths must be non-null");
     GSB_REQUIRE(aligned(means2d, 8), "means2d must be 8-byte aligned");
+    GSB_TRY(check_bin_mode(mode, n, conics, opacity));
     GSB_REQUIRE(ws != nullptr && aligned(ws, 256), "workspace must be non-null and 256-byte aligned");
     GSB_REQUIRE(ws_bytes >= need, "workspace of %zu bytes is smaller than the %zu needed", ws_bytes, need);
     GSB_REQUIRE(pair_capacity == 0 || point_list != nullptr, "point_list must be non-null");
     GSB_REQUIRE(ranges != nullptr && status_dev != nullptr, "ranges and status_dev must be non-null");
     GSB_TRY(check_device());
-    return bin_fill(means2d, radii, depths, n, W, H, ws, point_list, pair_capacity, ranges,
-                    status_dev, static_cast<hipStream_t>(stream));
+    return bin_fill(means2d, radii, conics, opacity, mode, depths, n, W, H, ws, point_list,
+                    pair_capacity, ranges, status_dev, static_cast<hipStream_t>(stream));
 }
 
 gsb_status gsb_blend_forward(int32_t W, int32_t H, const uint32_t *ranges,

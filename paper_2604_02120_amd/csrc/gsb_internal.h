@@ -36,10 +36,12 @@ __device__ inline int64_t xcd_tile(int64_t block, int64_t n_tiles) {
 
 // ---- binning (bin.hip)
 size_t bin_workspace_bytes(int64_t n, int64_t pair_capacity, int64_t n_tiles);
-gsb_status bin_count(const float *means2d, const int32_t *radii, int64_t n, int32_t W, int32_t H,
-                     void *ws, int64_t *n_pairs_dev, hipStream_t s);
-gsb_status bin_fill(const float *means2d, const int32_t *radii, const float *depths, int64_t n,
-                    int32_t W, int32_t H, void *ws, uint32_t *point_list, int64_t pair_capacity,
+gsb_status bin_count(const float *means2d, const int32_t *radii, const float *conics,
+                     const float *opacity, int32_t mode, int64_t n, int32_t W, int32_t H, void *ws,
+                     int64_t *n_pairs_dev, hipStream_t s);
+gsb_status bin_fill(const float *means2d, const int32_t *radii, const float *conics,
+                    const float *opacity, int32_t mode, const float *depths, int64_t n, int32_t W,
+                    int32_t H, void *ws, uint32_t *point_list, int64_t pair_capacity,
                     uint32_t *ranges, int32_t *status_dev, hipStream_t s);
 
 // ---- blending (blend.hip)

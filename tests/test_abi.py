@@ -36,7 +36,7 @@ def test_library_exports_every_declared_symbol():
 
 
 def test_abi_version():
-    assert _lib.gsb_abi_version() == 1
+    assert _lib.gsb_abi_version() == 2
 
 
 def test_no_oracle_in_library():
@@ -135,3 +135,20 @@ def test_plan_validation_before_device():
         _lib.gsb_blend_batched_forward(0)
     assert "plan" in str(e.value)
     _lib.gsb_plan_destroy(0)     # NULL is allowed
+
+
+def test_bin_mode_validation_before_device():
+    ok = 256
+    need = _lib.gsb_bin_workspace_bytes(100, 0, 32, 32)
+    with pytest.raises(_lib.GsbError) as e:
+        _lib.gsb_bin_count(ok, ok, 100, 32, 32, ok, need, ok, mode=7)
+    assert e.value.status == _lib.GSB_ERR_INVALID and "binning mode" in str(e.value)
+    with pytest.raises(_lib.GsbError) as e:
+        _lib.gsb_bin_count(ok, ok, 100, 32, 32, ok, need, ok, conics=0, opacity=ok,
+                           mode=_lib.GSB_BIN_VISIBLE)
+    assert "conics and opacity" in str(e.value)
+    need2 = _lib.gsb_bin_workspace_bytes(100, 50, 32, 32)
+    with pytest.raises(_lib.GsbError) as e:
+        _lib.gsb_bin_fill(ok, ok, ok, 100, 32, 32, ok, need2, ok, 50, ok, ok, conics=ok + 2,
+                          opacity=ok, mode=_lib.GSB_BIN_VISIBLE)
+    assert "aligned" in str(e.value)

@@ -156,6 +156,14 @@ def test_forward_c2_full_size(gpu):
     pl, rg = api.bin_tiles(sd["means2d"], sd["radii"], sd["depths"], 1920, 1080)
     np.testing.assert_array_equal(rg.cpu().numpy().astype(np.uint32), ref["ranges"])
     np.testing.assert_array_equal(pl.cpu().numpy().astype(np.uint32), ref["point_list"])
+    say("[fwd-full] C2 visible-tile binning")
+    pl1_ref, rg1_ref = oracle.bin_tiles(s["means2d"], s["radii"], s["depths"], 1920, 1080,
+                                        s["conics"], s["opacity"], oracle.BIN_VISIBLE)
+    pl1, rg1 = api.bin_tiles(sd["means2d"], sd["radii"], sd["depths"], 1920, 1080,
+                             conics=sd["conics"], opacity=sd["opacity"], mode="visible")
+    np.testing.assert_array_equal(rg1.cpu().numpy().astype(np.uint32), rg1_ref)
+    np.testing.assert_array_equal(pl1.cpu().numpy().astype(np.uint32), pl1_ref)
+    say(f"  pairs {len(ref['point_list'])} -> {len(pl1_ref)}")
     for prec in PRECS:
         say(f"[fwd-full] C2 {prec}")
         img, T, last = gpu_forward(sd, pl, rg, prec)
@@ -305,3 +313,74 @@ def test_c5_4k_sampled_tiles(gpu):
             e = normwise(v.cpu().numpy().astype(np.float64), gref[k])
             say(f"  bwd {prec} {k}: {e:.3e}")
             assert e <= bound, (prec, k, e)
+
+
+# ----------------------------------------------------------------------------- binning mode 1
+def needle_scene(seed=61, n=400, W=120, H=72):
+    """Strongly anisotropic Gaussians at all angles, opacities down to 1/255."""
+    rng = np.random.default_rng(seed)
+    s = gsinputs.make_scene("C1", seed=seed, n=n, width=W, height=H)
+    th = rng.uniform(0, np.pi, n)
+    s1, s2 = rng.uniform(0.5, 1.0, n), rng.uniform(4.0, 32.0, n)
+    s["conics"] = gsinputs.conic_from_axes(th, s1, s2).astype(np.float32)
+    s["radii"] = np.ceil(3.0 * np.maximum(s1, s2)).astype(np.int32)
+    s["opacity"] = rng.uniform(1.0 / 255.0, 0.99, n).astype(np.float32)
+    return s
+
+
+VIS = dict(SCENES, needles=needle_scene())
+
+
+def gpu_bins(sd, mode):
+    pl, rg = api.bin_tiles(sd["means2d"], sd["radii"], sd["depths"], sd["width"], sd["height"],
+                           conics=sd["conics"], opacity=sd["opacity"], mode=mode)
+    torch.cuda.synchronize()
+    return pl, rg
+
+
+@pytest.mark.parametrize("name", list(VIS))
+def test_bin_visible_bitexact(gpu, name):
+    """Binning mode 1 (tiles where alpha can reach 1/255) equals the oracle's bit for bit."""
+    s = VIS[name]
+    W, H = s["width"], s["height"]
+    say(f"[bin-visible] {name} {W}x{H} n={len(s['radii'])}")
+    pl_ref, rg_ref = oracle.bin_tiles(s["means2d"], s["radii"], s["depths"], W, H, s["conics"],
+                                      s["opacity"], oracle.BIN_VISIBLE)
+    sd = upload(s, gpu)
+    pl, rg = gpu_bins(sd, "visible")
+    np.testing.assert_array_equal(rg.cpu().numpy().astype(np.uint32), rg_ref)
+    np.testing.assert_array_equal(pl.cpu().numpy().astype(np.uint32), pl_ref)
+
+
+@pytest.mark.parametrize("prec", PRECS)
+@pytest.mark.parametrize("name", ["lognormal", "needles"])
+def test_visible_binning_same_blend(gpu, prec, name):
+    """Forward and backward over mode-1 lists reproduce those over the 3-sigma lists: image and
+    final T bit for bit, the same last Gaussian per pixel, gradients up to atomic order."""
+    s = VIS[name]
+    W, H = s["width"], s["height"]
+    sd = upload(s, gpu)
+    bg = (0.1, 0.3, 0.2)
+    g = torch.from_numpy(gsinputs.make_dloss(W, H, 77)).to(gpu)
+    out = {}
+    for mode in ("rect", "visible"):
+        pl, rg = gpu_bins(sd, mode)
+        img, T, last = api.blend_forward(sd["means2d"], sd["conics"], sd["opacity"], sd["colors"],
+                                         rg, pl, W, H, bg, prec)
+        grads = api.blend_backward(sd["means2d"], sd["conics"], sd["opacity"], sd["colors"], rg,
+                                   pl, W, H, T, last, g, bg, prec)
+        torch.cuda.synchronize()
+        gx, _ = oracle.grid(W, H)
+        lastc = last.cpu().numpy()
+        rgn = rg.cpu().numpy().astype(np.int64)
+        pln = pl.cpu().numpy().astype(np.int64)
+        tile = (np.arange(H)[:, None] // 16) * gx + np.arange(W)[None, :] // 16
+        who = np.where(lastc > 0, pln[np.clip(rgn[tile, 0] + lastc - 1, 0, max(len(pln) - 1, 0))], -1)
+        out[mode] = (img.cpu().numpy(), T.cpu().numpy(), who,
+                     [x.cpu().numpy().astype(np.float64) for x in grads], len(pln))
+    a, b = out["rect"], out["visible"]
+    say(f"  {name} {prec}: pairs {a[4]} -> {b[4]}")
+    assert b[4] < a[4]
+    assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1]) and np.array_equal(a[2], b[2])
+    for ga, gb in zip(a[3], b[3]):
+        assert normwise(gb, ga) <= 1e-5
