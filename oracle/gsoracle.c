@@ -96,9 +96,12 @@ static void tile_rect(double x, double y, int32_t r, int64_t gx, int64_t gy,
  * exponent error is far below 0.05 (every path here) skips it anyway: images and final T are
  * unchanged; only positions within the lists (last_contrib) move.
  * Q's minimum over a rectangle of d = (x - px, y - py) is 0 when the rectangle contains d = 0,
- * else it lies on one of the four edges, each a 1D quadratic minimised at an interior point or at
- * an end. Every test is written without division, with this fixed sequence of IEEE double
- * operations (no contraction), so the decision is reproducible bit for bit. */
+ * else it lies on an edge that faces d = 0 (an edge whose line separates the rectangle from 0: at
+ * a minimiser p on an edge with outward normal n, -grad Q(p) = -2 Sigma^-1 p is a non-negative
+ * multiple of n, so n.p = -c n^T Sigma n < 0), each a 1D quadratic minimised at an interior point
+ * or at an end. Only those (at most two) edges are tested. Every test is written without
+ * division, with this fixed sequence of IEEE double operations (no contraction), so the decision
+ * is reproducible bit for bit. */
 #define ORC_LN2_UP 0x1.62e42fefa39fp-1
 #define ORC_CULL_MARGIN 0.1
 
@@ -142,8 +145,12 @@ static int tile_visible(double x, double y, const double *conic, double o, int64
     if (dxl <= 0.0 && 0.0 <= dxh && dyl <= 0.0 && 0.0 <= dyh) return 1;
     const double theta = vis_theta(o);
     const double det = A * C - B * B;
-    return vis_edge(A, C, B, det, theta, dxl, dyl, dyh) || vis_edge(A, C, B, det, theta, dxh, dyl, dyh) ||
-           vis_edge(C, A, B, det, theta, dyl, dxl, dxh) || vis_edge(C, A, B, det, theta, dyh, dxl, dxh);
+    /* the x-edge facing 0 (if 0 is left or right of the rectangle), then the y-edge */
+    if (dxl > 0.0 && vis_edge(A, C, B, det, theta, dxl, dyl, dyh)) return 1;
+    if (dxh < 0.0 && vis_edge(A, C, B, det, theta, dxh, dyl, dyh)) return 1;
+    if (dyl > 0.0 && vis_edge(C, A, B, det, theta, dyl, dxl, dxh)) return 1;
+    if (dyh < 0.0 && vis_edge(C, A, B, det, theta, dyh, dxl, dxh)) return 1;
+    return 0;
 }
 
 /* whether pair (tile (tx, ty), Gaussian i) is emitted under `mode` (0: the 3-sigma rectangle alone) */

@@ -36,7 +36,8 @@ constexpr int kSortTile = kSortThreads * kSortItems;     // 4096 keys per block
 constexpr int kRadixBits = 8;
 constexpr int kRadix = 1 << kRadixBits;
 
-constexpr int kBigRect = 32;   // rectangles with more tiles are emitted by the whole wavefront
+constexpr int kBigRect = 32;   // mode 0: rectangles with more tiles are emitted by the whole wavefront
+
 
 struct BinHeader {
     unsigned long long total;     // pairs counted by bin_count
@@ -58,7 +59,7 @@ size_t align256(size_t b) { return (b + 255) & ~size_t(255); }
 
 struct Layout {
     // bin_count's part (depends on n only)
-    size_t hdr, counts, partials;
+    size_t hdr, counts, masks, partials;
     // bin_fill's part
     size_t sorts, dkey_a, dkey_b, dval_a, dval_b, offs, tkey_a, tkey_b, vals_tmp, sortbuf, end;
 };
@@ -71,6 +72,7 @@ Layout layout(int64_t n, int64_t cap) {
     size_t o = 0;
     L.hdr = o;       o += align256(sizeof(BinHeader));
     L.counts = o;    o += align256(sizeof(unsigned long long) * nn);
+    L.masks = o;     o += align256(sizeof(unsigned long long) * nn);
     L.partials = o;  o += align256(sizeof(unsigned long long) * kScanMaxBlocks);
     L.sorts = o;     o += align256(sizeof(SortState));
     L.dkey_a = o;    o += align256(sizeof(uint32_t) * nn);
@@ -290,6 +292,11 @@ __device__ inline bool vis_edge(double P, double R, double B, double det, double
 
 struct GaussVis {
     double x, y, A, B, C, det, theta;
+    // Shortcuts that settle most tiles with the same answer as the tests below: with d the point
+    // of the tile's rectangle nearest the mean, lmin |d|^2 <= min Q <= Q(d) <= lmax |d|^2 (lmin,
+    // lmax the eigenvalues of Sigma^-1). Beyond margins far above the tests' rounding:
+    //   |d|^2 > far  => invisible,   |d|^2 < near => visible.
+    double far2, near2;
     bool live;                                    // o >= fp32(1/255)
 };
 
@@ -301,6 +308,15 @@ __device__ inline GaussVis vis_setup(float2 m, const float *conic, float o) {
     g.live = o >= 1.0f / 255.0f;
     g.det = g.A * g.C - g.B * g.B;
     g.theta = vis_theta(double(o));
+    g.far2 = INFINITY;                            // no shortcut unless positive definite
+    g.near2 = -1.0;
+    if (g.A > 0.0 && g.det > 0.0) {
+        const double h = 0.5 * (g.A + g.C), r = sqrt(0.25 * (g.A - g.C) * (g.A - g.C) + g.B * g.B);
+        const double lmax = (h + r) * (1.0 + 1e-9);
+        const double lmin = (g.det / (h + r)) * (1.0 - 1e-9);
+        g.far2 = (g.theta + 1e-6 * (1.0 + g.theta)) / lmin;
+        g.near2 = (g.theta - 1e-6 * (1.0 + g.theta)) / lmax;
+    }
     return g;
 }
 
@@ -313,19 +329,106 @@ __device__ inline bool tile_visible(const GaussVis &g, int32_t tx, int32_t ty, i
     const double dxl = g.x - double(px1), dxh = g.x - double(tx * kTile);
     const double dyl = g.y - double(py1), dyh = g.y - double(ty * kTile);
     if (dxl <= 0.0 && 0.0 <= dxh && dyl <= 0.0 && 0.0 <= dyh) return true;
-    return vis_edge(g.A, g.C, g.B, g.det, g.theta, dxl, dyl, dyh) ||
-           vis_edge(g.A, g.C, g.B, g.det, g.theta, dxh, dyl, dyh) ||
-           vis_edge(g.C, g.A, g.B, g.det, g.theta, dyl, dxl, dxh) ||
-           vis_edge(g.C, g.A, g.B, g.det, g.theta, dyh, dxl, dxh);
+    const double cx = dxl > 0.0 ? dxl : (dxh < 0.0 ? dxh : 0.0);
+    const double cy = dyl > 0.0 ? dyl : (dyh < 0.0 ? dyh : 0.0);
+    const double d2 = cx * cx + cy * cy;
+    if (d2 > g.far2) return false;
+    if (d2 < g.near2) return true;
+    // only the edges facing the mean can hold the minimum (at most one in x, one in y)
+    if (dxl > 0.0 && vis_edge(g.A, g.C, g.B, g.det, g.theta, dxl, dyl, dyh)) return true;
+    if (dxh < 0.0 && vis_edge(g.A, g.C, g.B, g.det, g.theta, dxh, dyl, dyh)) return true;
+    if (dyl > 0.0 && vis_edge(g.C, g.A, g.B, g.det, g.theta, dyl, dxl, dxh)) return true;
+    if (dyh < 0.0 && vis_edge(g.C, g.A, g.B, g.det, g.theta, dyh, dxl, dxh)) return true;
+    return false;
 }
 
-// Pair counts per Gaussian. Mode 0: the rectangle's area. Mode 1: its visible tiles; a thread
-// counts its own rectangle when small, larger ones are counted by the whole wavefront together.
+// The candidate tiles of mode 1: the 3-sigma rectangle cut to the tiles that the bounding box of
+// {Q <= theta} (half-widths sqrt(theta C / det), sqrt(theta A / det), plus one pixel) can reach.
+// Every tile cut away has Q > theta on all its pixels by a wide margin, so the tests above would
+// reject it: the cut changes which tiles are tested, never a decision. Empty when o < 1/255.
+__device__ inline Rect cand_rect(const GaussVis &g, const Rect &R) {
+    if (!g.live) return Rect{0, 0, 0, 0};
+    if (!(g.A > 0.0 && g.C > 0.0 && g.det > 0.0)) return R;
+    const double hx = fmin(sqrt(g.theta * g.C / g.det) + 1.0, 1e8);
+    const double hy = fmin(sqrt(g.theta * g.A / g.det) + 1.0, 1e8);
+    Rect C = R;
+    const int64_t bx0 = int64_t(floor((g.x - hx - 15.0) / 16.0)), bx1 = int64_t(floor((g.x + hx) / 16.0)) + 1;
+    const int64_t by0 = int64_t(floor((g.y - hy - 15.0) / 16.0)), by1 = int64_t(floor((g.y + hy) / 16.0)) + 1;
+    if (bx0 > C.tx0) C.tx0 = int32_t(bx0 < C.tx1 ? bx0 : C.tx1);
+    if (bx1 < C.tx1) C.tx1 = int32_t(bx1 > C.tx0 ? bx1 : C.tx0);
+    if (by0 > C.ty0) C.ty0 = int32_t(by0 < C.ty1 ? by0 : C.ty1);
+    if (by1 < C.ty1) C.ty1 = int32_t(by1 > C.ty0 ? by1 : C.ty0);
+    return C;
+}
+
+// visible-tile masks: a Gaussian with at most this many candidates keeps its answer as one bit per
+// candidate (row-major), so that emission needs no second test
+constexpr uint32_t kMaskBits = 64;
+
+// ------------------------------------------------------------------------------- balanced pairs
+// The candidate tiles of a wavefront's 64 rectangles are enumerated in chunks of 64, one candidate
+// per lane, whatever the rectangles' sizes: a candidate's rectangle (its owner lane) is found by a
+// binary search over the wavefront's exclusive prefix of areas, and the tile from the index within
+// that rectangle (row-major). Owners' visibility parameters sit in LDS.
+struct WaveCands {
+    uint32_t excl;     // this lane's exclusive prefix of areas
+    uint32_t total;    // the wavefront's number of candidates
+};
+
+__device__ inline WaveCands wave_cands(uint32_t area) {
+    const int lane = threadIdx.x & 63;
+    uint32_t x = area;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        const uint32_t y = __shfl_up(x, o, 64);
+        if (lane >= o) x += y;
+    }
+    return WaveCands{x - area, uint32_t(__shfl(x, 63, 64))};
+}
+
+// the lane owning candidate k: the last lane whose exclusive prefix is <= k
+__device__ inline int cand_owner(uint32_t excl, uint32_t k) {
+    int o = 0;
+#pragma unroll
+    for (int step = 32; step >= 1; step >>= 1)
+        if (uint32_t(__shfl(int(excl), o + step, 64)) <= k) o += step;
+    return o;
+}
+
+// a / b and a % b for a < 2^25, 0 < b < 2^13: a float quotient (error < 8) corrected exactly
+__device__ inline void divmod_small(uint32_t a, uint32_t b, uint32_t &q, uint32_t &r) {
+    uint32_t qq = uint32_t(float(a) * __builtin_amdgcn_rcpf(float(b)));
+    int32_t rr = int32_t(a) - int32_t(qq * b);
+    while (rr < 0) { --qq; rr += int32_t(b); }
+    while (rr >= int32_t(b)) { ++qq; rr -= int32_t(b); }
+    q = qq;
+    r = uint32_t(rr);
+}
+
+// lanes [s, e) of a 64-bit lane mask (0 <= s <= e <= 64)
+__device__ inline unsigned long long lane_range(int s, int e) {
+    const unsigned long long hi = e >= 64 ? ~0ull : ((1ull << e) - 1ull);
+    const unsigned long long lo = s >= 64 ? ~0ull : ((1ull << s) - 1ull);
+    return hi & ~lo;
+}
+
+// candidates of owner lane l that fall in the chunk [cb, cb + 64)
+__device__ inline unsigned long long owner_run(uint32_t excl, uint32_t area, uint32_t cb) {
+    const int64_t s0 = int64_t(excl) - int64_t(cb), e0 = s0 + int64_t(area);
+    const int s = int(s0 < 0 ? 0 : (s0 > 64 ? 64 : s0)), e = int(e0 < 0 ? 0 : (e0 > 64 ? 64 : e0));
+    return lane_range(s, e);
+}
+
+// Pair counts per Gaussian. Mode 0: the rectangle's area. Mode 1: its visible candidates, with
+// the candidates of each wavefront balanced over its lanes; a Gaussian with at most kMaskBits
+// candidates also records which ones are visible (masks).
 __global__ __launch_bounds__(256) void k_bin_count(const float2 *means, const int32_t *radii,
                                                    const float *conics, const float *opac,
                                                    int32_t mode, int64_t n, int32_t gx,
                                                    int32_t gy, int32_t W, int32_t H,
-                                                   unsigned long long *counts) {
+                                                   unsigned long long *counts,
+                                                   unsigned long long *masks) {
+    __shared__ GaussVis s_vis[256];
     const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
     if (mode == 0) {
         if (i >= n) return;
@@ -336,43 +439,44 @@ __global__ __launch_bounds__(256) void k_bin_count(const float2 *means, const in
     }
     if (int64_t(blockIdx.x) * blockDim.x >= n) return;   // block-uniform
     const bool valid = i < n;
-    Rect R{0, 0, 0, 0};
+    Rect CR{0, 0, 0, 0};
     GaussVis g{};
     if (valid) {
         const float2 m = means[i];
-        R = tile_rect(m.x, m.y, radii[i], gx, gy);
         g = vis_setup(m, conics + 3 * i, opac[i]);
+        CR = cand_rect(g, tile_rect(m.x, m.y, radii[i], gx, gy));
     }
-    const int w = R.tx1 - R.tx0;
-    const int area = w * (R.ty1 - R.ty0);
-    const bool big = area > kBigRect;
-    unsigned long long cnt = 0;
-    if (!big && g.live)
-        for (int32_t ty = R.ty0; ty < R.ty1; ++ty)
-            for (int32_t tx = R.tx0; tx < R.tx1; ++tx) cnt += tile_visible(g, tx, ty, W, H);
-    unsigned long long todo = __ballot(big && g.live);
-    const int lane = threadIdx.x & 63;
-    while (todo) {
-        const int src = __ffsll((long long)todo) - 1;
-        todo &= todo - 1;
-        GaussVis sg;
-        sg.x = __shfl(g.x, src); sg.y = __shfl(g.y, src);
-        sg.A = __shfl(g.A, src); sg.B = __shfl(g.B, src); sg.C = __shfl(g.C, src);
-        sg.det = __shfl(g.det, src); sg.theta = __shfl(g.theta, src);
-        sg.live = true;
-        const int stx0 = __builtin_amdgcn_readlane(R.tx0, src);
-        const int sty0 = __builtin_amdgcn_readlane(R.ty0, src);
-        const int sw = __builtin_amdgcn_readlane(w, src);
-        const int sarea = __builtin_amdgcn_readlane(area, src);
-        unsigned long long total = 0;
-        for (int k0 = 0; k0 < sarea; k0 += 64) {
-            const int k = k0 + lane;
-            const bool v = k < sarea && tile_visible(sg, stx0 + k % sw, sty0 + k / sw, W, H);
-            total += __popcll(__ballot(v));
+    s_vis[threadIdx.x] = g;   // read only by this wavefront's lanes
+    __builtin_amdgcn_wave_barrier();
+    const int w = CR.tx1 - CR.tx0;
+    const uint32_t area = uint32_t(w * (CR.ty1 - CR.ty0));
+    const WaveCands wc = wave_cands(area);
+    const int lane = threadIdx.x & 63, wbase = threadIdx.x & ~63;
+    unsigned long long cnt = 0, mask = 0;
+    for (uint32_t cb = 0; cb < wc.total; cb += 64) {
+        const uint32_t k = cb + lane;
+        const bool act = k < wc.total;
+        const int o = cand_owner(wc.excl, act ? k : wc.total - 1);
+        const uint32_t jl = (act ? k : 0u) - uint32_t(__shfl(int(wc.excl), o, 64));
+        const int ow = __shfl(w, o, 64), otx0 = __shfl(CR.tx0, o, 64), oty0 = __shfl(CR.ty0, o, 64);
+        uint32_t qy = 0, rx = 0;
+        if (act) divmod_small(jl, uint32_t(ow), qy, rx);
+        bool v = false;
+        if (act) v = tile_visible(s_vis[wbase + o], otx0 + int(rx), oty0 + int(qy), W, H);
+        // as an owner: my candidates in this chunk are lanes [rs, re)
+        const unsigned long long mine = __ballot(v) & owner_run(wc.excl, area, cb);
+        cnt += __popcll(mine);
+        if (area <= kMaskBits && mine) {
+            const int64_t rs = int64_t(wc.excl) - int64_t(cb);
+            const int s0 = rs > 0 ? int(rs) : 0;
+            const int j0 = rs > 0 ? 0 : int(-rs);      // my first candidate index in this chunk
+            mask |= (mine >> s0) << j0;
         }
-        if (lane == src) cnt = total;
     }
-    if (valid) counts[i] = cnt;
+    if (valid) {
+        counts[i] = cnt;
+        masks[i] = mask;
+    }
 }
 
 // Depth keys: the float's bits, made order-preserving for any sign (a no-op flip of the sign bit
@@ -385,8 +489,8 @@ __device__ inline uint32_t depth_key(float d) {
 // Emits the pairs of the Gaussian of rank j at offs[j]: tile id as key, Gaussian index as value.
 // The block's 256 consecutive ranks own one contiguous output segment; when it fits in LDS the
 // pairs are assembled there and written out in order (coalesced), otherwise straight to memory.
-// A thread emits its own rectangle when it is small; larger ones are emitted by the whole
-// wavefront together, one after the other.
+// A lane emits its own rectangle when it is small; larger ones are emitted by the whole wavefront
+// together, one after the other.
 constexpr int kFillStage = 4096;   // pairs staged per block
 
 struct PairSink {
@@ -411,7 +515,8 @@ __global__ __launch_bounds__(256) void k_bin_fill(const float2 *means, const int
                                                   const uint32_t *sorted_idx, int64_t n,
                                                   int32_t gx, int32_t gy,
                                                   const unsigned long long *offs,
-                                                  const unsigned long long *counts, BinHeader *hdr,
+                                                  const unsigned long long *counts,
+                                                  const unsigned long long *masks, BinHeader *hdr,
                                                   int64_t cap, uint32_t *keys, uint32_t *vals,
                                                   int32_t *status) {
     __shared__ uint32_t s_key[kFillStage], s_val[kFillStage];
@@ -425,15 +530,19 @@ __global__ __launch_bounds__(256) void k_bin_fill(const float2 *means, const int
     if (j0 >= n) return;   // block-uniform (only the single block of an empty launch)
     const bool valid = j < n;
     const uint32_t i = valid ? sorted_idx[j] : 0u;
+    // the rectangle to emit from: mode 0 the 3-sigma one, mode 1 the candidates (cand_rect)
     Rect R{0, 0, 0, 0};
     GaussVis g{};
-    unsigned long long base = 0;
+    unsigned long long base = 0, vmask = 0;
     if (valid) {
         const float2 m = means[i];
         R = tile_rect(m.x, m.y, radii[i], gx, gy);
         base = offs[j];
-        if (mode != 0) g = vis_setup(m, conics + 3 * int64_t(i), opac[i]);
-        if (mode != 0 && !g.live) R = Rect{0, 0, 0, 0};   // emits nothing
+        if (mode != 0) {
+            g = vis_setup(m, conics + 3 * int64_t(i), opac[i]);
+            R = cand_rect(g, R);
+            vmask = masks[i];
+        }
     }
     // the block's segment: [first rank's offset, last rank's offset + its count)
     const int64_t jl = (j0 + int64_t(blockDim.x) < n ? j0 + int64_t(blockDim.x) : n) - 1;
@@ -445,14 +554,25 @@ __global__ __launch_bounds__(256) void k_bin_fill(const float2 *means, const int
 
     const int w = R.tx1 - R.tx0;
     const int area = w * (R.ty1 - R.ty0);
-    const bool big = area > kBigRect;
+    // small rectangles: the lane emits its own (mode 1: the recorded visible candidates); large
+    // ones: the whole wavefront together, one after the other (mode 1: testing each candidate)
+    const bool big = mode == 0 ? area > kBigRect : area > int(kMaskBits);
     if (!big) {
         unsigned long long o = base;
-        for (int32_t ty = R.ty0; ty < R.ty1; ++ty)
-            for (int32_t tx = R.tx0; tx < R.tx1; ++tx) {
-                if (mode != 0 && !tile_visible(g, tx, ty, W, H)) continue;
-                sink.put(o++, uint32_t(int64_t(ty) * gx + tx), i);
+        if (mode == 0) {
+            for (int32_t ty = R.ty0; ty < R.ty1; ++ty)
+                for (int32_t tx = R.tx0; tx < R.tx1; ++tx, ++o)
+                    sink.put(o, uint32_t(int64_t(ty) * gx + tx), i);
+        } else {
+            // row by row: bits [r w, r w + w) of the mask are row r of the candidates
+            const unsigned long long rowm = w >= 64 ? ~0ull : ((1ull << w) - 1ull);
+            for (int32_t ty = R.ty0, sh = 0; ty < R.ty1; ++ty, sh += w) {
+                for (unsigned long long mk = (vmask >> sh) & rowm; mk; mk &= mk - 1, ++o) {
+                    const int bx = __ffsll((long long)mk) - 1;
+                    sink.put(o, uint32_t(int64_t(ty) * gx + (R.tx0 + bx)), i);
+                }
             }
+        }
     }
     unsigned long long todo = __ballot(big);
     const int lane = threadIdx.x & 63;
@@ -478,8 +598,9 @@ __global__ __launch_bounds__(256) void k_bin_fill(const float2 *means, const int
             sg.x = __shfl(g.x, src); sg.y = __shfl(g.y, src);
             sg.A = __shfl(g.A, src); sg.B = __shfl(g.B, src); sg.C = __shfl(g.C, src);
             sg.det = __shfl(g.det, src); sg.theta = __shfl(g.theta, src);
+            sg.far2 = __shfl(g.far2, src); sg.near2 = __shfl(g.near2, src);
             sg.live = true;
-            unsigned long long o = sbase;       // visible tiles in row-major order
+            unsigned long long o = sbase;       // visible candidates in row-major order
             for (int k0 = 0; k0 < sarea; k0 += 64) {
                 const int k = k0 + lane;
                 const int ty = sty0 + k / sw, tx = stx0 + k % sw;
@@ -830,7 +951,7 @@ gsb_status bin_count(const float *means2d, const int32_t *radii, const float *co
     if (n > 0)
         k_bin_count<<<dim3(unsigned((n + 255) / 256)), 256, 0, s>>>(
             reinterpret_cast<const float2 *>(means2d), radii, conics, opacity, mode, n, gx, gy, W,
-            H, counts);
+            H, counts, at<unsigned long long>(ws, L.masks));
     // the total only: offsets are formed in depth order by bin_fill
     launch_scan<unsigned long long>(counts, n, partial, &hdr->total,
                                     reinterpret_cast<long long *>(n_pairs_dev), s, false);
@@ -872,8 +993,9 @@ gsb_status bin_fill(const float *means2d, const int32_t *radii, const float *con
     uint32_t *v_first = (tp % 2 == 0) ? point_list : vtmp;
     uint32_t *v_second = (tp % 2 == 0) ? vtmp : point_list;
     k_bin_fill<<<gn, 256, 0, s>>>(reinterpret_cast<const float2 *>(means2d), radii, conics, opacity,
-                                  mode, W, H, sorted_idx, n, gx, gy, offs, counts, hdr, cap, tka,
-                                  v_first, status_dev);
+                                  mode, W, H, sorted_idx, n, gx, gy, offs, counts,
+                                  at<unsigned long long>(ws, L.masks), hdr, cap, tka, v_first,
+                                  status_dev);
     // 3. stable sort of the pairs on the tile id
     sort_tiles(tka, tkb, v_first, v_second, &hdr->pairs, cap, tile_bits, sortbuf, partial32,
                status_dev, s);
