@@ -58,6 +58,9 @@ def parse():
                    help="skip the 16-view batched measurement")
     p.add_argument("--no-visible", action="store_true",
                    help="skip the step with visible-tile binning")
+    p.add_argument("--sweep", action="store_true",
+                   help="instead of the benchmark line: sensitivity sweeps of the LDS batch size "
+                        "and of the resolution (1x, 2x, 3x), GEMM form vs plain FP32")
     p.add_argument("--calib-copy-mib", type=int, default=0,
                    help="also run one device-to-device copy of this many MiB (a known-size "
                         "kernel for scaling HBM byte counters)")
@@ -68,15 +71,15 @@ class Frame:
     """Device buffers of one frame: inputs, binning workspace sized for the exact pair count,
     outputs and gradients."""
 
-    def __init__(self, cfg, dev, bin_mode="rect"):
+    def __init__(self, cfg, dev, bin_mode="rect", scene=None):
         self.bin_mode = bin_mode
-        s = gsinputs.make_scene(cfg)
+        s = gsinputs.make_scene(cfg) if scene is None else scene
         self.scene = s
         self.W, self.H, self.n = s["width"], s["height"], len(s["radii"])
         t = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(dev)  # noqa: E731
         self.means2d, self.conics, self.opacity = t(s["means2d"]), t(s["conics"]), t(s["opacity"])
         self.colors, self.depths, self.radii = t(s["colors"]), t(s["depths"]), t(s["radii"])
-        self.dloss_np = gsinputs.make_dloss(self.W, self.H, cfg.dloss_seed)
+        self.dloss_np = gsinputs.make_dloss(self.W, self.H, cfg.dloss_seed if cfg else 1002)
         self.dloss = t(self.dloss_np)
         ws0 = api.BinWorkspace(self.n, 0, self.W, self.H, device=dev)
         self.pairs = int(api.bin_count(self.means2d, self.radii, self.W, self.H, ws0,
@@ -92,6 +95,10 @@ class Frame:
         self.bwd_out = (torch.empty((self.n, 2), device=dev), torch.empty((self.n, 3), device=dev),
                         torch.empty((self.n,), device=dev), torch.empty((self.n, 3), device=dev))
         self.status = None
+
+    @classmethod
+    def from_scene(cls, scene, dev, bin_mode="rect"):
+        return cls(None, dev, bin_mode, scene)
 
     def step(self, prec, ev=None):
         if ev is not None:
@@ -235,6 +242,60 @@ def time_visible(cfg, dev, prec: str, steps: int, warmup: int, head: dict, ref_o
     return out
 
 
+def run_sweeps(dev, steps: int, warmup: int) -> dict:
+    """Sensitivity sweeps on the 1080p scene: (1) forward and backward time per LDS batch size
+    b (single-view plans with fixed launch shapes), (2) the same scene rendered at 1x, 2x and 3x
+    resolution (means and axis lengths scaled), forward + backward blend time, each in the FP16
+    GEMM form and the plain FP32 form."""
+    def upload(sc):
+        d = {"width": sc["width"], "height": sc["height"]}
+        for k in ("means2d", "conics", "opacity", "colors", "depths", "radii"):
+            d[k] = torch.from_numpy(np.ascontiguousarray(sc[k])).to(dev)
+        return d
+
+    def timed(fn):
+        for _ in range(warmup):
+            fn()
+        torch.cuda.synchronize()
+        ms = []
+        for _ in range(steps):
+            a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            a.record()
+            fn()
+            b.record()
+            b.synchronize()
+            ms.append(a.elapsed_time(b))
+        return float(np.median(ms))
+
+    out = {"batch": [], "resolution": []}
+    base = gsinputs.make_scene("C2")
+    view = upload(base)
+    g = torch.from_numpy(gsinputs.make_dloss(base["width"], base["height"], 1002)).to(dev)
+    for prec in ("fp16", "fp32"):
+        for nb in (64, 128, 256):
+            bv = api.BatchedViews([view], prec=prec,
+                                  tuning={"batch_fwd": nb, "batch_bwd": nb, "launch": 1})
+            bv.views[0]["dL_dimage"].copy_(g)
+            bv.bin()
+            out["batch"].append({"precision": prec, "b": nb, "fwd_ms": round(timed(bv.forward), 4),
+                                 "bwd_ms": round(timed(bv.backward), 4)})
+            bv.close()
+    for scale in (1, 2, 3):
+        sc = gsinputs.make_scene("C2", scale=float(scale))
+        fr = Frame.from_scene(sc, dev)
+        row = {"scale": scale, "width": sc["width"], "height": sc["height"], "pairs": fr.pairs}
+        for prec in ("fp16", "fp32"):
+            r = time_path(fr, prec, steps, warmup)
+            row[prec] = {"fwd_ms": round(r["fwd_ms"], 4), "bwd_ms": round(r["bwd_ms"], 4),
+                         "blend_mpix_s": round(r["blend_mpix_s"], 2)}
+        row["gemm_speedup_fwd"] = round(row["fp32"]["fwd_ms"] / row["fp16"]["fwd_ms"], 3)
+        row["gemm_speedup_blend"] = round(row["fp16"]["blend_mpix_s"] / row["fp32"]["blend_mpix_s"], 3)
+        out["resolution"].append(row)
+        del fr
+        torch.cuda.empty_cache()
+    return out
+
+
 def kernel_hash() -> str:
     return hashlib.sha256(open(KERNEL_SRC, "rb").read()).hexdigest()[:16]
 
@@ -305,6 +366,9 @@ def main():
               file=sys.stderr)
         sys.exit(2)
     dev = torch.device("cuda:0")
+    if args.sweep:
+        print(json.dumps({"sweep": run_sweeps(dev, max(5, args.steps // 2), 2)}), flush=True)
+        return
     if args.calib_copy_mib:
         n = args.calib_copy_mib * (1 << 20) // 4
         src = torch.ones(n, dtype=torch.float32, device=dev)

@@ -111,11 +111,12 @@ def conic_from_axes(theta: np.ndarray, s1: np.ndarray, s2: np.ndarray) -> np.nda
 
 def make_scene(cfg: SceneConfig | str, seed: int | None = None, *, n: int | None = None,
                width: int | None = None, height: int | None = None,
-               depth_levels: int | None = None) -> dict[str, np.ndarray | int]:
+               depth_levels: int | None = None, scale: float = 1.0) -> dict[str, np.ndarray | int]:
     """Draw one scene. Overrides (n, width, height, seed) keep the config's laws.
 
     ``depth_levels`` quantises depth to that many distinct values (ties stress the sort's
-    tie-break); ``None`` keeps continuous depth.
+    tie-break); ``None`` keeps continuous depth. ``scale`` renders the same draw at a
+    ``scale`` times larger resolution: image size, means and axis lengths are multiplied by it.
     """
     if isinstance(cfg, str):
         cfg = CONFIGS[cfg]
@@ -140,6 +141,9 @@ def make_scene(cfg: SceneConfig | str, seed: int | None = None, *, n: int | None
     depth = rng.uniform(1.0, 100.0, N)
     if depth_levels is not None:
         depth = 1.0 + np.floor((depth - 1.0) / 99.0 * depth_levels)
+    if scale != 1.0:
+        x, y, s1, s2 = x * scale, y * scale, s1 * scale, s2 * scale
+        W, H = int(round(W * scale)), int(round(H * scale))
     conic = conic_from_axes(theta, s1, s2)
     radii = np.ceil(3.0 * np.maximum(s1, s2)).astype(np.int32)
     return {
