@@ -32,6 +32,7 @@ import math
 import numpy as np
 
 __all__ = ["SceneConfig", "CONFIGS", "make_scene", "make_dloss", "make_views", "fd_subscene",
+           "Camera", "make_scene3d", "look_at",
            "stack_scene"]
 
 # log-normal sigma law: ln sigma ~ N(ln median, 0.932^2) has P(sigma > 64) = 1e-4 at median 2,
@@ -206,4 +207,72 @@ def stack_scene(n: int, opacity: float, width: int = 16, height: int = 16,
         "colors": np.tile(np.array([[1.0, 0.5, 0.25]], np.float32), (n, 1)),
         "depths": np.arange(1, n + 1, dtype=np.float32),
         "radii": np.full(n, int(math.ceil(3 * sigma)), np.int32),
+    }
+
+
+# ----------------------------------------------------------------------------- 3D scenes
+@dataclasses.dataclass(frozen=True)
+class Camera:
+    """Pinhole camera: world-to-camera rotation R (3x3, row-major) and translation t, focal
+    lengths and principal point in pixels, image size, near plane."""
+    R: tuple
+    t: tuple
+    fx: float
+    fy: float
+    cx: float
+    cy: float
+    width: int
+    height: int
+    near: float = 0.2
+
+
+def look_at(eye, target, up, fx, fy, width, height, near=0.2) -> Camera:
+    """Camera at ``eye`` looking at ``target`` (+z forward, +y down in the image, +x right)."""
+    eye, target, up = (np.asarray(v, np.float64) for v in (eye, target, up))
+    z = target - eye
+    z /= np.linalg.norm(z)
+    x = np.cross(z, up)
+    x /= np.linalg.norm(x)
+    y = np.cross(z, x)
+    R = np.stack([x, y, z])
+    t = -R @ eye
+    return Camera(tuple(map(tuple, R.astype(np.float32).astype(np.float64))),
+                  tuple(t.astype(np.float32).astype(np.float64)), float(fx), float(fy),
+                  width / 2.0, height / 2.0, int(width), int(height), float(near))
+
+
+def make_scene3d(n: int = 1_000_000, seed: int = 7, width: int = 1920, height: int = 1080,
+                 sigma_px_median: float = 2.0, camera: Camera | None = None) -> dict:
+    """3D Gaussians in front of a pinhole camera, drawn so that their projections resemble the
+    2D scenes above: depth z ~ U(2, 20) along the view axis, image position uniform, per-axis 3D
+    scale = (log-normal pixel sigma, median ``sigma_px_median``, sd 0.932, clipped to [0.5, 64])
+    * z / f, a uniformly random rotation (normalised Gaussian quaternion), opacity U(0.05, 0.99),
+    spherical-harmonic colour coefficients sh [n][16][3] (degree 3): band 0 U(-1.75, 1.75),
+    bands 1-3 N(0, 0.15^2). The camera looks along +z from the origin unless one is given (then
+    points are drawn in that camera's frame and mapped to world coordinates).
+    Draw order: u, v, z, the three scales, quaternion (4), opacity, band 0 (3), bands 1-3 (45)."""
+    cam = camera or Camera(((1.0, 0.0, 0.0), (0.0, 1.0, 0.0), (0.0, 0.0, 1.0)), (0.0, 0.0, 0.0),
+                           1000.0, 1000.0, width / 2.0, height / 2.0, width, height, 0.2)
+    rng = np.random.default_rng(seed)
+    u = rng.uniform(0.0, cam.width, n)
+    v = rng.uniform(0.0, cam.height, n)
+    z = rng.uniform(2.0, 20.0, n)
+    sig = np.clip(np.exp(rng.normal(math.log(sigma_px_median), 0.932, (n, 3))), 0.5, 64.0)
+    q = rng.normal(0.0, 1.0, (n, 4))
+    q /= np.linalg.norm(q, axis=1, keepdims=True)
+    opacity = rng.uniform(0.05, 0.99, n)
+    sh = np.empty((n, 16, 3))
+    sh[:, 0, :] = rng.uniform(-1.75, 1.75, (n, 3))
+    sh[:, 1:, :] = rng.normal(0.0, 0.15, (n, 15, 3))
+    pc = np.stack([(u - cam.cx) / cam.fx * z, (v - cam.cy) / cam.fy * z, z], axis=1)
+    R, t = np.asarray(cam.R), np.asarray(cam.t)
+    pw = (pc - t) @ R                                  # camera -> world (R orthonormal)
+    scales = sig * (z / cam.fx)[:, None]
+    return {
+        "camera": cam,
+        "means3d": pw.astype(np.float32),
+        "scales": scales.astype(np.float32),
+        "quats": q.astype(np.float32),                 # (w, x, y, z)
+        "opacity": opacity.astype(np.float32),
+        "sh": sh.astype(np.float32),
     }

@@ -49,6 +49,10 @@ def _load():
         lib.orc_forward.restype = None
         lib.orc_backward.argtypes = [i32, i32, P, P, P, P, P, P, P, i64, P, P, P, P, P]
         lib.orc_backward.restype = None
+        lib.orc_sh_basis.argtypes = [P, i64, i32, P]
+        lib.orc_sh_basis.restype = None
+        lib.orc_project.argtypes = [P, P, P, P, i32, i32, i64, P, P, P, P, P, P, P, P]
+        lib.orc_project.restype = None
         lib.orc_threads.restype = ctypes.c_int
         lib.orc_set_threads.argtypes = [ctypes.c_int]
         _lib = lib
@@ -209,3 +213,45 @@ def work_counts(fwd: dict, ranges) -> dict[str, int]:
             "Eb": int(fwd["last_contrib"].astype(np.int64).sum()),
             "K": int(fwd["n_contrib"].astype(np.int64).sum()), "F": F,
             "P": int((rg[:, 1] - rg[:, 0]).sum())}
+
+
+def camera_array(cam) -> np.ndarray:
+    """[R(9), t(3), fx, fy, cx, cy, W, H, near] of a ``gsinputs.Camera``; every float rounded
+    to FP32 first (the values the FP32 library receives)."""
+    f = np.float32
+    vals = [*np.ravel(cam.R), *cam.t, cam.fx, cam.fy, cam.cx, cam.cy]
+    return np.array([*np.asarray(vals, f).astype(np.float64), cam.width, cam.height,
+                     float(f(cam.near))], np.float64)
+
+
+def sh_basis(dirs, deg: int) -> np.ndarray:
+    """Real spherical harmonics (Condon-Shortley phase kept) of degree <= deg at directions
+    dirs [n][3] (normalised inside): [n][(deg + 1)^2]."""
+    lib = _load()
+    d = _f64(dirs).reshape(-1, 3)
+    out = np.empty((d.shape[0], (deg + 1) ** 2))
+    lib.orc_sh_basis(_ptr(d), d.shape[0], deg, _ptr(out))
+    return out
+
+
+def project(scene3d: dict, sh_degree: int | None = None) -> dict[str, np.ndarray]:
+    """Projection of 3D Gaussians to the screen in FP64 (rule in gsoracle.c): means2d, conics,
+    depths, radii, colors, plus rad_real (3 sqrt(lmax) before the ceiling) and margin (distance
+    of the culling decisions from their thresholds). sh [n][K][3]; sh_degree defaults to the
+    largest the stored K allows."""
+    lib = _load()
+    m, sc, q = _f64(scene3d["means3d"]), _f64(scene3d["scales"]), _f64(scene3d["quats"])
+    sh = _f64(scene3d["sh"])
+    n, K = m.shape[0], sh.shape[1]
+    deg = int(round(np.sqrt(K))) - 1 if sh_degree is None else int(sh_degree)
+    if not (0 <= deg <= 3 and (deg + 1) ** 2 <= K):
+        raise ValueError(f"SH degree {deg} needs (deg + 1)^2 <= {K} coefficients, deg <= 3")
+    cam = camera_array(scene3d["camera"])
+    out = {"means2d": np.empty((n, 2)), "conics": np.empty((n, 3)), "depths": np.empty(n),
+           "radii": np.empty(n, np.int32), "colors": np.empty((n, 3)), "rad_real": np.empty(n),
+           "margin": np.empty(n)}
+    lib.orc_project(_ptr(m), _ptr(sc), _ptr(q), _ptr(sh), K, deg, n, _ptr(cam),
+                    _ptr(out["means2d"]), _ptr(out["conics"]), _ptr(out["depths"]),
+                    _ptr(out["radii"]), _ptr(out["colors"]), _ptr(out["rad_real"]),
+                    _ptr(out["margin"]))
+    return out

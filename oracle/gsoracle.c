@@ -103,6 +103,7 @@ static void tile_rect(double x, double y, int32_t r, int64_t gx, int64_t gy,
  * division, with this fixed sequence of IEEE double operations (no contraction), so the decision
  * is reproducible bit for bit. */
 #define ORC_LN2_UP 0x1.62e42fefa39fp-1
+#define ORC_PI 3.14159265358979323846
 #define ORC_CULL_MARGIN 0.1
 
 static double vis_theta(double o) {
@@ -419,5 +420,167 @@ void orc_backward(int32_t W, int32_t H, const uint32_t *ranges, const uint32_t *
         }
         free(c_idx); free(c_alpha); free(c_T); free(c_G); free(c_dx); free(c_dy);
         free(c_aclamp); free(c_pclamp);
+    }
+}
+
+
+/* ---- Preprocessing (Sec. 2.1(a)): 3D Gaussians seen by a pinhole camera become the 2D
+ * Gaussians the blend consumes (mean, conic, depth, extent radius) and get their colour for this
+ * view. The paper names the step and its outputs without formulas; this is the EWA splatting
+ * projection of 3D Gaussian splatting, the method the paper accelerates.
+ *
+ * Real spherical harmonics of degree l <= 3 at a unit direction (x, y, z), polar axis z, in the
+ * usual order (l, m = -l..l), with the Condon-Shortley phase kept:
+ *   Y_l^m = sqrt(2) K_l^m cos(m phi) P_l^m(cos theta)     (m > 0)
+ *   Y_l^0 = K_l^0 P_l^0(cos theta)
+ *   Y_l^m = sqrt(2) K_l^|m| sin(|m| phi) P_l^|m|(cos theta) (m < 0)
+ *   K_l^m = sqrt((2l + 1) / (4 pi) (l - m)! / (l + m)!),
+ * P_l^m the associated Legendre functions (with the (-1)^m phase) from the textbook recurrences
+ *   P_m^m = (-1)^m (2m - 1)!! (1 - t^2)^(m/2),  P_{m+1}^m = t (2m + 1) P_m^m,
+ *   P_l^m = ((2l - 1) t P_{l-1}^m - (l + m - 1) P_{l-2}^m) / (l - m).
+ * out receives (deg + 1)^2 values per direction. */
+static double orc_fact(int k) {
+    double f = 1.0;
+    for (int i = 2; i <= k; ++i) f *= i;
+    return f;
+}
+
+static void sh_basis_one(const double *d, int deg, double *out) {
+    const double nrm = sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
+    const double x = d[0] / nrm, y = d[1] / nrm, t = d[2] / nrm;
+    const double st = sqrt(fmax(0.0, 1.0 - t * t));
+    const double phi = atan2(y, x);
+    double P[4][4] = {{0}};                          /* P[l][m], m >= 0 */
+    for (int m = 0; m <= deg; ++m) {
+        double pmm = 1.0;
+        for (int k = 1; k <= m; ++k) pmm *= -(2.0 * k - 1.0) * st;
+        P[m][m] = pmm;
+        if (m + 1 <= deg) P[m + 1][m] = t * (2.0 * m + 1.0) * pmm;
+        for (int l = m + 2; l <= deg; ++l)
+            P[l][m] = ((2.0 * l - 1.0) * t * P[l - 1][m] - (l + m - 1.0) * P[l - 2][m]) / (l - m);
+    }
+    for (int l = 0; l <= deg; ++l)
+        for (int m = -l; m <= l; ++m) {
+            const int am = m < 0 ? -m : m;
+            const double K = sqrt((2.0 * l + 1.0) / (4.0 * ORC_PI) * orc_fact(l - am) / orc_fact(l + am));
+            double v;
+            if (m > 0) v = sqrt(2.0) * K * cos(m * phi) * P[l][am];
+            else if (m == 0) v = K * P[l][0];
+            else v = sqrt(2.0) * K * sin(am * phi) * P[l][am];
+            out[l * l + l + m] = v;
+        }
+}
+
+void orc_sh_basis(const double *dirs, int64_t n, int32_t deg, double *out) {
+    const int64_t k = (int64_t)(deg + 1) * (deg + 1);
+    for (int64_t i = 0; i < n; ++i) sh_basis_one(dirs + 3 * i, deg, out + k * i);
+}
+
+/* Projection. Camera cam = [R (9, row-major, world to camera), t (3), fx, fy, cx, cy, W, H,
+ * near]. Per Gaussian i (mean m, per-axis scale s, quaternion q = (w, x, y, z), SH coefficients
+ * sh[i][k][c] for k < sh_coeffs of which the first (deg + 1)^2 are used):
+ *   p = R m + t; culled if p.z <= near;
+ *   means2d = (fx p.x / p.z + cx, fy p.y / p.z + cy), depth = p.z;
+ *   Sigma3 = Rq diag(s^2) Rq^T, Rq the rotation of q / |q|;
+ *   J = d(means2d)/dp = [[fx/z, 0, -fx x/z^2], [0, fy/z, -fy y/z^2]], evaluated with x/z and y/z
+ *       clamped to 1.3 times the half field of view (W / (2 fx), H / (2 fy));
+ *   Sigma2 = J R Sigma3 R^T J^T + 0.3 I (a low-pass filter); culled unless det Sigma2 > 0;
+ *   conic = Sigma2^-1 = (c, -b, a) / det for Sigma2 = [[a, b], [b, c]];
+ *   radius = ceil(3 sqrt(lmax)), lmax = mid + sqrt(max(0.1, mid^2 - det)), mid = (a + c) / 2;
+ *   culled if the radius-square's tile rectangle (the binning rule above) is empty;
+ *   colour_c = max(0, 0.5 + sum_k Y_k(dir) sh[i][k][c]), dir = (m - o) / |m - o| with the
+ *       camera centre o = -R^T t.
+ * A culled Gaussian has radius 0 and every other output 0.
+ * rad_real receives 3 sqrt(lmax) (before the ceiling) and margin the smallest distance of a
+ * culling decision from its threshold (relative for the depth and det tests, in pixels for the
+ * rectangle test), so a caller can tell which integers rounding may flip. */
+void orc_project(const double *means3d, const double *scales, const double *quats,
+                 const double *sh, int32_t sh_coeffs, int32_t deg, int64_t n, const double *cam,
+                 double *means2d, double *conics, double *depths, int32_t *radii,
+                 double *colors, double *rad_real, double *margin) {
+    const double *R = cam, *t = cam + 9;
+    const double fx = cam[12], fy = cam[13], cx = cam[14], cy = cam[15];
+    const int64_t W = (int64_t)cam[16], H = (int64_t)cam[17];
+    const double near = cam[18];
+    const double limx = 1.3 * ((double)W / (2.0 * fx)), limy = 1.3 * ((double)H / (2.0 * fy));
+    const int64_t gx = (W + ORC_TILE - 1) / ORC_TILE, gy = (H + ORC_TILE - 1) / ORC_TILE;
+    double o[3];
+    for (int c = 0; c < 3; ++c) o[c] = -(R[c] * t[0] + R[3 + c] * t[1] + R[6 + c] * t[2]);
+    const int nb = (deg + 1) * (deg + 1);
+#pragma omp parallel for schedule(static)
+    for (int64_t i = 0; i < n; ++i) {
+        const double *m = means3d + 3 * i, *sc = scales + 3 * i, *q0 = quats + 4 * i;
+        means2d[2 * i] = means2d[2 * i + 1] = 0.0;
+        conics[3 * i] = conics[3 * i + 1] = conics[3 * i + 2] = 0.0;
+        colors[3 * i] = colors[3 * i + 1] = colors[3 * i + 2] = 0.0;
+        depths[i] = 0.0;
+        radii[i] = 0;
+        rad_real[i] = 0.0;
+        double p[3];
+        for (int r = 0; r < 3; ++r) p[r] = R[3 * r] * m[0] + R[3 * r + 1] * m[1] + R[3 * r + 2] * m[2] + t[r];
+        margin[i] = fabs(p[2] - near) / fmax(fabs(near), 1e-30);
+        if (!(p[2] > near)) continue;
+        const double u = fx * p[0] / p[2] + cx, v = fy * p[1] / p[2] + cy;
+        /* Sigma3 */
+        const double qn = sqrt(q0[0] * q0[0] + q0[1] * q0[1] + q0[2] * q0[2] + q0[3] * q0[3]);
+        const double w = q0[0] / qn, x = q0[1] / qn, y = q0[2] / qn, z = q0[3] / qn;
+        const double Rq[3][3] = {
+            {1 - 2 * (y * y + z * z), 2 * (x * y - w * z), 2 * (x * z + w * y)},
+            {2 * (x * y + w * z), 1 - 2 * (x * x + z * z), 2 * (y * z - w * x)},
+            {2 * (x * z - w * y), 2 * (y * z + w * x), 1 - 2 * (x * x + y * y)}};
+        double S3[3][3];
+        for (int r = 0; r < 3; ++r)
+            for (int c = 0; c < 3; ++c) {
+                double acc = 0.0;
+                for (int k = 0; k < 3; ++k) acc += Rq[r][k] * sc[k] * sc[k] * Rq[c][k];
+                S3[r][c] = acc;
+            }
+        /* J R, then Sigma2 */
+        const double zc = p[2];
+        const double xz = fmin(limx, fmax(-limx, p[0] / zc)), yz = fmin(limy, fmax(-limy, p[1] / zc));
+        const double J[2][3] = {{fx / zc, 0.0, -fx * xz / zc}, {0.0, fy / zc, -fy * yz / zc}};
+        double T[2][3];
+        for (int r = 0; r < 2; ++r)
+            for (int c = 0; c < 3; ++c) T[r][c] = J[r][0] * R[c] + J[r][1] * R[3 + c] + J[r][2] * R[6 + c];
+        double S2[2][2];
+        for (int r = 0; r < 2; ++r)
+            for (int c = 0; c < 2; ++c) {
+                double acc = 0.0;
+                for (int k = 0; k < 3; ++k)
+                    for (int l = 0; l < 3; ++l) acc += T[r][k] * S3[k][l] * T[c][l];
+                S2[r][c] = acc;
+            }
+        const double a = S2[0][0] + 0.3, b = S2[0][1], c = S2[1][1] + 0.3;
+        const double det = a * c - b * b;
+        margin[i] = fmin(margin[i], fabs(det) / fmax(a * c, 1e-300));
+        if (!(det > 0.0)) continue;
+        const double mid = 0.5 * (a + c);
+        const double lmax = mid + sqrt(fmax(0.1, mid * mid - det));
+        const double rr = 3.0 * sqrt(lmax);
+        const int32_t r = (int32_t)ceil(rr);
+        /* empty tile rectangle: x + r + 15 < 16 or x - r >= 16 gx (and in y) */
+        int64_t tx0, tx1, ty0, ty1;
+        tile_rect(u, v, r, gx, gy, &tx0, &tx1, &ty0, &ty1);
+        const double em = fmin(fmin(fabs(u + r - 1.0), fabs(u - r - (double)(ORC_TILE * gx))),
+                               fmin(fabs(v + r - 1.0), fabs(v - r - (double)(ORC_TILE * gy))));
+        margin[i] = fmin(margin[i], em);
+        rad_real[i] = rr;
+        if (tx1 <= tx0 || ty1 <= ty0) continue;
+        means2d[2 * i] = u;
+        means2d[2 * i + 1] = v;
+        depths[i] = zc;
+        conics[3 * i] = c / det;
+        conics[3 * i + 1] = -b / det;
+        conics[3 * i + 2] = a / det;
+        radii[i] = r;
+        /* colour */
+        double dir[3] = {m[0] - o[0], m[1] - o[1], m[2] - o[2]};
+        double Y[16];
+        sh_basis_one(dir, deg, Y);
+        for (int ch = 0; ch < 3; ++ch) {
+            double acc = 0.5;
+            for (int k = 0; k < nb; ++k) acc += Y[k] * sh[(i * sh_coeffs + k) * 3 + ch];
+            colors[3 * i + ch] = fmax(0.0, acc);
+        }
     }
 }
