@@ -58,6 +58,8 @@ def parse():
                    help="skip the 16-view batched measurement")
     p.add_argument("--no-visible", action="store_true",
                    help="skip the step with visible-tile binning")
+    p.add_argument("--no-pipeline", action="store_true",
+                   help="skip the leg that starts from 3D Gaussians (projection + the step)")
     p.add_argument("--sweep", action="store_true",
                    help="instead of the benchmark line: sensitivity sweeps of the LDS batch size "
                         "and of the resolution (1x, 2x, 3x), GEMM form vs plain FP32")
@@ -242,6 +244,62 @@ def time_visible(cfg, dev, prec: str, steps: int, warmup: int, head: dict, ref_o
     return out
 
 
+def time_pipeline(dev, prec: str, steps: int, warmup: int) -> dict:
+    """The step preceded by preprocessing: 1,000,000 3D Gaussians (SH degree 3, 16 coefficients)
+    seen by a 1920x1080 pinhole camera are projected (gsb_project), then binned, blended forward
+    and backward as in the headline step. Reports each stage and the projection kernel against
+    HBM bandwidth: it moves 40 + 12 * 16 bytes in and 40 bytes out per Gaussian."""
+    s = gsinputs.make_scene3d(n=1_000_000, seed=7)
+    t = {k: torch.from_numpy(np.ascontiguousarray(s[k], np.float32)).to(dev)
+         for k in ("means3d", "scales", "quats", "sh", "opacity")}
+    n, K = s["means3d"].shape[0], s["sh"].shape[1]
+    cam = api.camera_struct(s["camera"].R, s["camera"].t, s["camera"].fx, s["camera"].fy,
+                            s["camera"].cx, s["camera"].cy, s["camera"].width,
+                            s["camera"].height, s["camera"].near)
+    proj = (torch.empty((n, 2), device=dev), torch.empty((n, 3), device=dev),
+            torch.empty((n,), device=dev), torch.empty((n,), dtype=torch.int32, device=dev),
+            torch.empty((n, 3), device=dev))
+    api.project(t["means3d"], t["scales"], t["quats"], t["sh"], cam, out=proj)
+    m2, con, dep, rad, col = proj
+    fr = Frame.from_scene({"width": s["camera"].width, "height": s["camera"].height,
+                           "means2d": m2.cpu().numpy(), "conics": con.cpu().numpy(),
+                           "opacity": s["opacity"], "colors": col.cpu().numpy(),
+                           "depths": dep.cpu().numpy(), "radii": rad.cpu().numpy()}, dev)
+    # the frame reads the projection's own buffers, which every step rewrites
+    fr.means2d, fr.conics, fr.colors, fr.depths, fr.radii = m2, con, col, dep, rad
+
+    def step(ev=None):
+        if ev is not None:
+            ev[0].record()
+        api.project(t["means3d"], t["scales"], t["quats"], t["sh"], cam, out=proj)
+        fr.step(prec, None if ev is None else ev[1:])
+
+    for _ in range(warmup):
+        step()
+    torch.cuda.synchronize()
+    evs = [[torch.cuda.Event(enable_timing=True) for _ in range(5)] for _ in range(steps)]
+    t0 = time.perf_counter()
+    for k in range(steps):
+        step(evs[k])
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    if int(fr.status.item()) != 0:
+        raise RuntimeError("binning overflowed its capacity")
+    ms = lambda a, b: float(np.mean([e[a].elapsed_time(e[b]) for e in evs]))  # noqa: E731
+    proj_ms = ms(0, 1)
+    nbytes = n * (40 + 12 * K + 40)
+    gbs = nbytes / (proj_ms * 1e-3) / 1e9
+    return {"workload": "1M 3D Gaussians, SH degree 3, 1920x1080 camera", "precision": prec,
+            "visible": int((rad > 0).sum().item()), "pairs": fr.pairs,
+            "ms_per_step": round(1e3 * wall / steps, 4),
+            "mpix_s": round(fr.W * fr.H * steps / wall / 1e6, 2),
+            "project_ms": round(proj_ms, 4), "bin_ms": round(ms(1, 2), 4),
+            "fwd_ms": round(ms(2, 3), 4), "bwd_ms": round(ms(3, 4), 4),
+            "project_roofline": {"bound": "hbm", "achieved": round(gbs, 1), "peak": 8000.0,
+                                 "unit": "GB/s", "frac": round(gbs / 8000.0, 4),
+                                 "bytes_per_gaussian": 40 + 12 * K + 40}}
+
+
 def run_sweeps(dev, steps: int, warmup: int) -> dict:
     """Sensitivity sweeps on the 1080p scene: (1) forward and backward time per LDS batch size
     b (single-view plans with fixed launch shapes), (2) the same scene rendered at 1x, 2x and 3x
@@ -411,6 +469,8 @@ def main():
     if not args.no_visible:
         line["visible_binning"] = time_visible(cfg, dev, precs[0], args.steps, args.warmup,
                                                head, outputs.get(precs[0]))
+    if not args.no_pipeline:
+        line["pipeline_3d"] = time_pipeline(dev, precs[0], args.steps, args.warmup)
     if not args.no_batched:
         line["batched_c4"] = time_batched(max(5, args.steps // 2), 2, dev)
     if not args.no_cpu_baseline:

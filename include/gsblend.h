@@ -52,7 +52,7 @@ typedef int32_t gsb_precision;
 #define GSB_FP16_GEMM 1   /* exponent as an MFMA product, FP16 hi+lo operands, FP32 accumulate */
 #define GSB_BF16_GEMM 2   /* same with BF16 hi+lo operands */
 
-#define GSB_ABI_VERSION 2
+#define GSB_ABI_VERSION 3
 
 /* Version of this interface (GSB_ABI_VERSION of the library that was loaded). */
 int32_t gsb_abi_version(void);
@@ -60,6 +60,51 @@ int32_t gsb_abi_version(void);
 /* Message of the last failed call on this thread ("" if none). Valid until the next call made by
  * the same thread. */
 const char *gsb_last_error(void);
+
+/* ---------------------------------------------------------------------------------------------
+ * Preprocessing (paper Sec. 2.1(a)): 3D Gaussians seen by a pinhole camera become the 2D Gaussians
+ * of the blend, with their depth, extent radius and view-dependent colour. The paper names this
+ * step and its outputs; the rule is the EWA splatting projection of 3D Gaussian splatting, the
+ * renderer whose blend the paper replaces. Per Gaussian i:
+ *   p = R m_i + t (camera coordinates); culled if p.z <= near;
+ *   means2d = (fx p.x / p.z + cx, fy p.y / p.z + cy), depth = p.z;
+ *   Sigma3 = Rq diag(s_i^2) Rq^T, Rq the rotation of the normalised quaternion q_i = (w, x, y, z);
+ *   J = d(means2d)/dp = [[fx/z, 0, -fx x/z^2], [0, fy/z, -fy y/z^2]] with x/z and y/z clamped to
+ *       +-1.3 W / (2 fx) and +-1.3 H / (2 fy);
+ *   Sigma2 = J R Sigma3 R^T J^T + 0.3 I = [[a, b], [b, c]]; culled unless det > 0;
+ *   conic = (c, -b, a) / det (the (A, B, C) of the blend);
+ *   radius = ceil(3 sqrt(lmax)), lmax = mid + sqrt(max(0.1, mid^2 - det)), mid = (a + c) / 2;
+ *   culled if the radius square covers no tile of the W x H image (binning rule below);
+ *   colour_c = max(0, 0.5 + sum_{k < (deg+1)^2} Y_k(d) sh_i[k][c]), d the unit direction from
+ *       the camera centre -R^T t to m_i, Y_k the real spherical harmonics of degree <= 3 in the
+ *       order (l, m = -l..l) with the Condon-Shortley phase kept (band 1 is
+ *       sqrt(3/(4 pi)) (-y, z, -x)).
+ * A culled Gaussian gets radius 0 and zeros in every other output. Opacity needs no
+ * preprocessing and is passed to binning and blending as it is.
+ * ------------------------------------------------------------------------------------------- */
+typedef struct gsb_camera {
+    float R[9];               /* world-to-camera rotation, row-major */
+    float t[3];               /* world-to-camera translation: p = R m + t */
+    float fx, fy;             /* focal lengths, pixels (> 0) */
+    float cx, cy;             /* principal point, pixels (pixel (i, j) sits at (i, j)) */
+    int32_t width, height;    /* image size, [1, 65536] */
+    float near;               /* near plane (>= 0): Gaussians with p.z <= near are culled */
+} gsb_camera;
+
+/* means3d f32[n][3], scales f32[n][3] (per-axis standard deviations), quats f32[n][4] (w, x, y,
+ * z; 16-byte aligned; non-zero), sh f32[n][sh_coeffs][3] (16-byte aligned), all device.
+ * sh_degree in [0, 3] with (sh_degree + 1)^2 <= sh_coeffs <= 16: the first (sh_degree + 1)^2
+ * coefficients of each row are used (the whole row is read).
+ * camera: host pointer. Outputs (device, overwritten): means2d f32[n][2] (8-byte aligned),
+ * conics f32[n][3], depths f32[n], radii i32[n], colors f32[n][3].
+ * Computed in FP32. Errors: INVALID (null pointers when n > 0, n outside [0, 2^31), bad degree
+ * or coefficient count, a camera with non-positive or non-finite focal lengths, a negative or
+ * non-finite near plane, an image size outside [1, 65536], misaligned pointers), UNSUPPORTED,
+ * HIP. */
+gsb_status gsb_project(const float *means3d, const float *scales, const float *quats,
+                       const float *sh, int32_t sh_coeffs, int32_t sh_degree, int64_t n,
+                       const gsb_camera *camera, float *means2d, float *conics, float *depths,
+                       int32_t *radii, float *colors, void *stream);
 
 /* ---------------------------------------------------------------------------------------------
  * Binning: duplication with tile|depth keys, depth sort and per-tile ranges (paper §2.1(b)-(c);

@@ -236,9 +236,10 @@ def sh_basis(dirs, deg: int) -> np.ndarray:
 
 def project(scene3d: dict, sh_degree: int | None = None) -> dict[str, np.ndarray]:
     """Projection of 3D Gaussians to the screen in FP64 (rule in gsoracle.c): means2d, conics,
-    depths, radii, colors, plus rad_real (3 sqrt(lmax) before the ceiling) and margin (distance
-    of the culling decisions from their thresholds). sh [n][K][3]; sh_degree defaults to the
-    largest the stored K allows."""
+    depths, radii, colors, plus rad_real (3 sqrt(lmax) before the ceiling) and margin [n][3]
+    (distance of the depth, det and screen-rectangle decisions from their thresholds: relative,
+    relative, pixels; +inf where not reached). sh [n][K][3]; sh_degree defaults to the largest
+    the stored K allows."""
     lib = _load()
     m, sc, q = _f64(scene3d["means3d"]), _f64(scene3d["scales"]), _f64(scene3d["quats"])
     sh = _f64(scene3d["sh"])
@@ -249,7 +250,7 @@ def project(scene3d: dict, sh_degree: int | None = None) -> dict[str, np.ndarray
     cam = camera_array(scene3d["camera"])
     out = {"means2d": np.empty((n, 2)), "conics": np.empty((n, 3)), "depths": np.empty(n),
            "radii": np.empty(n, np.int32), "colors": np.empty((n, 3)), "rad_real": np.empty(n),
-           "margin": np.empty(n)}
+           "margin": np.empty((n, 3))}
     lib.orc_project(_ptr(m), _ptr(sc), _ptr(q), _ptr(sh), K, deg, n, _ptr(cam),
                     _ptr(out["means2d"]), _ptr(out["conics"]), _ptr(out["depths"]),
                     _ptr(out["radii"]), _ptr(out["colors"]), _ptr(out["rad_real"]),

@@ -491,9 +491,10 @@ void orc_sh_basis(const double *dirs, int64_t n, int32_t deg, double *out) {
  *   colour_c = max(0, 0.5 + sum_k Y_k(dir) sh[i][k][c]), dir = (m - o) / |m - o| with the
  *       camera centre o = -R^T t.
  * A culled Gaussian has radius 0 and every other output 0.
- * rad_real receives 3 sqrt(lmax) (before the ceiling) and margin the smallest distance of a
- * culling decision from its threshold (relative for the depth and det tests, in pixels for the
- * rectangle test), so a caller can tell which integers rounding may flip. */
+ * rad_real receives 3 sqrt(lmax) (before the ceiling) and margin[i][3] the distance of each
+ * culling decision from its threshold: |z - near| / near, det / (a c), and the distance in pixels
+ * of the means2d from the nearest edge of the rectangle test, so a caller can tell which integers
+ * rounding may flip (a decision not reached has margin +inf). */
 void orc_project(const double *means3d, const double *scales, const double *quats,
                  const double *sh, int32_t sh_coeffs, int32_t deg, int64_t n, const double *cam,
                  double *means2d, double *conics, double *depths, int32_t *radii,
@@ -516,9 +517,10 @@ void orc_project(const double *means3d, const double *scales, const double *quat
         depths[i] = 0.0;
         radii[i] = 0;
         rad_real[i] = 0.0;
+        margin[3 * i] = margin[3 * i + 1] = margin[3 * i + 2] = HUGE_VAL;
         double p[3];
         for (int r = 0; r < 3; ++r) p[r] = R[3 * r] * m[0] + R[3 * r + 1] * m[1] + R[3 * r + 2] * m[2] + t[r];
-        margin[i] = fabs(p[2] - near) / fmax(fabs(near), 1e-30);
+        margin[3 * i] = fabs(p[2] - near) / fmax(fabs(near), 1e-30);
         if (!(p[2] > near)) continue;
         const double u = fx * p[0] / p[2] + cx, v = fy * p[1] / p[2] + cy;
         /* Sigma3 */
@@ -552,7 +554,7 @@ void orc_project(const double *means3d, const double *scales, const double *quat
             }
         const double a = S2[0][0] + 0.3, b = S2[0][1], c = S2[1][1] + 0.3;
         const double det = a * c - b * b;
-        margin[i] = fmin(margin[i], fabs(det) / fmax(a * c, 1e-300));
+        margin[3 * i + 1] = fabs(det) / fmax(a * c, 1e-300);
         if (!(det > 0.0)) continue;
         const double mid = 0.5 * (a + c);
         const double lmax = mid + sqrt(fmax(0.1, mid * mid - det));
@@ -563,7 +565,7 @@ void orc_project(const double *means3d, const double *scales, const double *quat
         tile_rect(u, v, r, gx, gy, &tx0, &tx1, &ty0, &ty1);
         const double em = fmin(fmin(fabs(u + r - 1.0), fabs(u - r - (double)(ORC_TILE * gx))),
                                fmin(fabs(v + r - 1.0), fabs(v - r - (double)(ORC_TILE * gy))));
-        margin[i] = fmin(margin[i], em);
+        margin[3 * i + 2] = em;
         rad_real[i] = rr;
         if (tx1 <= tx0 || ty1 <= ty0) continue;
         means2d[2 * i] = u;

@@ -31,9 +31,17 @@ GSB_LAUNCH_PERSISTENT = 0
 GSB_LAUNCH_GRID = 1
 
 # every function declared in include/gsblend.h
-EXPORTS = ("gsb_abi_version", "gsb_last_error", "gsb_bin_workspace_bytes", "gsb_bin_count",
+EXPORTS = ("gsb_abi_version", "gsb_last_error", "gsb_project", "gsb_bin_workspace_bytes",
+           "gsb_bin_count",
            "gsb_bin_fill", "gsb_blend_forward", "gsb_blend_backward", "gsb_plan_create",
            "gsb_plan_destroy", "gsb_blend_batched_forward", "gsb_blend_batched_backward")
+
+
+class GsbCamera(ctypes.Structure):
+    """struct gsb_camera: pinhole camera (host struct)."""
+    _fields_ = [("R", ctypes.c_float * 9), ("t", ctypes.c_float * 3), ("fx", ctypes.c_float),
+                ("fy", ctypes.c_float), ("cx", ctypes.c_float), ("cy", ctypes.c_float),
+                ("width", ctypes.c_int32), ("height", ctypes.c_int32), ("near", ctypes.c_float)]
 
 
 class GsbView(ctypes.Structure):
@@ -78,6 +86,8 @@ def load() -> ctypes.CDLL:
     lib.gsb_abi_version.restype = i32
     lib.gsb_last_error.argtypes = []
     lib.gsb_last_error.restype = ctypes.c_char_p
+    lib.gsb_project.argtypes = [P, P, P, P, i32, i32, i64, ctypes.POINTER(GsbCamera), P, P, P,
+                                P, P, P]
     lib.gsb_bin_workspace_bytes.argtypes = [i64, i64, i32, i32, ctypes.POINTER(sz)]
     lib.gsb_bin_count.argtypes = [P, P, P, P, i32, i64, i32, i32, P, sz, P, P]
     lib.gsb_bin_fill.argtypes = [P, P, P, P, i32, P, i64, i32, i32, P, sz, P, i64, P, P, P]
@@ -113,6 +123,14 @@ def gsb_abi_version() -> int:
 
 def gsb_last_error() -> str:
     return load().gsb_last_error().decode()
+
+
+def gsb_project(means3d: int, scales: int, quats: int, sh: int, sh_coeffs: int, sh_degree: int,
+                n: int, camera: GsbCamera, means2d: int, conics: int, depths: int, radii: int,
+                colors: int, stream: int = 0) -> None:
+    _check(load().gsb_project(means3d, scales, quats, sh, sh_coeffs, sh_degree, n,
+                              ctypes.byref(camera), means2d, conics, depths, radii, colors,
+                              stream))
 
 
 def gsb_bin_workspace_bytes(n: int, pair_capacity: int, W: int, H: int) -> int:

@@ -37,6 +37,52 @@ def prec_code(prec) -> int:
     return int(prec)
 
 
+def camera_struct(R, t, fx, fy, cx, cy, width, height, near=0.2) -> _lib.GsbCamera:
+    """A gsb_camera from a world-to-camera rotation R (3x3, row-major) and translation t."""
+    c = _lib.GsbCamera()
+    flat = [float(v) for row in R for v in row]
+    if len(flat) != 9 or len(t) != 3:
+        raise ValueError("R must be 3x3 and t of length 3")
+    c.R[:] = flat
+    c.t[:] = [float(v) for v in t]
+    c.fx, c.fy, c.cx, c.cy = float(fx), float(fy), float(cx), float(cy)
+    c.width, c.height, c.near = int(width), int(height), float(near)
+    return c
+
+
+def _camera(cam) -> _lib.GsbCamera:
+    if isinstance(cam, _lib.GsbCamera):
+        return cam
+    return camera_struct(cam.R, cam.t, cam.fx, cam.fy, cam.cx, cam.cy, cam.width, cam.height,
+                         cam.near)
+
+
+def project(means3d, scales, quats, sh, camera, sh_degree=None, stream=None, out=None):
+    """Preprocessing: 3D Gaussians (means3d f32[n][3], scales f32[n][3], quats f32[n][4] as
+    (w, x, y, z), sh f32[n][K][3]) seen by ``camera`` (a GsbCamera, or any object with R, t, fx,
+    fy, cx, cy, width, height, near) -> (means2d [n][2], conics [n][3], depths [n], radii i32[n],
+    colors [n][3]). sh_degree defaults to the largest that K coefficients hold."""
+    for t_, nm in ((means3d, "means3d"), (scales, "scales"), (quats, "quats"), (sh, "sh")):
+        _req(t_, torch.float32, nm)
+    n = means3d.shape[0]
+    if sh.dim() != 3 or sh.shape[0] != n or sh.shape[2] != 3:
+        raise ValueError("sh must be [n][K][3]")
+    K = sh.shape[1]
+    deg = int(round(K ** 0.5)) - 1 if sh_degree is None else int(sh_degree)
+    dev = means3d.device
+    if out is None:
+        out = (torch.empty((n, 2), dtype=torch.float32, device=dev),
+               torch.empty((n, 3), dtype=torch.float32, device=dev),
+               torch.empty((n,), dtype=torch.float32, device=dev),
+               torch.empty((n,), dtype=torch.int32, device=dev),
+               torch.empty((n, 3), dtype=torch.float32, device=dev))
+    m2, con, dep, rad, col = out
+    _lib.gsb_project(means3d.data_ptr(), scales.data_ptr(), quats.data_ptr(), sh.data_ptr(), K,
+                     deg, n, _camera(camera), m2.data_ptr(), con.data_ptr(), dep.data_ptr(),
+                     rad.data_ptr(), col.data_ptr(), _stream(stream))
+    return m2, con, dep, rad, col
+
+
 class BinWorkspace:
     """Device workspace of the binning calls, sized for (n, pair_capacity, W, H)."""
 

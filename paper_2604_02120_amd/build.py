@@ -16,7 +16,7 @@ PKG = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(PKG, "csrc")
 BUILD = os.path.join(PKG, "_build")
 LIB = os.path.join(PKG, "libgsblend.so")
-SOURCES = ["capi.hip", "bin.hip", "blend.hip"]
+SOURCES = ["capi.hip", "bin.hip", "blend.hip", "project.hip"]
 # per-file extras: the blend kernels never produce NaN from in-contract inputs (-inf is used, NaN
 # never), so min/max need no NaN canonicalisation
 EXTRA = {"blend.hip": ["-fno-honor-nans"]}

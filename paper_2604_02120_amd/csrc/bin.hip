@@ -226,27 +226,6 @@ void launch_scan(T *data, int64_t m, T *partial, unsigned long long *total_a, lo
     if (down && nb > 0) k_scan_down<T><<<dim3(unsigned(nb)), kScanThreads, 0, s>>>(data, data, m, partial);
 }
 
-// ------------------------------------------------------------------------------- tile rectangle
-// Covered tiles [tx0, tx1) x [ty0, ty1) of a Gaussian at (x, y) with radius r: tx in
-// [floor((x - r)/16), floor((x + r + 15)/16)) clamped to [0, gx], same for y. With x = ix + f,
-// 0 <= f < 1, and r an integer, floor((x - r)/16) = floor((ix - r)/16) = (ix - r) >> 4 exactly.
-struct Rect { int32_t tx0, tx1, ty0, ty1; };
-
-__device__ inline int64_t clampi(int64_t v, int64_t lo, int64_t hi) { return v < lo ? lo : (v > hi ? hi : v); }
-
-__device__ inline Rect tile_rect(float x, float y, int32_t r, int32_t gx, int32_t gy) {
-    Rect R{0, 0, 0, 0};
-    if (r <= 0) return R;
-    // |x|, |y| < 2^24 by contract; the clamp only keeps the integer conversion defined otherwise
-    const int64_t ix = int64_t(floorf(fminf(fmaxf(x, -16777216.f), 16777216.f)));
-    const int64_t iy = int64_t(floorf(fminf(fmaxf(y, -16777216.f), 16777216.f)));
-    R.tx0 = int32_t(clampi((ix - r) >> 4, 0, gx));
-    R.tx1 = int32_t(clampi((ix + r + kTile - 1) >> 4, 0, gx));
-    R.ty0 = int32_t(clampi((iy - r) >> 4, 0, gy));
-    R.ty1 = int32_t(clampi((iy + r + kTile - 1) >> 4, 0, gy));
-    return R;
-}
-
 // ------------------------------------------------------------------------------- mode 1
 // Binning mode 1 keeps a pair (tile, Gaussian) of the 3-sigma rectangle only when the Gaussian can
 // reach alpha >= 1/255 on a pixel of the tile inside the image (opacity-aware extent, a tighter

@@ -2,6 +2,7 @@
 // error strings, and dispatch to the binning and blending launchers.
 #include <hip/hip_runtime.h>
 
+#include <math.h>
 #include <stdarg.h>
 #include <stdio.h>
 #include <string.h>
@@ -100,6 +101,59 @@ extern "C" {
 int32_t gsb_abi_version(void) { return GSB_ABI_VERSION; }
 
 const char *gsb_last_error(void) { return g_err; }
+
+gsb_status gsb_project(const float *means3d, const float *scales, const float *quats,
+                       const float *sh, int32_t sh_coeffs, int32_t sh_degree, int64_t n,
+                       const gsb_camera *camera, float *means2d, float *conics, float *depths,
+                       int32_t *radii, float *colors, void *stream) {
+    g_err[0] = '\0';
+    GSB_REQUIRE(n >= 0 && n < (int64_t(1) << 31), "n = %lld outside [0, 2^31)", (long long)n);
+    GSB_REQUIRE(sh_degree >= 0 && sh_degree <= 3, "sh_degree = %d outside [0, 3]", int(sh_degree));
+    GSB_REQUIRE(sh_coeffs >= (sh_degree + 1) * (sh_degree + 1) && sh_coeffs <= 16,
+                "sh_coeffs = %d outside [%d, 16]", int(sh_coeffs), (sh_degree + 1) * (sh_degree + 1));
+    GSB_REQUIRE(camera != nullptr, "camera must be a non-null host pointer");
+    const gsb_camera &c = *camera;
+    GSB_TRY(check_dims(c.width, c.height));
+    GSB_REQUIRE(isfinite(c.fx) && isfinite(c.fy) && c.fx > 0.0f && c.fy > 0.0f,
+                "focal lengths must be finite and positive");
+    GSB_REQUIRE(isfinite(c.near) && c.near >= 0.0f, "near plane must be finite and >= 0");
+    GSB_REQUIRE(n == 0 || (means3d && scales && quats && sh && means2d && conics && depths &&
+                           radii && colors),
+                "array pointers must be non-null");
+    GSB_REQUIRE(aligned(quats, 16) && aligned(sh, 16), "quats and sh must be 16-byte aligned");
+    GSB_REQUIRE(aligned(means2d, 8), "means2d must be 8-byte aligned");
+    GSB_REQUIRE(aligned(means3d, 4) && aligned(scales, 4) && aligned(conics, 4) &&
+                    aligned(depths, 4) && aligned(radii, 4) && aligned(colors, 4),
+                "arrays must be 4-byte aligned");
+    GSB_TRY(check_device());
+    ProjectArgs a{};
+    a.means3d = means3d;
+    a.scales = scales;
+    a.quats = quats;
+    a.sh = sh;
+    a.n = n;
+    a.deg = sh_degree;
+    for (int k = 0; k < 9; ++k) a.cam.R[k] = c.R[k];
+    for (int k = 0; k < 3; ++k) a.cam.t[k] = c.t[k];
+    a.cam.fx = c.fx;
+    a.cam.fy = c.fy;
+    a.cam.cx = c.cx;
+    a.cam.cy = c.cy;
+    a.cam.limx = float(1.3 * (double(c.width) / (2.0 * double(c.fx))));
+    a.cam.limy = float(1.3 * (double(c.height) / (2.0 * double(c.fy))));
+    a.cam.near = c.near;
+    for (int k = 0; k < 3; ++k)
+        a.cam.o[k] = float(-(double(c.R[k]) * c.t[0] + double(c.R[3 + k]) * c.t[1] +
+                             double(c.R[6 + k]) * c.t[2]));
+    a.cam.gx = int32_t(grid_x(c.width));
+    a.cam.gy = int32_t(grid_y(c.height));
+    a.means2d = means2d;
+    a.conics = conics;
+    a.depths = depths;
+    a.radii = radii;
+    a.colors = colors;
+    return project(a, sh_coeffs, static_cast<hipStream_t>(stream));
+}
 
 gsb_status gsb_bin_workspace_bytes(int64_t n, int64_t pair_capacity, int32_t W, int32_t H,
                                    size_t *bytes) {

@@ -34,6 +34,28 @@ __device__ inline int64_t xcd_tile(int64_t block, int64_t n_tiles) {
     return (block % kXcds) * chunk + block / kXcds;
 }
 
+// Covered tiles [tx0, tx1) x [ty0, ty1) of a Gaussian at (x, y) with radius r: tx in
+// [floor((x - r)/16), floor((x + r + 15)/16)) clamped to [0, gx], same for y. With x = ix + f,
+// 0 <= f < 1, and r an integer, floor((x - r)/16) = floor((ix - r)/16) = (ix - r) >> 4 exactly.
+// Used by binning (the pairs to emit) and by preprocessing (a Gaussian whose rectangle is empty
+// is culled).
+struct Rect { int32_t tx0, tx1, ty0, ty1; };
+
+__device__ inline int64_t clampi(int64_t v, int64_t lo, int64_t hi) { return v < lo ? lo : (v > hi ? hi : v); }
+
+__device__ inline Rect tile_rect(float x, float y, int32_t r, int32_t gx, int32_t gy) {
+    Rect R{0, 0, 0, 0};
+    if (r <= 0) return R;
+    // |x|, |y| < 2^24 by contract; the clamp only keeps the integer conversion defined otherwise
+    const int64_t ix = int64_t(floorf(fminf(fmaxf(x, -16777216.f), 16777216.f)));
+    const int64_t iy = int64_t(floorf(fminf(fmaxf(y, -16777216.f), 16777216.f)));
+    R.tx0 = int32_t(clampi((ix - r) >> 4, 0, gx));
+    R.tx1 = int32_t(clampi((ix + r + kTile - 1) >> 4, 0, gx));
+    R.ty0 = int32_t(clampi((iy - r) >> 4, 0, gy));
+    R.ty1 = int32_t(clampi((iy + r + kTile - 1) >> 4, 0, gy));
+    return R;
+}
+
 // ---- binning (bin.hip)
 size_t bin_workspace_bytes(int64_t n, int64_t pair_capacity, int64_t n_tiles);
 gsb_status bin_count(const float *means2d, const int32_t *radii, const float *conics,
@@ -43,6 +65,26 @@ gsb_status bin_fill(const float *means2d, const int32_t *radii, const float *con
                     const float *opacity, int32_t mode, const float *depths, int64_t n, int32_t W,
                     int32_t H, void *ws, uint32_t *point_list, int64_t pair_capacity,
                     uint32_t *ranges, int32_t *status_dev, hipStream_t s);
+
+// ---- preprocessing (project.hip)
+struct ProjectCam {
+    float R[9], t[3];        // world to camera: p = R m + t (R row-major)
+    float fx, fy, cx, cy;
+    float limx, limy;        // clamp of x/z and y/z in the Jacobian: 1.3 W / (2 fx), 1.3 H / (2 fy)
+    float near;
+    float o[3];              // camera centre -R^T t (world)
+    int32_t gx, gy;          // tile grid
+};
+struct ProjectArgs {
+    const float *means3d, *scales, *quats, *sh;
+    int64_t n;
+    int32_t deg, pad;
+    ProjectCam cam;
+    float *means2d, *conics, *depths;
+    int32_t *radii;
+    float *colors;
+};
+gsb_status project(const ProjectArgs &a, int32_t sh_coeffs, hipStream_t s);
 
 // ---- blending (blend.hip)
 // Everything one tile launch needs about one view (image): geometry, inputs, outputs. Built on the

@@ -36,7 +36,41 @@ def test_library_exports_every_declared_symbol():
 
 
 def test_abi_version():
-    assert _lib.gsb_abi_version() == 2
+    assert _lib.gsb_abi_version() == 3
+
+
+def test_project_validation_before_device():
+    ok = 256   # non-null, 16-byte aligned fake address: validation fails before any use
+    from paper_2604_02120_amd import api
+    cam = api.camera_struct(((1, 0, 0), (0, 1, 0), (0, 0, 1)), (0, 0, 0), 500, 500, 32, 24, 64, 48)
+
+    def bad(frag, *args, camera=cam):
+        defaults = dict(means3d=ok, scales=ok, quats=ok, sh=ok, sh_coeffs=16, sh_degree=3, n=10)
+        defaults.update(dict(args))
+        with pytest.raises(_lib.GsbError) as e:
+            _lib.gsb_project(defaults["means3d"], defaults["scales"], defaults["quats"],
+                             defaults["sh"], defaults["sh_coeffs"], defaults["sh_degree"],
+                             defaults["n"], camera, ok, ok, ok, ok, ok)
+        assert e.value.status == _lib.GSB_ERR_INVALID and frag in str(e.value), str(e.value)
+
+    bad("n = -1", ("n", -1))
+    bad("n = ", ("n", 1 << 31))
+    bad("sh_degree", ("sh_degree", 4))
+    bad("sh_degree", ("sh_degree", -1))
+    bad("sh_coeffs", ("sh_coeffs", 8))           # degree 3 needs 16
+    bad("sh_coeffs", ("sh_coeffs", 17), ("sh_degree", 0))
+    bad("non-null", ("means3d", 0))
+    bad("16-byte", ("quats", ok + 4))
+    bad("16-byte", ("sh", ok + 8))
+    for field, val, frag in (("fx", 0.0, "focal"), ("fy", float("nan"), "focal"),
+                             ("near", -1.0, "near"), ("width", 0, "image size"),
+                             ("height", 70000, "image size")):
+        c = api.camera_struct(((1, 0, 0), (0, 1, 0), (0, 0, 1)), (0, 0, 0), 500, 500, 32, 24, 64, 48)
+        setattr(c, field, val)
+        bad(frag, camera=c)
+    with pytest.raises(_lib.GsbError) as e:     # camera = NULL
+        _lib._check(_lib.load().gsb_project(ok, ok, ok, ok, 16, 3, 10, None, ok, ok, ok, ok, ok, 0))
+    assert "camera" in str(e.value)
 
 
 def test_no_oracle_in_library():

@@ -249,7 +249,7 @@ def test_project_culling():
     for i in range(n):
         r = math.ceil(out["rad_real"][i])
         x, y = u[i], v[i]
-        if out["margin"][i] < 1e-6:
+        if out["margin"][i, 2] < 1e-6:
             continue
         hit = any(16 * tx <= x + r - 1 and 16 * (tx + 1) > x - r for tx in range(gx)) and \
             any(16 * ty <= y + r - 1 and 16 * (ty + 1) > y - r for ty in range(gy))
