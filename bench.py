@@ -43,6 +43,7 @@ FLOPS = {"forward": (16, 10), "backward": (16, 39)}
 COUNTS = os.path.join(ROOT, "tests", "golden", "workload_counts.json")
 TRAFFIC = os.path.join(ROOT, "profiles", "traffic.json")
 KERNEL_SRC = os.path.join(ROOT, "paper_2604_02120_amd", "csrc", "blend.hip")
+PROJECT_SRC = os.path.join(ROOT, "paper_2604_02120_amd", "csrc", "project.hip")
 
 
 def parse():
@@ -60,6 +61,8 @@ def parse():
                    help="skip the step with visible-tile binning")
     p.add_argument("--no-pipeline", action="store_true",
                    help="skip the leg that starts from 3D Gaussians (projection + the step)")
+    p.add_argument("--pipeline-only", action="store_true",
+                   help="run only the leg that starts from 3D Gaussians and print its JSON object")
     p.add_argument("--sweep", action="store_true",
                    help="instead of the benchmark line: sensitivity sweeps of the LDS batch size "
                         "and of the resolution (1x, 2x, 3x), GEMM form vs plain FP32")
@@ -310,6 +313,11 @@ def time_pipeline(dev, prec: str, steps: int, warmup: int) -> dict:
     kern_ms = float(np.median(kern))
     nbytes = n * (40 + 12 * K + 40)
     gbs = nbytes / (kern_ms * 1e-3) / 1e9
+    traffic = None                  # HBM bytes per launch from the counters, if they are current
+    if os.path.exists(TRAFFIC):
+        ent = json.load(open(TRAFFIC)).get("project")
+        if ent and ent.get("kernel_sha") == kernel_hash(PROJECT_SRC):
+            traffic = ent["bytes_per_launch"]
     return {"workload": "1M 3D Gaussians, SH degree 3, 1920x1080 camera", "precision": prec,
             "visible": int((rad > 0).sum().item()), "pairs": fr.pairs,
             "ms_per_step": round(1e3 * wall / steps, 4),
@@ -319,7 +327,7 @@ def time_pipeline(dev, prec: str, steps: int, warmup: int) -> dict:
             "fwd_ms": round(ms(2, 3), 4), "bwd_ms": round(ms(3, 4), 4),
             "project_roofline": {"bound": "hbm", "achieved": round(gbs, 1), "peak": 8000.0,
                                  "unit": "GB/s", "frac": round(gbs / 8000.0, 4),
-                                 "bytes_per_gaussian": 40 + 12 * K + 40}}
+                                 "traffic": traffic, "bytes_per_gaussian": 40 + 12 * K + 40}}
 
 
 def run_sweeps(dev, steps: int, warmup: int) -> dict:
@@ -376,8 +384,8 @@ def run_sweeps(dev, steps: int, warmup: int) -> dict:
     return out
 
 
-def kernel_hash() -> str:
-    return hashlib.sha256(open(KERNEL_SRC, "rb").read()).hexdigest()[:16]
+def kernel_hash(src: str = None) -> str:
+    return hashlib.sha256(open(src or KERNEL_SRC, "rb").read()).hexdigest()[:16]
 
 
 def roofline(res: dict, counts: dict) -> dict:
@@ -456,6 +464,10 @@ def main():
         dst.copy_(src)
         torch.cuda.synchronize()
         del src, dst
+    if args.pipeline_only:
+        print(json.dumps({"pipeline_3d": time_pipeline(dev, args.precs.split(",")[0], args.steps,
+                                                       args.warmup)}), flush=True)
+        return
     cfg = gsinputs.CONFIGS[args.config]
     fr = Frame(cfg, dev)
     counts = json.load(open(COUNTS))[args.config]
