@@ -119,12 +119,13 @@ struct StageBwd {
 
 constexpr int kGrad = 9;   // per-Gaussian sums kept per batch
 
-// Per-Gaussian gradient sums of the current batch: 9 words per staged Gaussian (an odd stride,
-// so the flush's per-thread reads of one word index hit distinct banks).
+// Per-Gaussian gradient sums of a batch: 9 words per staged Gaussian (an odd stride, so the
+// flush's per-thread reads of one word index hit distinct banks). Two buffers: batch b sums into
+// buffer b & 1 while batch b + 1's sums are flushed from the other.
 template <int NB>
 struct BwdAcc {
-    float v[NB * kGrad];
-    __device__ float *slot(int t) { return v + t * kGrad; }
+    float v[2][NB * kGrad];
+    __device__ float *slot(int ab, int t) { return v[ab] + t * kGrad; }
 };
 
 // Raw attributes of one list entry, fetched in the prefetch step.
@@ -149,24 +150,34 @@ __device__ inline float quad_acc(float A, float B, float C, float dx, float dy, 
     return fmaf(dx, gx, __fmul_rn(dy, gy));
 }
 
-// An index >= n (an inconsistent list) is treated as an empty slot rather than dereferenced.
-__device__ inline GRaw fetch(const uint32_t *plist, int64_t pos, bool valid, uint32_t n,
-                             const float2 *means, const F3 *conics, const float *opac,
-                             const F3 *colors) {
+// A list entry (Gaussian index) loaded ahead of its use. The load is unconditional (an invalid
+// slot reads the list's entry `fallback`, which exists) and validity is applied only at the use,
+// so that nothing waits for the load before then.
+constexpr uint32_t kNoEntry = 0xffffffffu;
+struct Entry {
+    uint32_t raw;
+    bool valid;
+    __device__ uint32_t id() const { return valid ? raw : kNoEntry; }
+};
+__device__ inline Entry load_entry(const uint32_t *plist, int64_t pos, bool valid, int64_t fallback) {
+    return Entry{plist[valid ? pos : fallback], valid};
+}
+
+// Attributes of the Gaussian `id` (from load_entry). Needs n > 0. An index >= n (kNoEntry, or an
+// inconsistent list) gives an invalid entry, which stage() makes inert; its loads read Gaussian 0
+// instead, so that no load is conditional: the loads of a batch stay in flight until the batch
+// is staged, with no copies of their results (and no waits for them) in between.
+__device__ inline GRaw fetch_attrs(uint32_t id, uint32_t n, const float2 *means, const F3 *conics,
+                                   const float *opac, const F3 *colors) {
     GRaw g;
-    g.id = valid ? plist[pos] : 0u;
-    valid = valid && g.id < n;
-    g.valid = valid;
-    if (valid) {
-        const float2 m = means[g.id];
-        const F3 c = conics[g.id];
-        const F3 col = colors[g.id];
-        g.x = m.x; g.y = m.y; g.A = c.a; g.B = c.b; g.C = c.c;
-        g.o = opac[g.id];
-        g.r = col.a; g.g = col.b; g.b = col.c;
-    } else {
-        g.id = 0; g.x = g.y = g.A = g.B = g.C = g.o = g.r = g.g = g.b = 0.f;
-    }
+    g.valid = id < n;
+    g.id = g.valid ? id : 0u;
+    const float2 m = means[g.id];
+    const F3 c = conics[g.id];
+    const F3 col = colors[g.id];
+    g.x = m.x; g.y = m.y; g.A = c.a; g.B = c.b; g.C = c.c;
+    g.o = opac[g.id];
+    g.r = col.a; g.g = col.b; g.b = col.c;
     return g;
 }
 
@@ -347,20 +358,31 @@ __device__ inline void fwd_tile(const ViewDesc &v, int64_t tile, Stage<M, NB> &S
         if constexpr (M != Mode::Plain) S.zero = Op<M>::cvt(z);
     }
     const uint2 rg = reinterpret_cast<const uint2 *>(v.ranges)[tile];
-    const int64_t start = rg.x, len = int64_t(rg.y) - int64_t(rg.x);
+    // without Gaussians every list entry would be invalid: the tile shows the background
+    const int64_t start = rg.x, len = n == 0 ? 0 : int64_t(rg.y) - int64_t(rg.x);
     const int nb = int((len + NB - 1) / NB);
 
+    // list entries are loaded two batches ahead and attributes one batch ahead, so that neither
+    // load waits on the other within an iteration
+    const auto entry = [&](int bb) {          // batch bb's entry for this thread (bb < nb + 2)
+        const int64_t o = int64_t(bb) * NB + L.t;
+        return load_entry(plist, start + o, L.t < NB && o < len, start);
+    };
     FwdState st{1.f, 0.f, 0.f, 0.f, L.inside ? kQCull : INFINITY, 0};
-    GRaw nxt = fetch(plist, start + L.t, L.t < NB && L.t < len, n, means, conics, opac, colors);
+    GRaw nxt{};
+    Entry ent{kNoEntry, false};
+    if (nb > 0) {                               // (len > 0, so entry `start` exists)
+        nxt = fetch_attrs(entry(0).id(), n, means, conics, opac, colors);
+        ent = entry(1);
+    }
     for (int b = 0; b < nb; ++b) {
         const int buf = b & 1;
         if (L.t < NB) stage<M, NB, false>(nxt, buf, L.t, xc, yc, S, nullptr);
         // barrier; also counts the pixels still live (the whole block leaves once none is)
         if (__syncthreads_count(st.thr != INFINITY) == 0) break;
-        if (b + 1 < nb) {
-            const int64_t o = int64_t(b + 1) * NB + L.t;
-            nxt = fetch(plist, start + o, L.t < NB && o < len, n, means, conics, opac, colors);
-        }
+        // unconditional: past the last batch these read entry `start` and Gaussian 0, unused
+        nxt = fetch_attrs(ent.id(), n, means, conics, opac, colors);
+        ent = entry(b + 2);
         const int base = b * NB;
         const int ng = int((len - base + kGroup - 1) / kGroup) < kGroups
                            ? int((len - base + kGroup - 1) / kGroup) : kGroups;
@@ -504,6 +526,7 @@ __device__ inline void bwd_tile(const ViewDesc &v, int64_t tile, Stage<M, NB> &S
         if constexpr (M != Mode::Plain) S.zero = Op<M>::cvt(z);
         s_maxlast = 0;
     }
+    if (n == 0) return;            // no Gaussian, no gradient (uniform: every thread returns)
     BwdState st{1.f, 1.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0};
     if (L.inside) {
         const int64_t p = int64_t(L.py) * v.W + int64_t(L.px);
@@ -524,23 +547,52 @@ __device__ inline void bwd_tile(const ViewDesc &v, int64_t tile, Stage<M, NB> &S
     const int nb = int((len + NB - 1) / NB);
     if (nb == 0) return;
 
-    GRaw nxt;
-    {
-        const int64_t o = int64_t(nb - 1) * NB + L.t;
-        nxt = fetch(plist, start + o, L.t < NB && o < len, n, means, conics, opac, colors);
-    }
+    // Memory operations of a batch are issued before its compute: the attribute loads of the next
+    // batch, the list entries of the one after, and the global atomics that flush the previous
+    // batch's sums (from the other accumulator buffer). Every wait at the top of an iteration is
+    // then for operations issued a whole compute phase earlier; with the flush after the compute,
+    // the next wait (the memory counter also counts atomics) would expose their latency.
+    const auto entry = [&](int bb) {          // batch bb's entry for this thread (bb may be < 0)
+        const int64_t o = int64_t(bb) * NB + L.t;
+        return load_entry(plist, start + o, bb >= 0 && L.t < NB && o < len, start);
+    };
+    const auto flush = [&](int bb) {     // batch bb's sums, accumulator buffer bb & 1
+        if (L.t >= NB) return;
+        float a9[kGrad];
+        const float *src = s_acc.slot(bb & 1, L.t);
+#pragma unroll
+        for (int k = 0; k < kGrad; ++k) a9[k] = src[k];
+        bool any = false;
+#pragma unroll
+        for (int k = 0; k < kGrad; ++k) any |= a9[k] != 0.f;
+        if (any) {
+            const uint32_t id = __float_as_uint(SB.bwd[bb & 1][L.t].w);
+            unsafeAtomicAdd(&v.dL_dconics[3 * id + 0], a9[0]);
+            unsafeAtomicAdd(&v.dL_dconics[3 * id + 1], a9[1]);
+            unsafeAtomicAdd(&v.dL_dconics[3 * id + 2], a9[2]);
+            unsafeAtomicAdd(&v.dL_dmeans2d[2 * id + 0], a9[3]);
+            unsafeAtomicAdd(&v.dL_dmeans2d[2 * id + 1], a9[4]);
+            unsafeAtomicAdd(&v.dL_dopacity[id], a9[5]);
+            unsafeAtomicAdd(&v.dL_dcolors[3 * id + 0], a9[6]);
+            unsafeAtomicAdd(&v.dL_dcolors[3 * id + 1], a9[7]);
+            unsafeAtomicAdd(&v.dL_dcolors[3 * id + 2], a9[8]);
+        }
+    };
+    GRaw nxt = fetch_attrs(entry(nb - 1).id(), n, means, conics, opac, colors);
+    Entry ent = entry(nb - 2);
     for (int b = nb - 1; b >= 0; --b) {
         const int buf = b & 1;
         if (L.t < NB) {
             stage<M, NB, true>(nxt, buf, L.t, xc, yc, S, &SB);
+            float *z = s_acc.slot(buf, L.t);
 #pragma unroll
-            for (int k = 0; k < kGrad; ++k) s_acc.slot(L.t)[k] = 0.f;
+            for (int k = 0; k < kGrad; ++k) z[k] = 0.f;
         }
         __syncthreads();
-        if (b > 0) {
-            const int64_t o = int64_t(b - 1) * NB + L.t;
-            nxt = fetch(plist, start + o, L.t < NB && o < len, n, means, conics, opac, colors);
-        }
+        // unconditional: before the first batch these read entry `start` and Gaussian 0, unused
+        nxt = fetch_attrs(ent.id(), n, means, conics, opac, colors);
+        ent = entry(b - 2);
+        if (b + 1 < nb) flush(b + 1);
         const int base = b * NB;
         const int ng = int((len - base + kGroup - 1) / kGroup) < kGroups
                            ? int((len - base + kGroup - 1) / kGroup) : kGroups;
@@ -549,7 +601,7 @@ __device__ inline void bwd_tile(const ViewDesc &v, int64_t tile, Stage<M, NB> &S
             if (__ballot(st.last > base + g * kGroup) == 0) continue;
             const float4 ga = S.attr[buf][g * kGroup + (L.l & (kGroup - 1))];
             const float4 gb = SB.bwd[buf][g * kGroup + (L.l & (kGroup - 1))];
-            float *acc = s_acc.slot(g * kGroup);
+            float *acc = s_acc.slot(buf, g * kGroup);
             const int rel = st.last - (base + g * kGroup);   // positions < last are in range
             // the whole group is in range for every lane (the common case once past the lanes'
             // last contributors; never for a partial tile, whose outside lanes have last = 0)
@@ -579,32 +631,12 @@ __device__ inline void bwd_tile(const ViewDesc &v, int64_t tile, Stage<M, NB> &S
                 }
             }
         }
-        // flush: thread t owns staged Gaussian t's sums (a Gaussian with no live pair in this
-        // tile has all-zero sums and costs no atomics)
-        __syncthreads();
-        if (L.t < NB) {
-            float a9[kGrad];
-#pragma unroll
-            for (int k = 0; k < kGrad; ++k) a9[k] = s_acc.slot(L.t)[k];
-            bool any = false;
-#pragma unroll
-            for (int k = 0; k < kGrad; ++k) any |= a9[k] != 0.f;
-            if (any) {
-                const uint32_t id = __float_as_uint(SB.bwd[buf][L.t].w);
-                unsafeAtomicAdd(&v.dL_dconics[3 * id + 0], a9[0]);
-                unsafeAtomicAdd(&v.dL_dconics[3 * id + 1], a9[1]);
-                unsafeAtomicAdd(&v.dL_dconics[3 * id + 2], a9[2]);
-                unsafeAtomicAdd(&v.dL_dmeans2d[2 * id + 0], a9[3]);
-                unsafeAtomicAdd(&v.dL_dmeans2d[2 * id + 1], a9[4]);
-                unsafeAtomicAdd(&v.dL_dopacity[id], a9[5]);
-                unsafeAtomicAdd(&v.dL_dcolors[3 * id + 0], a9[6]);
-                unsafeAtomicAdd(&v.dL_dcolors[3 * id + 1], a9[7]);
-                unsafeAtomicAdd(&v.dL_dcolors[3 * id + 2], a9[8]);
-            }
-        }
-        // the next iteration stages into the other buffer and re-zeroes slot t (program order
-        // after this read); the buffer read here is rewritten two iterations later
+        // Buffers: the next iteration stages into the other stage buffer and zeroes its own slot
+        // of the other accumulator buffer, whose batch (b + 1) this thread flushed above; the
+        // compute's LDS adds into either accumulator buffer are ordered by the barrier.
     }
+    __syncthreads();
+    flush(0);
 }
 
 // ------------------------------------------------------------------------------- kernels
