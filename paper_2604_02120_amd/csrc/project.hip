@@ -11,6 +11,8 @@
 // per instruction) into LDS, then each lane reads its row from there. Rows sit in LDS at a stride
 // of an odd number of float4s (or of dwords, when a row is not a whole number of float4s), so the
 // lanes' reads fall on distinct banks.
+#include <type_traits>
+
 #include "gsb_internal.h"
 
 namespace gsb {
@@ -26,6 +28,13 @@ struct ShLayout {
     static constexpr bool kVec = (kDw % 4) == 0;      // rows are whole float4s
     static constexpr int kQuads = kDw / 4;
     static constexpr int kStride = kVec ? 4 * (kQuads | 1) : (kDw | 1);   // LDS dwords per row
+    // elements each lane moves: float4s (vector path) or dwords
+    static constexpr int kIt = kVec ? kQuads : kDw;
+    // rows go through LDS in two passes of 32 when 64 of them would take more than 8 KB, which
+    // halves the LDS of a block (K = 16: 26 KB instead of 53 KB, 6 instead of 3 blocks per CU).
+    // With kIt even, the first kIt / 2 elements of every lane are exactly rows 0..31.
+    static constexpr int kPasses = (kWave * kStride * 4 > 8192 && kIt % 2 == 0) ? 2 : 1;
+    static constexpr int kRowsPerPass = kWave / kPasses;
 };
 
 // Real spherical harmonics up to degree 3 at a unit direction (polar axis z), order
@@ -76,53 +85,82 @@ __device__ inline void wave_lds_sync() {
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-// Streams the coefficient rows of Gaussians [g0, g0 + rows) into this wavefront's LDS rows.
-// Nothing is conditional, so that every load is in flight before the first wait: an index past
-// the block re-reads the block's last element (inside the array) and stores it into an LDS row
-// >= rows, which belongs to a lane that has no Gaussian.
-template <int K>
-__device__ inline void stage_rows(const float *__restrict__ sh, int64_t g0, int rows, float *lds,
-                                  int lane) {
+// Element e of a wavefront's block (float4s or dwords) into its row's LDS slot, for a pass that
+// holds rows [r0, r0 + kRowsPerPass).
+template <int K, typename T>
+__device__ inline void put_elem(float *lds, int e, int r0, const T &v) {
     using L = ShLayout<K>;
-    if constexpr (L::kVec) {
-        constexpr int kIt = L::kQuads;                // 64 rows * kQuads float4s / 64 lanes
-        const float4 *src = reinterpret_cast<const float4 *>(sh) + g0 * L::kQuads;
-        const int nq = rows * L::kQuads;
-        float4 buf[kIt];
+    constexpr int kW = L::kVec ? 4 : 1;               // dwords per element
+    constexpr int kPerRow = L::kDw / kW;              // elements per row
+    const int r = e / kPerRow, c = e - r * kPerRow;
+    *reinterpret_cast<T *>(lds + (r - r0) * L::kStride + kW * c) = v;
+}
+
+// The lane's row from its LDS slot into registers.
+template <int K, typename T>
+__device__ inline void get_row(const float *lds, int slot, float (&row)[3 * K]) {
+    using L = ShLayout<K>;
+    constexpr int kW = L::kVec ? 4 : 1;
+    const T *own = reinterpret_cast<const T *>(__builtin_assume_aligned(lds + slot * L::kStride, kW * 4));
 #pragma unroll
-        for (int it = 0; it < kIt; ++it) {
-            const int q = lane + kWave * it;
-            buf[it] = src[q < nq ? q : nq - 1];
+    for (int c = 0; c < L::kDw / kW; ++c) {
+        const T v = own[c];
+        if constexpr (L::kVec) {
+            row[4 * c] = v.x;
+            row[4 * c + 1] = v.y;
+            row[4 * c + 2] = v.z;
+            row[4 * c + 3] = v.w;
+        } else {
+            row[c] = v;
         }
+    }
+}
+
+// Brings the coefficient row of Gaussian g0 + lane into registers (row), for the wavefront's
+// Gaussians [g0, g0 + rows). The rows are streamed as one contiguous block and transposed
+// through LDS, in kPasses passes of kRowsPerPass rows: a pass stores the elements of its rows
+// (with kPasses = 2, the first half of every lane's elements are exactly rows 0..31), then the
+// lanes of those rows read theirs back. Loads are unconditional, so that every one is in flight
+// before the first wait: an index past the block re-reads the block's last element (inside the
+// array) into a row >= rows, which belongs to a lane that has no Gaussian.
+template <int K>
+__device__ inline void fetch_row(const float *__restrict__ sh, int64_t g0, int rows, float *lds,
+                                 int lane, float (&row)[3 * K]) {
+    using L = ShLayout<K>;
+    using T = typename std::conditional<L::kVec, float4, float>::type;
+    constexpr int kW = L::kVec ? 4 : 1;
+    constexpr int kHalf = L::kIt / L::kPasses;
+    constexpr int kRp = L::kRowsPerPass;
+    const T *src = reinterpret_cast<const T *>(sh) + g0 * (L::kDw / kW);
+    const int ne = rows * (L::kDw / kW);
+    // the two halves in separate arrays (one array indexed across both passes ends up on the
+    // stack)
+    T lo[kHalf], hi[L::kIt - kHalf > 0 ? L::kIt - kHalf : 1];
 #pragma unroll
-        for (int it = 0; it < kIt; ++it) {
-            const int q = lane + kWave * it;
-            const int r = q / L::kQuads, c = q - r * L::kQuads;
-            *reinterpret_cast<float4 *>(lds + r * L::kStride + 4 * c) = buf[it];
-        }
-    } else {
-        constexpr int kIt = L::kDw;                   // 64 rows * kDw dwords / 64 lanes
-        const float *src = sh + g0 * L::kDw;
-        const int nd = rows * L::kDw;
-        float buf[kIt];
+    for (int it = 0; it < L::kIt; ++it) {
+        const int e = lane + kWave * it;
+        const T v = src[e < ne ? e : ne - 1];
+        if (it < kHalf) lo[it] = v;
+        else hi[it - kHalf] = v;
+    }
 #pragma unroll
-        for (int it = 0; it < kIt; ++it) {
-            const int d = lane + kWave * it;
-            buf[it] = src[d < nd ? d : nd - 1];
-        }
+    for (int it = 0; it < kHalf; ++it) put_elem<K, T>(lds, lane + kWave * it, 0, lo[it]);
+    wave_lds_sync();
+    if (lane < kRp) get_row<K, T>(lds, lane, row);
+    if constexpr (L::kPasses == 2) {
+        wave_lds_sync();
 #pragma unroll
-        for (int it = 0; it < kIt; ++it) {
-            const int d = lane + kWave * it;
-            const int r = d / L::kDw, c = d - r * L::kDw;
-            lds[r * L::kStride + c] = buf[it];
-        }
+        for (int it = kHalf; it < L::kIt; ++it)
+            put_elem<K, T>(lds, lane + kWave * it, kRp, hi[it - kHalf]);
+        wave_lds_sync();
+        if (lane >= kRp) get_row<K, T>(lds, lane - kRp, row);
     }
 }
 
 template <int K>
 __global__ __launch_bounds__(kProjBlock) void k_project(ProjectArgs a) {
     using L = ShLayout<K>;
-    __shared__ __align__(16) float lds_all[kWavesPerBlock][kWave * L::kStride];
+    __shared__ __align__(16) float lds_all[kWavesPerBlock][L::kRowsPerPass * L::kStride];
     const int lane = threadIdx.x % kWave, wave = threadIdx.x / kWave;
     const int64_t g0 = (int64_t(blockIdx.x) * kWavesPerBlock + wave) * kWave;
     if (g0 >= a.n) return;                            // whole wavefront past the end
@@ -135,9 +173,8 @@ __global__ __launch_bounds__(kProjBlock) void k_project(ProjectArgs a) {
     const float mx = a.means3d[3 * i], my = a.means3d[3 * i + 1], mz = a.means3d[3 * i + 2];
     const float sx = a.scales[3 * i], sy = a.scales[3 * i + 1], sz = a.scales[3 * i + 2];
     const float4 q4 = reinterpret_cast<const float4 *>(a.quats)[i];
-    float *lds = lds_all[wave];
-    stage_rows<K>(a.sh, g0, rows, lds, lane);
-    wave_lds_sync();
+    float row[L::kDw];
+    fetch_row<K>(a.sh, g0, rows, lds_all[wave], lane, row);
     if (!active) return;
 
     const float *R = a.cam.R;
@@ -210,23 +247,6 @@ __global__ __launch_bounds__(kProjBlock) void k_project(ProjectArgs a) {
                 const float dinv = 1.0f / sqrtf(fmaf(dx, dx, fmaf(dy, dy, dz * dz)));
                 float Y[16];
                 sh_basis(dx * dinv, dy * dinv, dz * dinv, a.deg, Y);
-                float row[L::kDw];
-                const float *src = lds + lane * L::kStride;
-                if constexpr (L::kVec) {
-                    const float4 *src4 = reinterpret_cast<const float4 *>(
-                        __builtin_assume_aligned(src, 16));
-#pragma unroll
-                    for (int c = 0; c < L::kQuads; ++c) {
-                        const float4 t4 = src4[c];
-                        row[4 * c] = t4.x;
-                        row[4 * c + 1] = t4.y;
-                        row[4 * c + 2] = t4.z;
-                        row[4 * c + 3] = t4.w;
-                    }
-                } else {
-#pragma unroll
-                    for (int c = 0; c < L::kDw; ++c) row[c] = src[c];
-                }
                 float acc[3] = {0.5f, 0.5f, 0.5f};
 #pragma unroll
                 for (int k = 0; k < K; ++k)
