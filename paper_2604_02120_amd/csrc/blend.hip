@@ -410,25 +410,29 @@ __device__ inline void fwd_tile(const ViewDesc &v, int64_t tile, Stage<M, NB> &S
 }
 
 // ------------------------------------------------------------------------------- backward
-// One step of a sum over each row of 16 lanes with DPP row shifts (after row_shr 1, 2, 4 and 8,
-// lane 15 of every row, i.e. lanes 15, 31, 47, 63, holds its row's total). Every lane active.
+// u + (v moved within its 16-lane row by the DPP control Ctrl). Every control used here reads
+// inside the row, so bound_ctrl (out-of-row reads give 0) never applies; it spares an `old`
+// operand.
 template <int Ctrl>
-__device__ inline float dpp_add(float x) {
-    // bound_ctrl: lanes shifted in from outside the row read 0 (no `old` operand to set up)
-    const int y = __builtin_amdgcn_update_dpp(0, __float_as_int(x), Ctrl, 0xf, 0xf, true);
-    return x + __int_as_float(y);
+__device__ inline float dpp_add2(float u, float v) {
+    const int y = __builtin_amdgcn_update_dpp(0, __float_as_int(v), Ctrl, 0xf, 0xf, true);
+    return u + __int_as_float(y);
 }
+constexpr int kDppRowRor8 = 0x128, kDppRowHalfMirror = 0x141;
+constexpr int kDppQuadRev = 0x1b, kDppQuadSwap = 0xb1;       // quad_perm [3,2,1,0], [1,0,3,2]
 
 // Sum of 9 values over the whole wavefront, transposed so that the 9 totals land in distinct
 // lanes (two values share each swap-and-add, so the wavefront is halved per value pair, not per
 // value):
 //   permlane32_swap + add on the pairs (s0,s1) (s2,s3) (s4,s5) (s6,s7), and s8 with itself:
 //       lanes 0-31 hold the first value's 32 partial sums, lanes 32-63 the second's;
-//   permlane16_swap + add on the register pairs: rows (16 lanes) hold (s0, s2, s1, s3) and
-//       (s4, s6, s5, s7), every row of the third register s8;
-//   row_shr 1, 2, 4, 8: lane 15 of each row holds its row's total.
-// Result: lane 16r + 15 of a holds s[{0,2,1,3}[r]], of b s[4 + {0,2,1,3}[r]]; lane 15 of c
-// holds s8. Every lane must be active.
+//   permlane16_swap + add on the register pairs: rows (16 lanes) of a hold (s0, s2, s1, s3),
+//       rows of b hold (s4, s6, s5, s7), every row of c holds s8;
+//   a and b share one register from here: lanes 0-7 of a row take a's row values, lanes 8-15
+//       b's, each summed with the lane 8 away (row_ror 8); then half_mirror, and two quad
+//       permutations finish each 8-lane half; c takes the same four steps alone.
+// Result: lanes 16r .. 16r+7 of ab hold s[{0,2,1,3}[r]], lanes 16r+8 .. 16r+15 hold
+// s[4 + {0,2,1,3}[r]]; lanes 0-7 of c hold s8. Every lane must be active.
 __device__ inline float swap_add32(float &x, float y) {   // returns [x.lo + x.hi | y.lo + y.hi]
     const auto r = __builtin_amdgcn_permlane32_swap(__float_as_uint(x), __float_as_uint(y), false, false);
     return __uint_as_float(r[0]) + __uint_as_float(r[1]);
@@ -437,31 +441,36 @@ __device__ inline float swap_add16(float x, float y) {    // rows: [x0+x1, y0+y1
     const auto r = __builtin_amdgcn_permlane16_swap(__float_as_uint(x), __float_as_uint(y), false, false);
     return __uint_as_float(r[0]) + __uint_as_float(r[1]);
 }
-__device__ inline void wave_sum9(const float (&s)[kGrad], float &a, float &b, float &c) {
+__device__ inline void wave_sum9(const float (&s)[kGrad], int lane, float &ab, float &c) {
     float x0 = s[0], x2 = s[2], x4 = s[4], x6 = s[6], x8 = s[8];
     const float p01 = swap_add32(x0, s[1]), p23 = swap_add32(x2, s[3]);
     const float p45 = swap_add32(x4, s[5]), p67 = swap_add32(x6, s[7]);
     const float p88 = swap_add32(x8, s[8]);
-    a = swap_add16(p01, p23);
-    b = swap_add16(p45, p67);
+    const float a = swap_add16(p01, p23);
+    const float b = swap_add16(p45, p67);
     c = swap_add16(p88, p88);
-    a = dpp_add<0x111>(a); b = dpp_add<0x111>(b); c = dpp_add<0x111>(c);   // row_shr:1
-    a = dpp_add<0x112>(a); b = dpp_add<0x112>(b); c = dpp_add<0x112>(c);
-    a = dpp_add<0x114>(a); b = dpp_add<0x114>(b); c = dpp_add<0x114>(c);
-    a = dpp_add<0x118>(a); b = dpp_add<0x118>(b); c = dpp_add<0x118>(c);   // row_shr:8
-    // keep the last shift-and-add here, where it is one DPP add, not moved into the callers'
-    // leader branch (where it would need a separate move)
-    asm volatile("" : "+v"(a), "+v"(b), "+v"(c));
+    const bool lo = (lane & 8) == 0;
+    ab = dpp_add2<kDppRowRor8>(lo ? a : b, lo ? b : a);
+    c = dpp_add2<kDppRowRor8>(c, c);
+    ab = dpp_add2<kDppRowHalfMirror>(ab, ab); c = dpp_add2<kDppRowHalfMirror>(c, c);
+    ab = dpp_add2<kDppQuadRev>(ab, ab);       c = dpp_add2<kDppQuadRev>(c, c);
+    ab = dpp_add2<kDppQuadSwap>(ab, ab);      c = dpp_add2<kDppQuadSwap>(c, c);
+    // keep the last add here, where it is one DPP add, not moved into the callers' leader branch
+    // (where it would need a separate move)
+    asm volatile("" : "+v"(ab), "+v"(c));
 }
 
 struct BwdState {
-    float T, Tfin, behind, gr, gg, gb, bgg;
+    float T;        // transmittance in front of the pairs not yet visited
+    float behind;   // T_final (bg . g) + sum over the visited pairs of alpha T (c . g)
+    float gr, gg, gb;
     int last;
 };
 
 // Reverse step for one (Gaussian, pixel) pair. Nothing but a compare and a scalar branch is
 // spent when no lane of the wave has a live pair. Otherwise every lane evaluates the step without
-// branches (a dead lane's terms are forced to zero by selects, and its state is left unchanged),
+// branches (a dead lane takes alpha = 0: its terms vanish and its state is unchanged exactly,
+// since 1 / (1 - 0) = 1),
 // the pair's 9 gradient terms are summed over the wavefront, and the totals are added into the
 // Gaussian's LDS accumulator (`acc`), which the block flushes to global memory once per batch. Raw sums: S_xx, S_xy, S_yy, S_x, S_y (times dL/dpower), dL/do, and the three colour
 // gradients.
@@ -476,32 +485,31 @@ __device__ inline void reverse_pair(float q, bool in_range, const float4 &ga, co
     const float4 attr = make_float4(from_lane(ga.x, u), from_lane(ga.y, u), from_lane(ga.z, u),
                                     from_lane(ga.w, u));
     const float4 bw = make_float4(from_lane(gb.x, u), from_lane(gb.y, u), from_lane(gb.z, u), 0.f);
-    // a dead lane has q < log2(1/255) or is past its last contributor: its alpha is finite and
-    // below 1/255 or belongs to a pair it never blended; either way its terms are selected away
+    // a dead lane has q < log2(1/255) or is past its last contributor: it blended nothing here
     const float araw = __builtin_amdgcn_exp2f(fminf(q, attr.x));
-    const float a = fminf(araw, kAlphaMax);
-    const float r = __builtin_amdgcn_rcpf(1.0f - a);
+    const float a = alive ? fminf(araw, kAlphaMax) : 0.f;
+    const float r = __builtin_amdgcn_rcpf(1.0f - a);  // exactly 1 for a dead lane
     const float Tb = st.T * r;                           // T in front of this Gaussian
     const float gc = st.gr * attr.y + st.gg * attr.z + st.gb * attr.w;
-    const float dLda = Tb * gc - (st.behind + st.Tfin * st.bgg) * r;
-    const float wc = alive ? a * Tb : 0.f;
+    const float dLda = Tb * gc - st.behind * r;
+    const float wc = a * Tb;
     st.behind = fmaf(wc, gc, st.behind);
-    st.T = alive ? Tb : st.T;
+    st.T = Tb;
     // dL/dpower = alpha * dL/dalpha unless the 0.99 clamp is active
-    const float da = (alive && araw < kAlphaMax) ? a * dLda : 0.f;
+    const float da = araw < kAlphaMax ? a * dLda : 0.f;
     // no gradient reaches the geometry through a clamped (positive) power
     const float dg = q > attr.x ? 0.f : da;
     const float dx = bw.x - L.px, dy = bw.y - L.py;
     const float tx = dg * dx, ty = dg * dy;
     const float s[kGrad] = {tx * dx, tx * dy, ty * dy, tx, ty, da * bw.z,   // dL/do = alpha/o dL/dalpha
                             wc * st.gr, wc * st.gg, wc * st.gb};
-    float ra, rb, rc;
-    wave_sum9(s, ra, rb, rc);
-    if ((L.l & 15) == 15) {
-        const int r = L.l >> 4, k = 2 * (r & 1) + (r >> 1);   // row r holds s[{0,2,1,3}[r]]
-        atomicAdd(&acc[k], ra);
-        atomicAdd(&acc[4 + k], rb);
-        if (r == 0) atomicAdd(&acc[8], rc);
+    float rab, rc;
+    wave_sum9(s, L.l, rab, rc);
+    if ((L.l & 7) == 0) {
+        // lane 16r holds s[{0,2,1,3}[r]], lane 16r + 8 holds s[4 + {0,2,1,3}[r]], lane 0 also s8
+        const int r = L.l >> 4, k = 2 * (r & 1) + (r >> 1) + (L.l & 8 ? 4 : 0);
+        atomicAdd(&acc[k], rab);
+        if (L.l == 0) atomicAdd(&acc[8], rc);
     }
 }
 
@@ -527,14 +535,14 @@ __device__ inline void bwd_tile(const ViewDesc &v, int64_t tile, Stage<M, NB> &S
         s_maxlast = 0;
     }
     if (n == 0) return;            // no Gaussian, no gradient (uniform: every thread returns)
-    BwdState st{1.f, 1.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0};
+    BwdState st{1.f, 0.f, 0.f, 0.f, 0.f, 0};
     if (L.inside) {
         const int64_t p = int64_t(L.py) * v.W + int64_t(L.px);
         const int64_t HW = int64_t(v.H) * v.W;
-        st.T = st.Tfin = v.final_T[p];
+        st.T = v.final_T[p];
         st.last = v.last_contrib[p];
         st.gr = v.dL_dimage[p]; st.gg = v.dL_dimage[HW + p]; st.gb = v.dL_dimage[2 * HW + p];
-        st.bgg = v.bg[0] * st.gr + v.bg[1] * st.gg + v.bg[2] * st.gb;
+        st.behind = st.T * (v.bg[0] * st.gr + v.bg[1] * st.gg + v.bg[2] * st.gb);
     }
     __syncthreads();
     if (st.last > 0) atomicMax(&s_maxlast, st.last);
