@@ -408,6 +408,37 @@ def roofline(res: dict, counts: dict) -> dict:
             "flops_per_launch": flops, "avg_ms": round(ms, 4)}
 
 
+def counter_fractions() -> dict | None:
+    """Fractions of the chip's rates for the FP16 blend kernels and the projection, from the
+    rocprofv3 counters of the same workload (profiles/traffic.json), for the kernels whose
+    source is unchanged since the counters were taken."""
+    if not os.path.exists(TRAFFIC):
+        return None
+    tr = json.load(open(TRAFFIC))
+    out = {"source": "rocprofv3 --pmc over the FP16 step and the projection leg; "
+                     "profiles/blend_c2_1080p_pmc.md, profiles/project_1080p_1M_kernel_trace.md"}
+    for kern, src in (("forward", KERNEL_SRC), ("backward", KERNEL_SRC), ("project", PROJECT_SRC)):
+        ent = tr.get(kern)
+        if not ent or ent.get("kernel_sha") != kernel_hash(src):
+            out[kern] = None            # kernel changed since the counters were taken
+        elif "fractions" in ent:
+            out[kern] = ent["fractions"]
+        else:
+            t = ent["median_us_trace"] * 1e-6
+            out[kern] = {"hbm_gbs": round(ent["bytes_per_launch"] / t / 1e9, 1),
+                         "hbm_frac_of_8tbs": round(ent["bytes_per_launch"] / t / 8e12, 4)}
+    return out
+
+
+# The paper's own figures, for orientation only: end-to-end forward render latency of the whole
+# 3DGS pipeline on trained scenes (Table 2); the paper has no blend-only and no backward figure.
+PAPER_CONTEXT = {
+    "kind": "end-to-end forward render latency, trained scenes (Table 2); not comparable",
+    "A100_mean_latency_ms": {"vanilla_3dgs": 5.36, "gemm_gs": 3.79, "speedup": 1.42},
+    "H100_mean_speedup": 1.37,
+}
+
+
 def psnr(a, b) -> float:
     mse = float(np.mean((a - b) ** 2))
     return math.inf if mse == 0 else 10 * math.log10(1.0 / mse)
@@ -493,8 +524,10 @@ def main():
         "blend_mpix_s": round(head["blend_mpix_s"], 3),
         "breakdown_ms": {k: round(head[k], 4) for k in ("bin_ms", "fwd_ms", "bwd_ms")},
         "roofline": roofline(head, counts),
+        "counters": counter_fractions(),
         "paths": {p: {k: (round(v, 4) if isinstance(v, float) else v) for k, v in r.items()}
                   for p, r in results.items()},
+        "paper_context": PAPER_CONTEXT,
     }
     if "fp32" in results and precs[0] != "fp32":
         line["speedup_vs_plain_fp32"] = {
