@@ -121,9 +121,10 @@ __device__ T block_exclusive_scan(T v, T *s_wave, T &total) {
 }
 
 // ------------------------------------------------------------------------------- device scan
-// Exclusive prefix sum. Short arrays: one block walks the array in chunks with a running carry.
-// Long arrays: per-block sums, a single-block scan of those, then a per-block scan with the
-// block's offset. `in` and `out` may alias. The total goes to *total_a / *total_b if given.
+// Exclusive prefix sum, in place. Short arrays: one block walks the array in chunks with a running
+// carry. Long arrays: per-block sums, then a per-block scan whose blocks add up the sums before
+// them. The total goes to *total_a / *total_b if given (a total-only call scans the per-block
+// sums in one block instead).
 template <typename T>
 __global__ __launch_bounds__(kScanTopThreads) void k_scan_small(T *data, int64_t m,
                                                                 unsigned long long *total_a,
@@ -192,23 +193,37 @@ __global__ __launch_bounds__(kScanTopThreads) void k_scan_top(T *partial, int64_
     }
 }
 
+// The down pass with the block offsets formed in place: block b sums the per-block totals
+// partial[0, b) itself (a few hundred values at most, read from L2) instead of a separate
+// single-block scan of them, which saves a launch; the last block writes the total.
 template <typename T>
-__global__ __launch_bounds__(kScanThreads) void k_scan_down(const T *in, T *out, int64_t m,
-                                                             const T *partial) {
+__global__ __launch_bounds__(kScanThreads) void k_scan_down_fused(T *data, int64_t m,
+                                                                   const T *partial, int64_t nb,
+                                                                   unsigned long long *total_a,
+                                                                   long long *total_b) {
     __shared__ T s_wave[kScanThreads / 64];
-    const int64_t base = int64_t(blockIdx.x) * kScanTile + int64_t(threadIdx.x) * kScanItems;
+    const int64_t blk = blockIdx.x;
+    T mine = 0;
+    for (int64_t i = threadIdx.x; i < blk; i += kScanThreads) mine += partial[i];
+    T offset;
+    block_exclusive_scan<T>(mine, s_wave, offset);       // offset = sum of partial[0, blk)
+    const int64_t base = blk * kScanTile + int64_t(threadIdx.x) * kScanItems;
     T v[kScanItems], sum = 0;
 #pragma unroll
     for (int k = 0; k < kScanItems; ++k) {
-        v[k] = (base + k < m) ? in[base + k] : T(0);
+        v[k] = (base + k < m) ? data[base + k] : T(0);
         sum += v[k];
     }
     T tot;
-    T run = block_exclusive_scan<T>(sum, s_wave, tot) + partial[blockIdx.x];
+    T run = block_exclusive_scan<T>(sum, s_wave, tot) + offset;
 #pragma unroll
     for (int k = 0; k < kScanItems; ++k) {
-        if (base + k < m) out[base + k] = run;
+        if (base + k < m) data[base + k] = run;
         run += v[k];
+    }
+    if (blk == nb - 1 && threadIdx.x == 0) {
+        if (total_a) *total_a = (unsigned long long)(offset + tot);
+        if (total_b) *total_b = (long long)(offset + tot);
     }
 }
 
@@ -222,8 +237,11 @@ void launch_scan(T *data, int64_t m, T *partial, unsigned long long *total_a, lo
         return;
     }
     if (nb > 0) k_scan_reduce<T><<<dim3(unsigned(nb)), kScanThreads, 0, s>>>(data, m, partial);
-    k_scan_top<T><<<1, kScanTopThreads, 0, s>>>(partial, nb, total_a, total_b);
-    if (down && nb > 0) k_scan_down<T><<<dim3(unsigned(nb)), kScanThreads, 0, s>>>(data, data, m, partial);
+    if (down)
+        k_scan_down_fused<T><<<dim3(unsigned(nb)), kScanThreads, 0, s>>>(data, m, partial, nb,
+                                                                          total_a, total_b);
+    else
+        k_scan_top<T><<<1, kScanTopThreads, 0, s>>>(partial, nb, total_a, total_b);
 }
 
 // ------------------------------------------------------------------------------- mode 1
