@@ -648,9 +648,23 @@ __device__ inline void bwd_tile(const ViewDesc &v, int64_t tile, Stage<M, NB> &S
 }
 
 // ------------------------------------------------------------------------------- kernels
+// Wavefronts per SIMD that a kernel's launch bound asks for: its register target, but never more
+// than the blocks that fit in a compute unit's 160 KB of LDS (a 256-thread block puts one
+// wavefront on each SIMD), so the compiler is not held to an occupancy the LDS rules out.
+constexpr size_t kLdsPerCu = 160 * 1024;
+constexpr int fit_waves(int target, size_t lds) {
+    return int(kLdsPerCu / lds) < target ? int(kLdsPerCu / lds) : target;
+}
+// LDS of one block: the staged batches (and, backward, the gradient accumulators), plus the few
+// scalars the kernels share
+template <Mode M, int NB> constexpr size_t lds_fwd() { return sizeof(Stage<M, NB>) + 64; }
+template <Mode M, int NB> constexpr size_t lds_bwd() {
+    return sizeof(Stage<M, NB>) + sizeof(StageBwd<NB>) + sizeof(BwdAcc<NB>) + 64;
+}
 // Single view: block b renders tile xcd_tile(b).
 template <Mode M, int NB>
-__global__ __launch_bounds__(kBlock, M == Mode::Plain ? 8 : 7) void k_blend_fwd(ViewDesc v) {
+__global__ __launch_bounds__(kBlock, fit_waves(M == Mode::Plain ? 8 : 7, lds_fwd<M, NB>()))
+void k_blend_fwd(ViewDesc v) {
     __shared__ Stage<M, NB> S;
     const int64_t tile = xcd_tile(blockIdx.x, v.n_tiles);
     if (tile >= v.n_tiles) return;
@@ -658,7 +672,8 @@ __global__ __launch_bounds__(kBlock, M == Mode::Plain ? 8 : 7) void k_blend_fwd(
 }
 
 template <Mode M, int NB>
-__global__ __launch_bounds__(kBlock, M == Mode::Plain ? 7 : 5) void k_blend_bwd(ViewDesc v) {
+__global__ __launch_bounds__(kBlock, fit_waves(M == Mode::Plain ? 7 : 5, lds_bwd<M, NB>()))
+void k_blend_bwd(ViewDesc v) {
     __shared__ Stage<M, NB> S;
     __shared__ StageBwd<NB> SB;
     __shared__ BwdAcc<NB> s_acc;   // per-Gaussian gradient sums of the current batch
@@ -718,7 +733,8 @@ template <Mode M> constexpr int waves_fwd() { return M == Mode::Plain ? 7 : 4; }
 template <Mode M> constexpr int waves_bwd() { return M == Mode::Plain ? 5 : 4; }
 
 template <Mode M, int NB>
-__global__ __launch_bounds__(kBlock, waves_fwd<M>()) void k_blend_fwd_batched(Queues Q) {
+__global__ __launch_bounds__(kBlock, fit_waves(waves_fwd<M>(), lds_fwd<M, NB>()))
+void k_blend_fwd_batched(Queues Q) {
     __shared__ Stage<M, NB> S;
     __shared__ int s_view;
     __shared__ int64_t s_tile;
@@ -745,7 +761,8 @@ __global__ __launch_bounds__(kBlock, waves_fwd<M>()) void k_blend_fwd_batched(Qu
 }
 
 template <Mode M, int NB>
-__global__ __launch_bounds__(kBlock, waves_bwd<M>()) void k_blend_bwd_batched(Queues Q) {
+__global__ __launch_bounds__(kBlock, fit_waves(waves_bwd<M>(), lds_bwd<M, NB>()))
+void k_blend_bwd_batched(Queues Q) {
     __shared__ Stage<M, NB> S;
     __shared__ StageBwd<NB> SB;
     __shared__ BwdAcc<NB> s_acc;
@@ -792,7 +809,8 @@ __device__ inline bool grid_item(const Queues &Q, int64_t b, int &view, int64_t 
 }
 
 template <Mode M, int NB>
-__global__ __launch_bounds__(kBlock, M == Mode::Plain ? 8 : 7) void k_blend_fwd_grid(Queues Q) {
+__global__ __launch_bounds__(kBlock, fit_waves(M == Mode::Plain ? 8 : 7, lds_fwd<M, NB>()))
+void k_blend_fwd_grid(Queues Q) {
     __shared__ Stage<M, NB> S;
     int view;
     int64_t tile;
@@ -802,7 +820,8 @@ __global__ __launch_bounds__(kBlock, M == Mode::Plain ? 8 : 7) void k_blend_fwd_
 }
 
 template <Mode M, int NB>
-__global__ __launch_bounds__(kBlock, M == Mode::Plain ? 7 : 5) void k_blend_bwd_grid(Queues Q) {
+__global__ __launch_bounds__(kBlock, fit_waves(M == Mode::Plain ? 7 : 5, lds_bwd<M, NB>()))
+void k_blend_bwd_grid(Queues Q) {
     __shared__ Stage<M, NB> S;
     __shared__ StageBwd<NB> SB;
     __shared__ BwdAcc<NB> s_acc;
@@ -948,7 +967,7 @@ gsb_status plan_create(const ViewDesc *views, int n_views, gsb_precision prec, c
     p->n_views = n_views;
     p->prec = prec;
     p->tune = t;
-    hipGetDevice(&p->device);
+    hipError_t e = hipGetDevice(&p->device);
     // heaviest-first: Gaussians per tile is proportional to the mean tile list length
     std::vector<int> order(n_views);
     for (int i = 0; i < n_views; ++i) order[i] = i;
@@ -971,7 +990,7 @@ gsb_status plan_create(const ViewDesc *views, int n_views, gsb_precision prec, c
         prefix[size_t(x) * (n_views + 1) + n_views] = run;
         p->grid_items = std::max(p->grid_items, run * kXcds);
     }
-    hipError_t e = hipMalloc(&p->d_views, sizeof(ViewDesc) * size_t(n_views));
+    if (e == hipSuccess) e = hipMalloc(&p->d_views, sizeof(ViewDesc) * size_t(n_views));
     if (e == hipSuccess) e = hipMalloc(&p->d_prefix, sizeof(int64_t) * prefix.size());
     if (e == hipSuccess) e = hipMalloc(&p->d_counters, sizeof(unsigned int) * 2 * kXcds);
     if (e == hipSuccess) e = hipMemcpy(p->d_views, ordered.data(), sizeof(ViewDesc) * size_t(n_views), hipMemcpyHostToDevice);
@@ -981,7 +1000,7 @@ gsb_status plan_create(const ViewDesc *views, int n_views, gsb_precision prec, c
     if (e == hipSuccess) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ_f, batched_fn(prec, true, t.batch_fwd), kBlock, 0);
     if (e == hipSuccess) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ_b, batched_fn(prec, false, t.batch_bwd), kBlock, 0);
     if (e != hipSuccess) {
-        plan_destroy(p);
+        (void)plan_destroy(p);      // the creation error is the one reported
         return fail(GSB_ERR_HIP, "plan_create: %s", hipGetErrorString(e));
     }
     const int want = t.blocks_per_cu > 0 ? t.blocks_per_cu : 1 << 30;
@@ -994,12 +1013,18 @@ gsb_status plan_create(const ViewDesc *views, int n_views, gsb_precision prec, c
     return GSB_OK;
 }
 
-void plan_destroy(Plan *p) {
-    if (!p) return;
-    if (p->d_views) hipFree(p->d_views);
-    if (p->d_prefix) hipFree(p->d_prefix);
-    if (p->d_counters) hipFree(p->d_counters);
+hipError_t plan_destroy(Plan *p) {
+    if (!p) return hipSuccess;
+    // every buffer is freed; the first failure is the one reported
+    hipError_t e = hipSuccess;
+    for (void *d : {static_cast<void *>(p->d_views), static_cast<void *>(p->d_prefix),
+                    static_cast<void *>(p->d_counters)}) {
+        if (!d) continue;
+        const hipError_t f = hipFree(d);
+        if (e == hipSuccess) e = f;
+    }
     delete p;
+    return e;
 }
 
 template <Mode M>

@@ -309,7 +309,8 @@ gsb_status gsb_plan_create(const gsb_view *views, int32_t n_views, gsb_precision
 
 gsb_status gsb_plan_destroy(gsb_plan plan) {
     g_err[0] = '\0';
-    plan_destroy(reinterpret_cast<Plan *>(plan));
+    const hipError_t e = plan_destroy(reinterpret_cast<Plan *>(plan));
+    if (e != hipSuccess) return fail(GSB_ERR_HIP, "gsb_plan_destroy: %s", hipGetErrorString(e));
     return GSB_OK;
 }
 

@@ -127,7 +127,7 @@ gsb_status blend_backward(const ViewDesc &v, gsb_precision prec, int batch, hipS
 struct Plan;
 gsb_status plan_create(const ViewDesc *views, int n_views, gsb_precision prec, const Tuning &t,
                        Plan **out);
-void plan_destroy(Plan *p);
+hipError_t plan_destroy(Plan *p);   // frees everything; returns the first hipFree error
 gsb_status plan_forward(Plan *p, hipStream_t s);
 gsb_status plan_backward(Plan *p, hipStream_t s);
 
