@@ -9,9 +9,18 @@ resident in HBM. The GEMM form (FP16 hi+lo exponent on MFMA, FP32 accumulate and
 is the headline; the plain FP32 per-pixel form and the BF16 GEMM form are timed the same way.
 
 Prints one JSON line. `value` = frame pixels x steps / wall time of the timed steps (binning
-included); `blend_mpix_s` = pixels / (forward + backward kernel time) alone.
+included); `blend_mpix_s` = pixels / (forward + backward kernel time) alone. Beside the headline
+the line carries: `roofline` (the dominant kernel against the FP32 vector peak, HBM traffic from
+the counters), `counters` (issue and bandwidth fractions from rocprofv3 counters of the same
+workload), `paths` (every precision), `visible_binning` (the same step with the opacity-aware
+tile extent), `pipeline_3d` (the step preceded by projecting 1M 3D Gaussians), `batched_c4`
+(16 views in one persistent launch per direction, replayed from a hipGraph), `cpu_baseline`
+(the FP64 oracle on the host's cores) and `accuracy` (every path against that oracle).
 
-    python bench.py [--steps K] [--warmup W] [--no-cpu-baseline]
+    python bench.py [--steps K] [--warmup W] [--no-cpu-baseline] [--no-visible] [--no-pipeline]
+                    [--no-batched]
+    python bench.py --sweep            # LDS batch size and resolution sweeps
+    python bench.py --pipeline-only    # the 3D leg alone
 """
 from __future__ import annotations
 

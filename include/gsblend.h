@@ -248,7 +248,7 @@ typedef struct gsb_view {
 #define GSB_LAUNCH_PERSISTENT 0   /* resident blocks pull items from the per-XCD queues */
 #define GSB_LAUNCH_GRID 1         /* one block per item: block b takes item b/8 of queue b%8 */
 typedef struct gsb_tuning {
-    int32_t batch_fwd;       /* Gaussians staged in LDS per batch, forward: 64, 128, 256 (256) */
+    int32_t batch_fwd;       /* Gaussians staged in LDS per batch, forward: 64, 128, 256 (128) */
     int32_t batch_bwd;       /* same, backward (128) */
     int32_t blocks_per_cu;   /* persistent: resident blocks per compute unit; 0 = as many as fit */
     int32_t launch;          /* GSB_LAUNCH_PERSISTENT (default) or GSB_LAUNCH_GRID */

@@ -3,7 +3,9 @@
 ``include/gsblend.h``) plus this thin binding.
 
 * ``paper_2604_02120_amd._lib``     — ctypes functions with the C names (``gsb_*``).
-* ``paper_2604_02120_amd.api``      — tensor-level bin / forward / backward.
+* ``paper_2604_02120_amd.api``      — tensor-level projection of 3D Gaussians, bin / forward /
+  backward, and ``BatchedViews`` (many views per launch).
+* ``paper_2604_02120_amd.autotune`` — launch-shape autotuner for batched views.
 * ``paper_2604_02120_amd.autograd`` — ``BlendFunction`` / ``blend`` for torch autograd.
 * ``paper_2604_02120_amd.build``    — hipcc build of the library.
 """

@@ -3,7 +3,9 @@ step of the work runs in libgsblend's kernels.
 
 Tensors must be contiguous and on the current HIP device:
   means2d f32[n][2], conics f32[n][3] (A, B, C), opacity f32[n], colors f32[n][3],
-  depths f32[n], radii i32[n]; point_list/ranges are i32 tensors holding u32 values.
+  depths f32[n], radii i32[n]; point_list/ranges are i32 tensors holding u32 values;
+  for the projection means3d f32[n][3], scales f32[n][3], quats f32[n][4] (w, x, y, z) and
+  sh f32[n][K][3].
 """
 from __future__ import annotations
 
@@ -211,8 +213,7 @@ class BatchedViews:
     from its exact pair count (times ``capacity_slack``), so that ``bin()``, ``forward()`` and
     ``backward()`` afterwards enqueue kernels only: the whole step can be captured in a hipGraph.
     ``tuning``: None (library defaults), a dict (batch_fwd, batch_bwd, blocks_per_cu, launch) or
-    "auto"
-    (``autotune.tune``). ``dL_dimage[v]`` is allocated here (zeros) for the caller to fill.
+    "auto" (``autotune.tune``). ``dL_dimage[v]`` is allocated here (zeros) for the caller to fill.
     """
 
     def __init__(self, scenes, prec="fp16", tuning=None, bg=(0.0, 0.0, 0.0),
