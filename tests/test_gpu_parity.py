@@ -384,3 +384,28 @@ def test_visible_binning_same_blend(gpu, prec, name):
     assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1]) and np.array_equal(a[2], b[2])
     for ga, gb in zip(a[3], b[3]):
         assert normwise(gb, ga) <= 1e-5
+
+
+def test_three_tile_sort_passes(gpu):
+    """More than 65536 tiles (4112 x 4112 pixels: 257 x 257 tiles, 17-bit tile ids) take the
+    tile sort through three passes, an odd count above one, which routes the sorted values
+    through the other buffer. Both binning modes bit for bit over the whole frame, then the plain
+    forward on every pixel."""
+    cfg = gsinputs.SceneConfig("tiles66k", 4112, 4112, 30000, "loguniform", 0.5, 8.0, "uniform", 46)
+    s = gsinputs.make_scene(cfg)
+    W, H = s["width"], s["height"]
+    gx, gy = oracle.grid(W, H)
+    assert gx * gy > 65536
+    say(f"[bin] {W}x{H} ({gx * gy} tiles) n={len(s['radii'])}")
+    sd = upload(s, gpu)
+    for mode, omode in (("rect", oracle.BIN_RECT), ("visible", oracle.BIN_VISIBLE)):
+        pl_ref, rg_ref = oracle.bin_tiles(s["means2d"], s["radii"], s["depths"], W, H,
+                                          s["conics"], s["opacity"], omode)
+        pl, rg = gpu_bins(sd, mode)
+        np.testing.assert_array_equal(rg.cpu().numpy().astype(np.uint32), rg_ref)
+        np.testing.assert_array_equal(pl.cpu().numpy().astype(np.uint32), pl_ref)
+        if mode == "rect":
+            ref = oracle.forward(W, H, rg_ref, pl_ref, s["means2d"], s["conics"], s["opacity"],
+                                 s["colors"])
+            img, T, last = gpu_forward(sd, pl, rg, "fp32")
+            check_plain(ref, img, T, last, "66k tiles")
