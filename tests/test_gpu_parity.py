@@ -44,6 +44,11 @@ def scenes():
         "bigrects": gsinputs.make_scene(
             gsinputs.SceneConfig("bigrects", 1024, 1024, 3000, "loguniform", 8.0, 64.0,
                                  "uniform", 44)),
+        # means bunched around a few centres: tile lists up to ~8700 long (68 batches of 128),
+        # most pixels saturate and stop early
+        "clustered": gsinputs.make_scene(
+            gsinputs.SceneConfig("clustered", 512, 384, 60000, "lognormal", 2.0, 0.0,
+                                 "uniform", 47, clustered=True)),
     }
 
 
@@ -201,7 +206,7 @@ def backward_case(s, gpu, prec, seed=77, bg=(0.1, 0.3, 0.2)):
 
 
 @pytest.mark.parametrize("prec", PRECS)
-@pytest.mark.parametrize("name", ["C1", "ragged", "lognormal"])
+@pytest.mark.parametrize("name", ["C1", "ragged", "lognormal", "clustered"])
 def test_backward_parity(gpu, prec, name):
     s = SCENES[name]
     say(f"[bwd] {name} {prec}")
