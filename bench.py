@@ -417,6 +417,13 @@ def roofline(res: dict, counts: dict) -> dict:
             "flops_per_launch": flops, "avg_ms": round(ms, 4)}
 
 
+def device_info(dev) -> dict:
+    p = torch.cuda.get_device_properties(dev)
+    return {"name": p.name, "arch": p.gcnArchName.split(":")[0], "compute_units":
+            p.multi_processor_count, "hbm_gib": round(p.total_memory / 2 ** 30, 1),
+            "torch": torch.__version__, "hip": torch.version.hip}
+
+
 def counter_fractions() -> dict | None:
     """Fractions of the chip's rates for the FP16 blend kernels and the projection, from the
     rocprofv3 counters of the same workload (profiles/traffic.json), for the kernels whose
@@ -537,6 +544,7 @@ def main():
         "paths": {p: {k: (round(v, 4) if isinstance(v, float) else v) for k, v in r.items()}
                   for p, r in results.items()},
         "paper_context": PAPER_CONTEXT,
+        "device": device_info(dev),
     }
     if "fp32" in results and precs[0] != "fp32":
         line["speedup_vs_plain_fp32"] = {
