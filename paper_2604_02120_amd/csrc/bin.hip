@@ -910,14 +910,30 @@ __global__ __launch_bounds__(256) void k_bin_init(uint32_t *ranges, int64_t m, S
     }
 }
 
+// Tile boundaries in the sorted tile ids: four consecutive pairs per thread (one 16-byte load and
+// the two neighbours outside it). `tiles` is 16-byte aligned.
 __global__ __launch_bounds__(256) void k_ranges(const uint32_t *tiles, const BinHeader *hdr,
                                                 uint32_t *ranges) {
     const int64_t P = int64_t(hdr->pairs);
-    const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-    if (i >= P) return;
-    const uint32_t t = tiles[i];
-    if (i == 0 || tiles[i - 1] != t) ranges[2 * int64_t(t)] = uint32_t(i);
-    if (i == P - 1 || tiles[i + 1] != t) ranges[2 * int64_t(t) + 1] = uint32_t(i + 1);
+    const int64_t i0 = 4 * (int64_t(blockIdx.x) * blockDim.x + threadIdx.x);
+    if (i0 >= P) return;
+    uint32_t t[6];                       // tiles[i0 - 1 .. i0 + 4]; outside [0, P): no tile
+    t[0] = i0 > 0 ? tiles[i0 - 1] : 0xffffffffu;
+    if (i0 + 4 <= P) {
+        const uint4 v = *reinterpret_cast<const uint4 *>(tiles + i0);
+        t[1] = v.x; t[2] = v.y; t[3] = v.z; t[4] = v.w;
+    } else {
+#pragma unroll
+        for (int k = 0; k < 4; ++k) t[1 + k] = i0 + k < P ? tiles[i0 + k] : 0xffffffffu;
+    }
+    t[5] = i0 + 4 < P ? tiles[i0 + 4] : 0xffffffffu;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        const int64_t i = i0 + k;
+        if (i >= P) break;
+        if (t[k] != t[k + 1]) ranges[2 * int64_t(t[k + 1])] = uint32_t(i);
+        if (t[k + 2] != t[k + 1]) ranges[2 * int64_t(t[k + 1]) + 1] = uint32_t(i + 1);
+    }
 }
 
 int ceil_log2(int64_t v) {
@@ -998,7 +1014,7 @@ gsb_status bin_fill(const float *means2d, const int32_t *radii, const float *con
                status_dev, s);
     const uint32_t *tiles_sorted = (tp % 2 == 0) ? tka : tkb;
     if (cap > 0)
-        k_ranges<<<dim3(unsigned((cap + 255) / 256)), 256, 0, s>>>(tiles_sorted, hdr, ranges);
+        k_ranges<<<dim3(unsigned((cap + 1023) / 1024)), 256, 0, s>>>(tiles_sorted, hdr, ranges);
     return check_launch("bin_fill");
 }
 
