@@ -696,10 +696,18 @@ __global__ __launch_bounds__(kSortThreads) void k_block_hist(const uint32_t *key
     __syncthreads();
     const int64_t P = int64_t(*count);
     const int64_t base = int64_t(blockIdx.x) * kSortTile;
-#pragma unroll 4
-    for (int k = 0; k < kSortItems; ++k) {
-        const int64_t idx = base + int64_t(k) * kSortThreads + t;
-        if (idx < P) atomicAdd(&s_h[(keys[idx] >> shift) & (kRadix - 1)], 1u);
+    // 16-byte loads (order does not matter to a histogram). The key buffers are 256-byte aligned
+    // and padded to 256 bytes, so a load that straddles P stays inside; entries >= P are ignored.
+#pragma unroll
+    for (int k = 0; k < kSortItems / 4; ++k) {
+        const int64_t idx = base + 4 * (int64_t(k) * kSortThreads + t);
+        if (idx < P) {
+            const uint4 v = *reinterpret_cast<const uint4 *>(keys + idx);
+            atomicAdd(&s_h[(v.x >> shift) & (kRadix - 1)], 1u);
+            if (idx + 1 < P) atomicAdd(&s_h[(v.y >> shift) & (kRadix - 1)], 1u);
+            if (idx + 2 < P) atomicAdd(&s_h[(v.z >> shift) & (kRadix - 1)], 1u);
+            if (idx + 3 < P) atomicAdd(&s_h[(v.w >> shift) & (kRadix - 1)], 1u);
+        }
     }
     __syncthreads();
     hist[int64_t(t) * nblk + blockIdx.x] = s_h[t];
