@@ -662,20 +662,35 @@ __global__ __launch_bounds__(kSortThreads) void k_sort_hist(const float *depths,
     for (int64_t b = blockIdx.x; b < nblk; b += gridDim.x) {
         const int64_t base = b * kSortTile;
         if (base >= P) break;
-#pragma unroll 4
-        for (int k = 0; k < kSortItems; ++k) {
-            const int64_t idx = base + int64_t(k) * kSortThreads + t;
-            if (idx < P) {
-                uint32_t key;
-                if constexpr (kDepth) {
-                    key = depth_key(depths[idx]);
-                    keys_io[idx] = key;
-                    vals_out[idx] = uint32_t(idx);
+        // four consecutive entries per thread and step: the keys and identity values are stored
+        // with 16-byte writes (the workspace buffers are 256-byte aligned)
+#pragma unroll
+        for (int k = 0; k < kSortItems / 4; ++k) {
+            const int64_t idx = base + 4 * (int64_t(k) * kSortThreads + t);
+            if (idx >= P) continue;
+            uint32_t key[4];
+            if constexpr (kDepth) {
+#pragma unroll
+                for (int j = 0; j < 4; ++j) key[j] = idx + j < P ? depth_key(depths[idx + j]) : 0u;
+                if (idx + 4 <= P) {
+                    *reinterpret_cast<uint4 *>(keys_io + idx) = make_uint4(key[0], key[1], key[2], key[3]);
+                    const uint32_t i0 = uint32_t(idx);
+                    *reinterpret_cast<uint4 *>(vals_out + idx) = make_uint4(i0, i0 + 1, i0 + 2, i0 + 3);
                 } else {
-                    key = keys_io[idx];
+                    for (int j = 0; idx + j < P; ++j) {
+                        keys_io[idx + j] = key[j];
+                        vals_out[idx + j] = uint32_t(idx + j);
+                    }
                 }
+            } else {
+#pragma unroll
+                for (int j = 0; j < 4; ++j) key[j] = idx + j < P ? keys_io[idx + j] : 0u;
+            }
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                if (idx + j >= P) break;
                 for (int p = 0; p < passes; ++p)
-                    atomicAdd(&s_h[p][(key >> (kRadixBits * p)) & (kRadix - 1)], 1u);
+                    atomicAdd(&s_h[p][(key[j] >> (kRadixBits * p)) & (kRadix - 1)], 1u);
             }
         }
     }
