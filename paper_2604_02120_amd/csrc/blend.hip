@@ -115,6 +115,10 @@ struct Stage<Mode::Plain, NB> {  // plain form
 template <int NB>
 struct StageBwd {
     float4 bwd[2][NB];         // (x, y, 1/o, index bits)
+    // GEMM forms: the Gaussian index of each slot of batch b, in ids[b % 3]. The flush of batch
+    // b + 1 reads other threads' slots while the next batch is staged; three buffers keep that
+    // staging out of the ones being read.
+    uint32_t ids[3][NB];
 };
 
 constexpr int kGrad = 9;   // per-Gaussian sums kept per batch
@@ -564,7 +568,9 @@ __device__ inline void bwd_tile(const ViewDesc &v, int64_t tile, Stage<M, NB> &S
         const int64_t o = int64_t(bb) * NB + L.t;
         return load_entry(plist, start + o, bb >= 0 && L.t < NB && o < len, start);
     };
-    const auto flush = [&](int bb) {     // batch bb's sums, accumulator buffer bb & 1
+    // Plain form: thread t < NB flushes the nine sums of slot t (and zeroes them when it stages
+    // the next batch into that slot).
+    const auto flush_slot = [&](int bb) {     // batch bb's sums, accumulator buffer bb & 1
         if (L.t >= NB) return;
         float a9[kGrad];
         const float *src = s_acc.slot(bb & 1, L.t);
@@ -586,15 +592,62 @@ __device__ inline void bwd_tile(const ViewDesc &v, int64_t tile, Stage<M, NB> &S
             unsafeAtomicAdd(&v.dL_dcolors[3 * id + 2], a9[8]);
         }
     };
+    // GEMM forms: the 9 NB sums of a batch are flushed by the whole block, item e in the order
+    // dL/dconics (3 per slot), dL/dmeans2d (2), dL/dopacity (1), dL/dcolors (3), so that
+    // consecutive lanes add consecutive words of one Gaussian and a wavefront's atomics reach
+    // a third as many cache lines (the global atomics are this kernel's largest cost). Every
+    // segment bound is a multiple of 64 (NB is), so each wavefront takes one branch. The thread
+    // that reads an item also zeroes it for batch bb - 2, which reuses the buffer after the next
+    // barrier.
+    const auto flush_items = [&](int bb) {
+        float *acc = s_acc.v[bb & 1];
+        const uint32_t *ids = SB.ids[bb % 3];
+#pragma unroll
+        for (int e0 = 0; e0 < kGrad * NB; e0 += kBlock) {
+            const int e = e0 + L.t;
+            if (e >= kGrad * NB) break;
+            int slot, k, c, stride;
+            float *out;
+            if (e < 3 * NB) {
+                slot = e / 3; c = e - 3 * slot; k = c; out = v.dL_dconics; stride = 3;
+            } else if (e < 5 * NB) {
+                const int f = e - 3 * NB;
+                slot = f >> 1; c = f & 1; k = 3 + c; out = v.dL_dmeans2d; stride = 2;
+            } else if (e < 6 * NB) {
+                slot = e - 5 * NB; c = 0; k = 5; out = v.dL_dopacity; stride = 1;
+            } else {
+                const int f = e - 6 * NB;
+                slot = f / 3; c = f - 3 * slot; k = 6 + c; out = v.dL_dcolors; stride = 3;
+            }
+            float *p = acc + slot * kGrad + k;
+            const float val = *p;
+            *p = 0.f;
+            if (val != 0.f) unsafeAtomicAdd(&out[int64_t(stride) * ids[slot] + c], val);
+        }
+    };
+    const auto flush = [&](int bb) {
+        if constexpr (M == Mode::Plain) flush_slot(bb);
+        else flush_items(bb);
+    };
     GRaw nxt = fetch_attrs(entry(nb - 1).id(), n, means, conics, opac, colors);
     Entry ent = entry(nb - 2);
+    if constexpr (M != Mode::Plain) {   // both accumulator buffers start at zero
+        for (int e = L.t; e < NB * kGrad; e += kBlock) {
+            s_acc.v[0][e] = 0.f;
+            s_acc.v[1][e] = 0.f;
+        }
+    }
     for (int b = nb - 1; b >= 0; --b) {
         const int buf = b & 1;
         if (L.t < NB) {
             stage<M, NB, true>(nxt, buf, L.t, xc, yc, S, &SB);
-            float *z = s_acc.slot(buf, L.t);
+            if constexpr (M == Mode::Plain) {
+                float *z = s_acc.slot(buf, L.t);
 #pragma unroll
-            for (int k = 0; k < kGrad; ++k) z[k] = 0.f;
+                for (int k = 0; k < kGrad; ++k) z[k] = 0.f;
+            } else {
+                SB.ids[b % 3][L.t] = nxt.id;
+            }
         }
         __syncthreads();
         // unconditional: before the first batch these read entry `start` and Gaussian 0, unused
@@ -639,9 +692,10 @@ __device__ inline void bwd_tile(const ViewDesc &v, int64_t tile, Stage<M, NB> &S
                 }
             }
         }
-        // Buffers: the next iteration stages into the other stage buffer and zeroes its own slot
-        // of the other accumulator buffer, whose batch (b + 1) this thread flushed above; the
-        // compute's LDS adds into either accumulator buffer are ordered by the barrier.
+        // Buffers: the next iteration stages into the other stage buffer. The accumulator buffer
+        // of batch b + 1, flushed above, is zeroed before batch b - 1 adds into it: in the plain
+        // form by each thread for its own slot when it stages, in the GEMM forms by the flush
+        // itself, item by item; either way the barrier orders the zeroing before those adds.
     }
     __syncthreads();
     flush(0);
