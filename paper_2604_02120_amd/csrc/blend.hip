@@ -129,6 +129,10 @@ constexpr int kGrad = 9;   // per-Gaussian sums kept per batch
 template <int NB>
 struct BwdAcc {
     float v[2][NB * kGrad];
+    // GEMM forms: whether a slot received any sum (set by the wavefronts that add into it), and
+    // each wavefront's list of its touched slots, built when it flushes
+    uint32_t hit[2][NB];
+    uint16_t list[kBlock / 64][64];
     __device__ float *slot(int ab, int t) { return v[ab] + t * kGrad; }
 };
 
@@ -482,7 +486,8 @@ struct BwdState {
 // contributor, so the skip test alone decides (one compare, whose mask is the ballot).
 template <bool kRanged>
 __device__ inline void reverse_pair(float q, bool in_range, const float4 &ga, const float4 &gb,
-                                    int u, const Lane &L, BwdState &st, float *acc) {
+                                    int u, const Lane &L, BwdState &st, float *acc,
+                                    uint32_t *hit) {
     const bool alive = kRanged ? (in_range && q >= kQCull) : (q >= kQCull);
     const unsigned long long live = __builtin_amdgcn_ballot_w64(alive);
     if (live == 0ull) return;
@@ -513,7 +518,10 @@ __device__ inline void reverse_pair(float q, bool in_range, const float4 &ga, co
         // lane 16r holds s[{0,2,1,3}[r]], lane 16r + 8 holds s[4 + {0,2,1,3}[r]], lane 0 also s8
         const int r = L.l >> 4, k = 2 * (r & 1) + (r >> 1) + (L.l & 8 ? 4 : 0);
         atomicAdd(&acc[k], rab);
-        if (L.l == 0) atomicAdd(&acc[8], rc);
+        if (L.l == 0) {
+            atomicAdd(&acc[8], rc);
+            if (hit) *hit = 1u;
+        }
     }
 }
 
@@ -592,37 +600,44 @@ __device__ inline void bwd_tile(const ViewDesc &v, int64_t tile, Stage<M, NB> &S
             unsafeAtomicAdd(&v.dL_dcolors[3 * id + 2], a9[8]);
         }
     };
-    // GEMM forms: the 9 NB sums of a batch are flushed by the whole block, item e in the order
-    // dL/dconics (3 per slot), dL/dmeans2d (2), dL/dopacity (1), dL/dcolors (3), so that
-    // consecutive lanes add consecutive words of one Gaussian and a wavefront's atomics reach
-    // a third as many cache lines (the global atomics are this kernel's largest cost). Every
-    // segment bound is a multiple of 64 (NB is), so each wavefront takes one branch. The thread
-    // that reads an item also zeroes it for batch bb - 2, which reuses the buffer after the next
-    // barrier.
+    // GEMM forms: wavefront w flushes slots [w NB/4, (w + 1) NB/4). It lists the slots that
+    // received a sum, in slot order, and then spreads their nine sums over its lanes, item j the
+    // sum j % 9 of listed slot j / 9, so that consecutive lanes add consecutive words of one
+    // Gaussian (a wavefront's atomic instruction reaches about 30 cache lines instead of 64) and
+    // no lane is spent on the slots without a sum (over half of a 3-sigma list's). Each item is
+    // zeroed by the lane that reads it, and each flag by the lane that lists it, ready for batch
+    // bb - 2, which reuses the buffers after the next barrier.
     const auto flush_items = [&](int bb) {
+        constexpr int kPer = NB / (kBlock / 64);   // slots per wavefront, at most 64
         float *acc = s_acc.v[bb & 1];
+        uint32_t *hit = s_acc.hit[bb & 1];
         const uint32_t *ids = SB.ids[bb % 3];
-#pragma unroll
-        for (int e0 = 0; e0 < kGrad * NB; e0 += kBlock) {
-            const int e = e0 + L.t;
-            if (e >= kGrad * NB) break;
-            int slot, k, c, stride;
-            float *out;
-            if (e < 3 * NB) {
-                slot = e / 3; c = e - 3 * slot; k = c; out = v.dL_dconics; stride = 3;
-            } else if (e < 5 * NB) {
-                const int f = e - 3 * NB;
-                slot = f >> 1; c = f & 1; k = 3 + c; out = v.dL_dmeans2d; stride = 2;
-            } else if (e < 6 * NB) {
-                slot = e - 5 * NB; c = 0; k = 5; out = v.dL_dopacity; stride = 1;
-            } else {
-                const int f = e - 6 * NB;
-                slot = f / 3; c = f - 3 * slot; k = 6 + c; out = v.dL_dcolors; stride = 3;
-            }
+        uint16_t *list = s_acc.list[L.w];
+        const int s0 = L.w * kPer;
+        bool touched = false;
+        if (L.l < kPer) {
+            touched = hit[s0 + L.l] != 0u;
+            hit[s0 + L.l] = 0u;
+        }
+        const unsigned long long m = __ballot(touched);
+        if (touched) list[__popcll(m & ((1ull << L.l) - 1ull))] = uint16_t(s0 + L.l);
+        __builtin_amdgcn_wave_barrier();   // the list is written and read by this wavefront only
+        const int items = kGrad * __popcll(m);
+#pragma unroll 1
+        for (int j = L.l; j < items; j += 64) {
+            const int i = j / kGrad, k = j - kGrad * i;
+            const int slot = list[i];
             float *p = acc + slot * kGrad + k;
             const float val = *p;
             *p = 0.f;
-            if (val != 0.f) unsafeAtomicAdd(&out[int64_t(stride) * ids[slot] + c], val);
+            if (val != 0.f) {
+                const int64_t id = ids[slot];
+                float *dst = k < 3 ? v.dL_dconics + 3 * id + k
+                           : k < 5 ? v.dL_dmeans2d + 2 * id + (k - 3)
+                           : k == 5 ? v.dL_dopacity + id
+                                    : v.dL_dcolors + 3 * id + (k - 6);
+                unsafeAtomicAdd(dst, val);
+            }
         }
     };
     const auto flush = [&](int bb) {
@@ -631,10 +646,14 @@ __device__ inline void bwd_tile(const ViewDesc &v, int64_t tile, Stage<M, NB> &S
     };
     GRaw nxt = fetch_attrs(entry(nb - 1).id(), n, means, conics, opac, colors);
     Entry ent = entry(nb - 2);
-    if constexpr (M != Mode::Plain) {   // both accumulator buffers start at zero
+    if constexpr (M != Mode::Plain) {   // both accumulator buffers and flags start at zero
         for (int e = L.t; e < NB * kGrad; e += kBlock) {
             s_acc.v[0][e] = 0.f;
             s_acc.v[1][e] = 0.f;
+        }
+        if (L.t < NB) {
+            s_acc.hit[0][L.t] = 0u;
+            s_acc.hit[1][L.t] = 0u;
         }
     }
     for (int b = nb - 1; b >= 0; --b) {
@@ -663,6 +682,7 @@ __device__ inline void bwd_tile(const ViewDesc &v, int64_t tile, Stage<M, NB> &S
             const float4 ga = S.attr[buf][g * kGroup + (L.l & (kGroup - 1))];
             const float4 gb = SB.bwd[buf][g * kGroup + (L.l & (kGroup - 1))];
             float *acc = s_acc.slot(buf, g * kGroup);
+            uint32_t *hit = &s_acc.hit[buf][g * kGroup];
             const int rel = st.last - (base + g * kGroup);   // positions < last are in range
             // the whole group is in range for every lane (the common case once past the lanes'
             // last contributors; never for a partial tile, whose outside lanes have last = 0)
@@ -672,23 +692,25 @@ __device__ inline void bwd_tile(const ViewDesc &v, int64_t tile, Stage<M, NB> &S
 #pragma unroll
                     for (int u = kGroup - 1; u >= 0; --u)
                         reverse_pair<false>(plain_q(S, buf, g * kGroup + u, L), true, ga, gb, u,
-                                            L, st, acc + u * kGrad);
+                                            L, st, acc + u * kGrad, nullptr);
                 } else {
 #pragma unroll
                     for (int u = kGroup - 1; u >= 0; --u)
                         reverse_pair<true>(plain_q(S, buf, g * kGroup + u, L), u < rel, ga, gb, u,
-                                           L, st, acc + u * kGrad);
+                                           L, st, acc + u * kGrad, nullptr);
                 }
             } else {
                 const f16x q = group_q_mfma<M, NB>(S, buf, g, L, bhi, blo);
                 if (whole) {
 #pragma unroll
                     for (int u = kGroup - 1; u >= 0; --u)
-                        reverse_pair<false>(q[u], true, ga, gb, u, L, st, acc + u * kGrad);
+                        reverse_pair<false>(q[u], true, ga, gb, u, L, st, acc + u * kGrad,
+                                            hit + u);
                 } else {
 #pragma unroll
                     for (int u = kGroup - 1; u >= 0; --u)
-                        reverse_pair<true>(q[u], u < rel, ga, gb, u, L, st, acc + u * kGrad);
+                        reverse_pair<true>(q[u], u < rel, ga, gb, u, L, st, acc + u * kGrad,
+                                           hit + u);
                 }
             }
         }
