@@ -115,7 +115,7 @@ struct Stage<Mode::Plain, NB> {  // plain form
 template <int NB>
 struct StageBwd {
     float4 bwd[2][NB];         // (x, y, 1/o, index bits)
-    // GEMM forms: the Gaussian index of each slot of batch b, in ids[b % 3]. The flush of batch
+    // The Gaussian index of each slot of batch b, in ids[b % 3]. The flush of batch
     // b + 1 reads other threads' slots while the next batch is staged; three buffers keep that
     // staging out of the ones being read.
     uint32_t ids[3][NB];
@@ -123,14 +123,14 @@ struct StageBwd {
 
 constexpr int kGrad = 9;   // per-Gaussian sums kept per batch
 
-// Per-Gaussian gradient sums of a batch: 9 words per staged Gaussian (an odd stride, so the
-// flush's per-thread reads of one word index hit distinct banks). Two buffers: batch b sums into
-// buffer b & 1 while batch b + 1's sums are flushed from the other.
+// Per-Gaussian gradient sums of a batch: 9 consecutive words per staged Gaussian, which the
+// flush reads as consecutive words across lanes. Two buffers: batch b sums into buffer b & 1
+// while batch b + 1's sums are flushed from the other.
 template <int NB>
 struct BwdAcc {
     float v[2][NB * kGrad];
-    // GEMM forms: whether a slot received any sum (set by the wavefronts that add into it), and
-    // each wavefront's list of its touched slots, built when it flushes
+    // whether a slot received any sum (set by the wavefronts that add into it), and each
+    // wavefront's list of its touched slots, built when it flushes
     uint32_t hit[2][NB];
     uint16_t list[kBlock / 64][64];
     __device__ float *slot(int ab, int t) { return v[ab] + t * kGrad; }
@@ -480,7 +480,8 @@ struct BwdState {
 // branches (a dead lane takes alpha = 0: its terms vanish and its state is unchanged exactly,
 // since 1 / (1 - 0) = 1),
 // the pair's 9 gradient terms are summed over the wavefront, and the totals are added into the
-// Gaussian's LDS accumulator (`acc`), which the block flushes to global memory once per batch. Raw sums: S_xx, S_xy, S_yy, S_x, S_y (times dL/dpower), dL/do, and the three colour
+// Gaussian's LDS accumulator (`acc`, its flag `hit` set), which the block flushes to global memory
+// once per batch. Raw sums: S_xx, S_xy, S_yy, S_x, S_y (times dL/dpower), dL/do, and the three colour
 // gradients.
 // kRanged = false: the caller has checked that the whole group lies before every lane's last
 // contributor, so the skip test alone decides (one compare, whose mask is the ballot).
@@ -520,7 +521,7 @@ __device__ inline void reverse_pair(float q, bool in_range, const float4 &ga, co
         atomicAdd(&acc[k], rab);
         if (L.l == 0) {
             atomicAdd(&acc[8], rc);
-            if (hit) *hit = 1u;
+            *hit = 1u;
         }
     }
 }
@@ -576,38 +577,14 @@ __device__ inline void bwd_tile(const ViewDesc &v, int64_t tile, Stage<M, NB> &S
         const int64_t o = int64_t(bb) * NB + L.t;
         return load_entry(plist, start + o, bb >= 0 && L.t < NB && o < len, start);
     };
-    // Plain form: thread t < NB flushes the nine sums of slot t (and zeroes them when it stages
-    // the next batch into that slot).
-    const auto flush_slot = [&](int bb) {     // batch bb's sums, accumulator buffer bb & 1
-        if (L.t >= NB) return;
-        float a9[kGrad];
-        const float *src = s_acc.slot(bb & 1, L.t);
-#pragma unroll
-        for (int k = 0; k < kGrad; ++k) a9[k] = src[k];
-        bool any = false;
-#pragma unroll
-        for (int k = 0; k < kGrad; ++k) any |= a9[k] != 0.f;
-        if (any) {
-            const uint32_t id = __float_as_uint(SB.bwd[bb & 1][L.t].w);
-            unsafeAtomicAdd(&v.dL_dconics[3 * id + 0], a9[0]);
-            unsafeAtomicAdd(&v.dL_dconics[3 * id + 1], a9[1]);
-            unsafeAtomicAdd(&v.dL_dconics[3 * id + 2], a9[2]);
-            unsafeAtomicAdd(&v.dL_dmeans2d[2 * id + 0], a9[3]);
-            unsafeAtomicAdd(&v.dL_dmeans2d[2 * id + 1], a9[4]);
-            unsafeAtomicAdd(&v.dL_dopacity[id], a9[5]);
-            unsafeAtomicAdd(&v.dL_dcolors[3 * id + 0], a9[6]);
-            unsafeAtomicAdd(&v.dL_dcolors[3 * id + 1], a9[7]);
-            unsafeAtomicAdd(&v.dL_dcolors[3 * id + 2], a9[8]);
-        }
-    };
-    // GEMM forms: wavefront w flushes slots [w NB/4, (w + 1) NB/4). It lists the slots that
+    // Wavefront w flushes slots [w NB/4, (w + 1) NB/4). It lists the slots that
     // received a sum, in slot order, and then spreads their nine sums over its lanes, item j the
     // sum j % 9 of listed slot j / 9, so that consecutive lanes add consecutive words of one
     // Gaussian (a wavefront's atomic instruction reaches about 30 cache lines instead of 64) and
     // no lane is spent on the slots without a sum (over half of a 3-sigma list's). Each item is
     // zeroed by the lane that reads it, and each flag by the lane that lists it, ready for batch
     // bb - 2, which reuses the buffers after the next barrier.
-    const auto flush_items = [&](int bb) {
+    const auto flush = [&](int bb) {     // batch bb's sums, accumulator buffer bb & 1
         constexpr int kPer = NB / (kBlock / 64);   // slots per wavefront, at most 64
         float *acc = s_acc.v[bb & 1];
         uint32_t *hit = s_acc.hit[bb & 1];
@@ -640,33 +617,22 @@ __device__ inline void bwd_tile(const ViewDesc &v, int64_t tile, Stage<M, NB> &S
             }
         }
     };
-    const auto flush = [&](int bb) {
-        if constexpr (M == Mode::Plain) flush_slot(bb);
-        else flush_items(bb);
-    };
     GRaw nxt = fetch_attrs(entry(nb - 1).id(), n, means, conics, opac, colors);
     Entry ent = entry(nb - 2);
-    if constexpr (M != Mode::Plain) {   // both accumulator buffers and flags start at zero
-        for (int e = L.t; e < NB * kGrad; e += kBlock) {
-            s_acc.v[0][e] = 0.f;
-            s_acc.v[1][e] = 0.f;
-        }
-        if (L.t < NB) {
-            s_acc.hit[0][L.t] = 0u;
-            s_acc.hit[1][L.t] = 0u;
-        }
+    // both accumulator buffers and their flags start at zero
+    for (int e = L.t; e < NB * kGrad; e += kBlock) {
+        s_acc.v[0][e] = 0.f;
+        s_acc.v[1][e] = 0.f;
+    }
+    if (L.t < NB) {
+        s_acc.hit[0][L.t] = 0u;
+        s_acc.hit[1][L.t] = 0u;
     }
     for (int b = nb - 1; b >= 0; --b) {
         const int buf = b & 1;
         if (L.t < NB) {
             stage<M, NB, true>(nxt, buf, L.t, xc, yc, S, &SB);
-            if constexpr (M == Mode::Plain) {
-                float *z = s_acc.slot(buf, L.t);
-#pragma unroll
-                for (int k = 0; k < kGrad; ++k) z[k] = 0.f;
-            } else {
-                SB.ids[b % 3][L.t] = nxt.id;
-            }
+            SB.ids[b % 3][L.t] = nxt.id;
         }
         __syncthreads();
         // unconditional: before the first batch these read entry `start` and Gaussian 0, unused
@@ -692,12 +658,12 @@ __device__ inline void bwd_tile(const ViewDesc &v, int64_t tile, Stage<M, NB> &S
 #pragma unroll
                     for (int u = kGroup - 1; u >= 0; --u)
                         reverse_pair<false>(plain_q(S, buf, g * kGroup + u, L), true, ga, gb, u,
-                                            L, st, acc + u * kGrad, nullptr);
+                                            L, st, acc + u * kGrad, hit + u);
                 } else {
 #pragma unroll
                     for (int u = kGroup - 1; u >= 0; --u)
                         reverse_pair<true>(plain_q(S, buf, g * kGroup + u, L), u < rel, ga, gb, u,
-                                           L, st, acc + u * kGrad, nullptr);
+                                           L, st, acc + u * kGrad, hit + u);
                 }
             } else {
                 const f16x q = group_q_mfma<M, NB>(S, buf, g, L, bhi, blo);
@@ -715,9 +681,8 @@ __device__ inline void bwd_tile(const ViewDesc &v, int64_t tile, Stage<M, NB> &S
             }
         }
         // Buffers: the next iteration stages into the other stage buffer. The accumulator buffer
-        // of batch b + 1, flushed above, is zeroed before batch b - 1 adds into it: in the plain
-        // form by each thread for its own slot when it stages, in the GEMM forms by the flush
-        // itself, item by item; either way the barrier orders the zeroing before those adds.
+        // of batch b + 1 and its flags, flushed above, were zeroed by the flush itself, item by
+        // item; the barrier orders that before batch b - 1 adds into them.
     }
     __syncthreads();
     flush(0);
