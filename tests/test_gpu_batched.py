@@ -65,21 +65,34 @@ def test_batched_equals_single_view(gpu, small_views, prec):
     bv.close()
 
 
-def test_batched_every_shape_same_forward(gpu, small_views):
+@pytest.mark.parametrize("prec", ["fp16", "fp32", "bf16"])
+def test_batched_every_shape_same_results(gpu, small_views, prec):
+    """Every launch shape (LDS batch 64 / 128 / 256 each way, grid or persistent launch): the same
+    images and, up to the order of the gradient atomics, the same gradients as the default plan.
+    The backward's flush splits each batch's slots among the wavefronts differently per batch
+    size, so every size is checked."""
     _, views = small_views
-    bv = api.BatchedViews(views, prec="fp16")
+    bv = api.BatchedViews(views, prec=prec)
     fill_dloss(bv)
     bv.step()
     torch.cuda.synchronize()
     ref = [v["image"].clone() for v in bv.views]
+    ref_g = [[v[k].clone() for k in GRADS] for v in bv.views]
     for cand in autotune.CANDIDATES:
-        say(f"[batched-shape] {cand}")
+        say(f"[batched-shape] {prec} {cand}")
         bv._make_plan(cand)
+        for v in bv.views:
+            for k in GRADS:
+                v[k].fill_(123.0)          # the backward must overwrite every gradient
         bv.forward()
         bv.backward()
         torch.cuda.synchronize()
         for i, v in enumerate(bv.views):
             assert torch.equal(v["image"], ref[i]), (cand, i)
+            for k, r in zip(GRADS, ref_g[i]):
+                e = normwise(v[k].cpu().numpy().astype(np.float64),
+                             r.cpu().numpy().astype(np.float64))
+                assert e <= 1e-5, (cand, i, k, e)
     bv.close()
 
 
