@@ -306,9 +306,10 @@ struct FwdState {
     int last;
 };
 
-// Per-Gaussian values of a group of 16 are read from LDS once per group, one Gaussian per lane
-// (lane l holds Gaussian l % 16); a Gaussian's value is then broadcast from its lane to a scalar
-// register. This keeps LDS reads out of the per-Gaussian dependency chain.
+// Backward: per-Gaussian values of a group of 16 are read from LDS once per group, one Gaussian
+// per lane (lane l holds Gaussian l % 16); a Gaussian's value is then broadcast from its lane to
+// a scalar register. (The forward reads each live Gaussian's four values with one LDS broadcast
+// instead, which spares four vector instructions per Gaussian in its much shorter step.)
 __device__ inline float from_lane(float v, int u) {
     return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), u));
 }
@@ -331,17 +332,17 @@ __device__ inline void composite(float q, float lo2o, float cr, float cg, float 
     st.thr = (hit && stop) ? INFINITY : st.thr;
 }
 
-// Composites the 16 Gaussians of one group; q(u) gives Gaussian u's exponent for this lane.
+// Composites the 16 Gaussians of one group; q(u) gives Gaussian u's exponent for this lane. A
+// Gaussian that some lane takes has its (log2 o, r, g, b) read at one LDS address by every lane.
 template <typename QFn>
-__device__ inline void composite_group(const float4 *attr, int base, const Lane &L, FwdState &st,
+__device__ inline void composite_group(const float4 *attr, int base, FwdState &st,
                                        QFn q_of) {
-    const float4 ga = attr[L.l & (kGroup - 1)];   // (log2 o, r, g, b) of Gaussian l % 16
 #pragma unroll
     for (int u = 0; u < kGroup; ++u) {
         const float q = q_of(u);
         if (__builtin_amdgcn_ballot_w64(q >= st.thr) == 0ull) continue;   // no lane takes it
-        composite(q, from_lane(ga.x, u), from_lane(ga.y, u), from_lane(ga.z, u),
-                  from_lane(ga.w, u), base + u, st);
+        const float4 a = attr[u];      // one address for every lane: an LDS broadcast
+        composite(q, a.x, a.y, a.z, a.w, base + u, st);
     }
 }
 
@@ -398,11 +399,11 @@ __device__ inline void fwd_tile(const ViewDesc &v, int64_t tile, Stage<M, NB> &S
             if (__ballot(st.thr != INFINITY) == 0) break;
             const float4 *attr = &S.attr[buf][g * kGroup];
             if constexpr (M == Mode::Plain) {
-                composite_group(attr, base + g * kGroup, L, st,
+                composite_group(attr, base + g * kGroup, st,
                                 [&](int u) { return plain_q(S, buf, g * kGroup + u, L); });
             } else {
                 const f16x q = group_q_mfma<M, NB>(S, buf, g, L, bhi, blo);
-                composite_group(attr, base + g * kGroup, L, st, [&](int u) { return q[u]; });
+                composite_group(attr, base + g * kGroup, st, [&](int u) { return q[u]; });
             }
         }
     }
