@@ -306,14 +306,6 @@ struct FwdState {
     int last;
 };
 
-// Backward: per-Gaussian values of a group of 16 are read from LDS once per group, one Gaussian
-// per lane (lane l holds Gaussian l % 16); a Gaussian's value is then broadcast from its lane to
-// a scalar register. (The forward reads each live Gaussian's four values with one LDS broadcast
-// instead, which spares four vector instructions per Gaussian in its much shorter step.)
-__device__ inline float from_lane(float v, int u) {
-    return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), u));
-}
-
 // One front-to-back step (Alg. 1 / Alg. 2 inner loop) for this lane's pixel, without branches:
 // a skipped pair or a finished pixel leaves the state unchanged.
 __device__ inline void composite(float q, float lo2o, float cr, float cg, float cb, int pos,
@@ -487,15 +479,14 @@ struct BwdState {
 // kRanged = false: the caller has checked that the whole group lies before every lane's last
 // contributor, so the skip test alone decides (one compare, whose mask is the ballot).
 template <bool kRanged>
-__device__ inline void reverse_pair(float q, bool in_range, const float4 &ga, const float4 &gb,
+__device__ inline void reverse_pair(float q, bool in_range, const float4 *ga, const float4 *gb,
                                     int u, const Lane &L, BwdState &st, float *acc,
                                     uint32_t *hit) {
     const bool alive = kRanged ? (in_range && q >= kQCull) : (q >= kQCull);
     const unsigned long long live = __builtin_amdgcn_ballot_w64(alive);
     if (live == 0ull) return;
-    const float4 attr = make_float4(from_lane(ga.x, u), from_lane(ga.y, u), from_lane(ga.z, u),
-                                    from_lane(ga.w, u));
-    const float4 bw = make_float4(from_lane(gb.x, u), from_lane(gb.y, u), from_lane(gb.z, u), 0.f);
+    const float4 attr = ga[u];   // one address for every lane: LDS broadcasts
+    const float4 bw = gb[u];
     // a dead lane has q < log2(1/255) or is past its last contributor: it blended nothing here
     const float araw = __builtin_amdgcn_exp2f(fminf(q, attr.x));
     const float a = alive ? fminf(araw, kAlphaMax) : 0.f;
@@ -646,8 +637,8 @@ __device__ inline void bwd_tile(const ViewDesc &v, int64_t tile, Stage<M, NB> &S
         for (int g = ng - 1; g >= 0; --g) {
             // nothing to do for this wave unless one of its pixels blended past the group start
             if (__ballot(st.last > base + g * kGroup) == 0) continue;
-            const float4 ga = S.attr[buf][g * kGroup + (L.l & (kGroup - 1))];
-            const float4 gb = SB.bwd[buf][g * kGroup + (L.l & (kGroup - 1))];
+            const float4 *ga = &S.attr[buf][g * kGroup];   // the group's staged values
+            const float4 *gb = &SB.bwd[buf][g * kGroup];
             float *acc = s_acc.slot(buf, g * kGroup);
             uint32_t *hit = &s_acc.hit[buf][g * kGroup];
             const int rel = st.last - (base + g * kGroup);   // positions < last are in range
