@@ -483,7 +483,20 @@ __device__ inline void reverse_pair(float q, bool in_range, const float4 *ga, co
                                     int u, const Lane &L, BwdState &st, float *acc,
                                     uint32_t *hit) {
     const bool alive = kRanged ? (in_range && q >= kQCull) : (q >= kQCull);
-    const unsigned long long live = __builtin_amdgcn_ballot_w64(alive);
+    unsigned long long live;
+    if constexpr (kRanged) {
+        // one ballot per compare (each is just that compare's lane mask), combined and tested in
+        // scalar registers: a ballot of the combined condition is copied through a vector
+        // register, two more vector instructions for every Gaussian of a ranged group. The empty
+        // asm statements keep the compiler from merging the two ballots back into one.
+        unsigned long long m_range = __builtin_amdgcn_ballot_w64(in_range);
+        unsigned long long m_cull = __builtin_amdgcn_ballot_w64(q >= kQCull);
+        asm volatile("" : "+s"(m_range));
+        asm volatile("" : "+s"(m_cull));
+        live = m_range & m_cull;
+    } else {
+        live = __builtin_amdgcn_ballot_w64(alive);
+    }
     if (live == 0ull) return;
     const float4 attr = ga[u];   // one address for every lane: LDS broadcasts
     const float4 bw = gb[u];
