@@ -461,6 +461,13 @@ __device__ inline void wave_sum9(const float (&s)[kGrad], int lane, float &ab, f
     asm volatile("" : "+v"(ab), "+v"(c));
 }
 
+// The word of a Gaussian's nine sums that a leader lane (l % 8 == 0) adds after wave_sum9:
+// lane 16r holds s[{0,2,1,3}[r]], lane 16r + 8 holds s[4 + {0,2,1,3}[r]] (lane 0 also s8).
+__device__ inline int sum_word(int l) {
+    const int r = l >> 4;
+    return 2 * (r & 1) + (r >> 1) + (l & 8 ? 4 : 0);
+}
+
 struct BwdState {
     float T;        // transmittance in front of the pairs not yet visited
     float behind;   // T_final (bg . g) + sum over the visited pairs of alpha T (c . g)
@@ -473,8 +480,8 @@ struct BwdState {
 // branches (a dead lane takes alpha = 0: its terms vanish and its state is unchanged exactly,
 // since 1 / (1 - 0) = 1),
 // the pair's 9 gradient terms are summed over the wavefront, and the totals are added into the
-// Gaussian's LDS accumulator (`acc`, its flag `hit` set), which the block flushes to global memory
-// once per batch. Raw sums: S_xx, S_xy, S_yy, S_x, S_y (times dL/dpower), dL/do, and the three colour
+// Gaussian's LDS accumulator (`acc` points at the word this lane adds when it leads, see
+// sum_word; the flag `hit` is set), which the block flushes to global memory once per batch. Raw sums: S_xx, S_xy, S_yy, S_x, S_y (times dL/dpower), dL/do, and the three colour
 // gradients.
 // kRanged = false: the caller has checked that the whole group lies before every lane's last
 // contributor, so the skip test alone decides (one compare, whose mask is the ballot).
@@ -521,11 +528,10 @@ __device__ inline void reverse_pair(float q, bool in_range, const float4 *ga, co
     float rab, rc;
     wave_sum9(s, L.l, rab, rc);
     if ((L.l & 7) == 0) {
-        // lane 16r holds s[{0,2,1,3}[r]], lane 16r + 8 holds s[4 + {0,2,1,3}[r]], lane 0 also s8
-        const int r = L.l >> 4, k = 2 * (r & 1) + (r >> 1) + (L.l & 8 ? 4 : 0);
-        atomicAdd(&acc[k], rab);
+        // acc is this lane's word of the Gaussian's sums (see sum_word); lane 0's is word 0
+        atomicAdd(acc, rab);
         if (L.l == 0) {
-            atomicAdd(&acc[8], rc);
+            atomicAdd(acc + 8, rc);
             *hit = 1u;
         }
     }
@@ -544,6 +550,7 @@ __device__ inline void bwd_tile(const ViewDesc &v, int64_t tile, Stage<M, NB> &S
     const F3 *colors = reinterpret_cast<const F3 *>(v.colors);
     const float *opac = v.opacity;
     const Lane L = lane_setup(tile, v.gx, v.W, v.H);
+    const int word = sum_word(L.l);   // the sum this lane adds when it leads a reduction
     const float xc = float(int(tile % v.gx) * kTile) + 7.5f, yc = float(int(tile / v.gx) * kTile) + 7.5f;
     typename Op<M>::vec bhi, blo;
     pixel_basis<M>(L, bhi, blo);
@@ -652,7 +659,7 @@ __device__ inline void bwd_tile(const ViewDesc &v, int64_t tile, Stage<M, NB> &S
             if (__ballot(st.last > base + g * kGroup) == 0) continue;
             const float4 *ga = &S.attr[buf][g * kGroup];   // the group's staged values
             const float4 *gb = &SB.bwd[buf][g * kGroup];
-            float *acc = s_acc.slot(buf, g * kGroup);
+            float *acc = s_acc.slot(buf, g * kGroup) + word;   // this lane's word, Gaussian 0
             uint32_t *hit = &s_acc.hit[buf][g * kGroup];
             const int rel = st.last - (base + g * kGroup);   // positions < last are in range
             // the whole group is in range for every lane (the common case once past the lanes'
