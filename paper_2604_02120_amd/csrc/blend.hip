@@ -425,10 +425,12 @@ constexpr int kDppQuadRev = 0x1b, kDppQuadSwap = 0xb1;       // quad_perm [3,2,1
 // Sum of 9 values over the whole wavefront, transposed so that the 9 totals land in distinct
 // lanes (two values share each swap-and-add, so the wavefront is halved per value pair, not per
 // value):
-//   permlane32_swap + add on the pairs (s0,s1) (s2,s3) (s4,s5) (s6,s7), and s8 with itself:
-//       lanes 0-31 hold the first value's 32 partial sums, lanes 32-63 the second's;
+//   permlane32_swap + add on the pairs (s0,s1) (s2,s3) (s4,s5) (s6,s7): lanes 0-31 hold the
+//       first value's 32 partial sums, lanes 32-63 the second's; s8, which has no partner, adds
+//       lane l ^ 32 through ds_bpermute;
 //   permlane16_swap + add on the register pairs: rows (16 lanes) of a hold (s0, s2, s1, s3),
-//       rows of b hold (s4, s6, s5, s7), every row of c holds s8;
+//       rows of b hold (s4, s6, s5, s7); s8 adds lane l ^ 16 through ds_swizzle, so every row of
+//       c holds s8;
 //   a and b share one register from here: lanes 0-7 of a row take a's row values, lanes 8-15
 //       b's, each summed with the lane 8 away (row_ror 8); then half_mirror, and two quad
 //       permutations finish each 8-lane half; c takes the same four steps alone.
@@ -443,13 +445,16 @@ __device__ inline float swap_add16(float x, float y) {    // rows: [x0+x1, y0+y1
     return __uint_as_float(r[0]) + __uint_as_float(r[1]);
 }
 __device__ inline void wave_sum9(const float (&s)[kGrad], int lane, float &ab, float &c) {
-    float x0 = s[0], x2 = s[2], x4 = s[4], x6 = s[6], x8 = s[8];
+    float x0 = s[0], x2 = s[2], x4 = s[4], x6 = s[6];
     const float p01 = swap_add32(x0, s[1]), p23 = swap_add32(x2, s[3]);
     const float p45 = swap_add32(x4, s[5]), p67 = swap_add32(x6, s[7]);
-    const float p88 = swap_add32(x8, s[8]);
+    // the ninth value alone: lane l adds lane l ^ 32 (ds_bpermute), then lane l ^ 16 (ds_swizzle,
+    // xor mask 16 within each 32-lane half); both go through the LDS crossbar, not the VALU
+    const float p88 = s[8] + __int_as_float(__builtin_amdgcn_ds_bpermute((lane ^ 32) << 2,
+                                                                        __float_as_int(s[8])));
     const float a = swap_add16(p01, p23);
     const float b = swap_add16(p45, p67);
-    c = swap_add16(p88, p88);
+    c = p88 + __int_as_float(__builtin_amdgcn_ds_swizzle(__float_as_int(p88), 0x401f));
     const bool lo = (lane & 8) == 0;
     ab = dpp_add2<kDppRowRor8>(lo ? a : b, lo ? b : a);
     c = dpp_add2<kDppRowRor8>(c, c);
