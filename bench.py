@@ -21,6 +21,8 @@ tile extent), `pipeline_3d` (the step preceded by projecting 1M 3D Gaussians), `
                     [--no-batched]
     python bench.py --sweep            # LDS batch size and resolution sweeps
     python bench.py --pipeline-only    # the 3D leg alone
+    python bench.py --config C5        # the same line for another workload (C3: 1280x720, 500k;
+                                       # C5: 3840x2160, 3M); counters are attached for C2 only
 """
 from __future__ import annotations
 
@@ -50,6 +52,8 @@ PEAK_ALU_TFLOPS = 256 * 4 * 16 * 2 * 2.4e9 / 1e12
 #   backward: 16 per revisited pair + 39 per blended pair
 FLOPS = {"forward": (16, 10), "backward": (16, 39)}
 COUNTS = os.path.join(ROOT, "tests", "golden", "workload_counts.json")
+COUNTERS_CONFIG = "C2"     # the workload whose rocprofv3 counters profiles/traffic.json holds
+OPACITY_LAW = {"uniform": "U(0.05, 0.99)", "beta22": "Beta(2, 2) x 0.99"}
 TRAFFIC = os.path.join(ROOT, "profiles", "traffic.json")
 KERNEL_SRC = os.path.join(ROOT, "paper_2604_02120_amd", "csrc", "blend.hip")
 PROJECT_SRC = os.path.join(ROOT, "paper_2604_02120_amd", "csrc", "project.hip")
@@ -60,7 +64,7 @@ def parse():
     p.add_argument("--gpus", type=int, default=1)
     p.add_argument("--steps", type=int, default=20)
     p.add_argument("--warmup", type=int, default=5)
-    p.add_argument("--config", default="C2", choices=["C2", "C3"])
+    p.add_argument("--config", default="C2", choices=["C2", "C3", "C5"])
     p.add_argument("--precs", default="fp16,fp32,bf16",
                    help="comma list; the first is the headline")
     p.add_argument("--no-cpu-baseline", action="store_true")
@@ -397,8 +401,9 @@ def kernel_hash(src: str = None) -> str:
     return hashlib.sha256(open(src or KERNEL_SRC, "rb").read()).hexdigest()[:16]
 
 
-def roofline(res: dict, counts: dict) -> dict:
-    """ALU roofline of the dominant blend kernel (the slower of forward / backward)."""
+def roofline(res: dict, counts: dict, config: str = "C2") -> dict:
+    """ALU roofline of the dominant blend kernel (the slower of forward / backward). The measured
+    HBM traffic is attached only for the workload the counters were taken on."""
     kern = "backward" if res["bwd_ms"] >= res["fwd_ms"] else "forward"
     per_pair, per_blend = FLOPS[kern]
     pairs = counts["E"] if kern == "forward" else counts["Eb"]
@@ -406,7 +411,7 @@ def roofline(res: dict, counts: dict) -> dict:
     ms = res["fwd_ms"] if kern == "forward" else res["bwd_ms"]
     achieved = flops / (ms * 1e-3) / 1e12
     traffic = None
-    if os.path.exists(TRAFFIC):
+    if os.path.exists(TRAFFIC) and config == COUNTERS_CONFIG:
         tr = json.load(open(TRAFFIC))
         ent = tr.get(kern)
         if ent and ent.get("kernel_sha") == kernel_hash():
@@ -534,13 +539,14 @@ def main():
         "dtype": {"fp16": "f16+f32", "bf16": "bf16+f32", "fp32": "f32"}[precs[0]],
         "data": "synthetic",
         "config": {"workload": f"{cfg.name}: {fr.W}x{fr.H}, {fr.n} projected Gaussians, "
-                               "log-normal sigma (median 2 px); step = bin + forward + backward",
+                               f"log-normal sigma (median {cfg.sigma_a:g} px), opacity "
+                               f"{OPACITY_LAW[cfg.opacity_law]}; step = bin + forward + backward",
                    "width": fr.W, "height": fr.H, "gaussians": fr.n, "pairs": fr.pairs,
                    "precision": precs[0], "parallelism": "single GPU"},
         "blend_mpix_s": round(head["blend_mpix_s"], 3),
         "breakdown_ms": {k: round(head[k], 4) for k in ("bin_ms", "fwd_ms", "bwd_ms")},
-        "roofline": roofline(head, counts),
-        "counters": counter_fractions(),
+        "roofline": roofline(head, counts, args.config),
+        "counters": counter_fractions() if args.config == COUNTERS_CONFIG else None,
         "paths": {p: {k: (round(v, 4) if isinstance(v, float) else v) for k, v in r.items()}
                   for p, r in results.items()},
         "paper_context": PAPER_CONTEXT,
