@@ -425,6 +425,64 @@ def test_work_counters():
     assert c["K"] == int(f["n_contrib"].sum()) and c["Eb"] == int(f["last_contrib"].sum())
 
 
+def tile_stacks_scene():
+    """A 40x20 image (3 x 2 tiles; the right tile column is 8 px wide, the bottom row 4 px high)
+    where tile t = ty * 3 + tx holds its own stack of k_t = (7, 1, 3, 2, 5, 4) nearly flat
+    Gaussians (conic 1e-8 I, so alpha = 0.8 (1 - O(1e-6)) on every pixel of the tile; radius 1 at
+    (16 tx + 4, 16 ty + 2) covers that tile alone), plus, in front of tile 4's stack, one sharp
+    Gaussian (conic 100 I, o = 0.99) on pixel (20, 18) that reaches alpha >= 1/255 there only."""
+    k = (7, 1, 3, 2, 5, 4)
+    means, depth = [], []
+    for t, kt in enumerate(k):
+        tx, ty = t % 3, t // 3
+        for j in range(kt):
+            means.append((16 * tx + 4.0, 16 * ty + 2.0))
+            depth.append(10.0 * (t + 1) + j)
+    n = len(means)
+    s = {"width": 40, "height": 20,
+         "means2d": np.array(means + [(20.0, 18.0)], np.float32),
+         "conics": np.array([[1e-8, 0.0, 1e-8]] * n + [[100.0, 0.0, 100.0]], np.float32),
+         "opacity": np.array([0.8] * n + [0.99], np.float32),
+         "colors": np.full((n + 1, 3), 0.5, np.float32),
+         "depths": np.array(depth + [1.0], np.float32),
+         "radii": np.ones(n + 1, np.int32)}
+    return s
+
+
+def test_work_counts_hand_fixture():
+    """E, Eb, K, F and P of a scene whose per-pixel stop positions follow by hand (the F of
+    work_counts is the per-tile maximum of the stop position, summed over tiles; a reshape or
+    transpose of its tile grouping changes it). Transmittance 0.2^j after j blends of alpha 0.8:
+    a stack of k blends min(k, 5) (the 6th would take T to 6.4e-5 < 1e-4), so a pixel evaluates
+    min(k, 6) entries and its last contributor is position min(k, 5). On pixel (20, 18) the sharp
+    Gaussian blends first (T = 0.01), then 0.002 and 0.0004, and the third stack member would take
+    T to 8e-5: 4 evaluations, 3 blends, last contributor 3; tile 4's other 63 pixels skip it
+    (alpha ~ 0.99 e^-50 one pixel away) and blend all 5: 6 evaluations, last contributor 6."""
+    s = tile_stacks_scene()
+    f = oracle.render(s)
+    c = oracle.work_counts(f, f["ranges"])
+    px = (256, 256, 128, 64, 64, 32)            # pixels of tiles 0..5 inside the 40x20 image
+    n_eval = (6, 1, 3, 2, 6, 4)                  # per pixel; tile 4's exception is pixel (20, 18)
+    blends = (5, 1, 3, 2, 5, 4)
+    last = (5, 1, 3, 2, 6, 4)
+    E = sum(p * e for p, e in zip(px, n_eval)) - 6 + 4
+    K = sum(p * b for p, b in zip(px, blends)) - 5 + 3
+    Eb = sum(p * l for p, l in zip(px, last)) - 6 + 3
+    assert (E, K, Eb) == (2814, 2494, 2557)
+    assert f["n_eval"][18, 20] == 4 and f["last_contrib"][18, 20] == 3
+    assert c == {"E": E, "Eb": Eb, "K": K, "F": 6 + 1 + 3 + 2 + 6 + 4, "P": 7 + 1 + 3 + 2 + 6 + 4}
+    # F against a pixel loop over each tile's own pixels, on a scene with uneven stops
+    s2 = gsinputs.make_scene("C1", seed=12, n=600, width=70, height=37)
+    f2 = oracle.render(s2)
+    gx, gy = oracle.grid(70, 37)
+    F = 0
+    for t in range(gx * gy):
+        tx, ty = t % gx, t // gx
+        F += max(int(f2["n_eval"][py, px_]) for py in range(16 * ty, min(16 * ty + 16, 37))
+                 for px_ in range(16 * tx, min(16 * tx + 16, 70)))
+    assert oracle.work_counts(f2, f2["ranges"])["F"] == F
+
+
 def test_bin_tile_matches_bruteforce():
     s = small_scene(14, depth_levels=3)
     W, H = s["width"], s["height"]
@@ -492,6 +550,85 @@ def test_visible_binning_drops_only_invisible_pairs(name):
             assert amax < TAU * math.exp(-0.05), (name, t, i, amax)
             dropped += 1
     assert dropped > 0.2 * len(pl0), (name, dropped, len(pl0))
+
+
+def rect_min_q(m, conic, x0, x1, y0, y1):
+    """Minimum of Q(p) = d^T Sigma^-1 d, d = m - p, over the closed rectangle [x0, x1] x [y0, y1]
+    of pixel positions, and a point where it is reached: the mean itself when it lies inside,
+    else the best of the four edge minima, each edge the 1D quadratic Q restricted to it minimised
+    at its stationary point clamped to the edge (every edge is tried, not only those facing the
+    mean)."""
+    a, b, c = (float(v) for v in conic)
+    mx, my = float(m[0]), float(m[1])
+    if x0 <= mx <= x1 and y0 <= my <= y1:
+        return 0.0, mx, my
+
+    def q(px, py):
+        dx, dy = mx - px, my - py
+        return a * dx * dx + 2.0 * b * dx * dy + c * dy * dy
+
+    best = (math.inf, 0.0, 0.0)
+    for px in (x0, x1):                      # vertical edges: dQ/dpy = 0 at py = my + b dx / c
+        py = min(max(my + b * (mx - px) / c, y0), y1)
+        best = min(best, (q(px, py), px, py))
+    for py in (y0, y1):                      # horizontal edges
+        px = min(max(mx + b * (my - py) / a, x0), x1)
+        best = min(best, (q(px, py), px, py))
+    return best
+
+
+def visibility_threshold(o):
+    """2 (e ln 2 + m - 1) + 0.1 with 255 o = m 2^e, m in [1, 2), from numpy's frexp."""
+    mant, ex = np.frexp(255.0 * float(o))
+    return 2.0 * ((int(ex) - 1) * math.log(2.0) + (2.0 * float(mant) - 1.0)) + 0.1
+
+
+@pytest.mark.parametrize("name", list(VIS_SCENES))
+def test_visible_binning_matches_rectangle_minimum(name):
+    """Mode 1 in both directions against an independent minimum of Q over each tile's pixel
+    rectangle (clipped to the image): a kept pair has min Q <= theta (+ rounding), and a pair of the
+    3-sigma square with min Q < theta (- rounding) and o >= fp32(1/255) is kept. The analytic
+    minimum is cross-checked against Q on a 1/8-pixel grid of the rectangle."""
+    s = VIS_SCENES[name]()
+    W, H = s["width"], s["height"]
+    gx, gy = oracle.grid(W, H)
+    pl0, rg0 = oracle.bin_tiles(s["means2d"], s["radii"], s["depths"], W, H)
+    pl1, rg1 = oracle.bin_tiles(s["means2d"], s["radii"], s["depths"], W, H, s["conics"],
+                                s["opacity"], oracle.BIN_VISIBLE)
+    tau32 = float(np.float32(1.0) / np.float32(255.0))
+    checked = 0
+    for t in range(gx * gy):
+        tx, ty = t % gx, t // gx
+        x0, y0 = 16.0 * tx, 16.0 * ty
+        x1, y1 = min(x0 + 15.0, W - 1.0), min(y0 + 15.0, H - 1.0)
+        kept = set(pl1[rg1[t, 0]:rg1[t, 1]].tolist())
+        for i in pl0[rg0[t, 0]:rg0[t, 1]].tolist():
+            o = float(s["opacity"][i])
+            mq, qx, qy = rect_min_q(s["means2d"][i], s["conics"][i], x0, x1, y0, y1)
+            if checked % 7 == 0:                 # the analytic minimum against a dense grid
+                h = 0.125
+                X, Y = np.meshgrid(np.arange(x0, x1 + 1e-9, h), np.arange(y0, y1 + 1e-9, h))
+                a, b, c = (float(v) for v in s["conics"][i])
+                mx, my = float(s["means2d"][i][0]), float(s["means2d"][i][1])
+                dx, dy = mx - X, my - Y
+                dense = float(np.min(a * dx * dx + 2 * b * dx * dy + c * dy * dy))
+                # every grid point is in the rectangle: the minimum is not above any of them
+                assert mq <= dense * (1 + 1e-12) + 1e-12, (name, t, i, mq, dense)
+                # the grid point nearest the minimiser (within h / sqrt 2) bounds it from above:
+                # Q(p* + v) <= Q(p*) + |grad Q(p*)| |v| + lmax |v|^2
+                ex, ey = mx - qx, my - qy
+                grad = 2.0 * math.hypot(a * ex + b * ey, b * ex + c * ey)
+                lmax = 0.5 * (a + c) + math.hypot(0.5 * (a - c), b)
+                v = h / math.sqrt(2.0)
+                assert dense <= mq + grad * v + lmax * v * v + 1e-9, (name, t, i, mq, dense)
+            checked += 1
+            th = visibility_threshold(o)
+            eps = 1e-9 * (1.0 + th)
+            if i in kept:
+                assert o >= tau32 and mq <= th + eps, (name, t, i, mq, th)
+            elif o >= tau32:
+                assert mq >= th - eps, (name, t, i, mq, th)
+    assert checked > 0
 
 
 @pytest.mark.parametrize("name", list(VIS_SCENES))
