@@ -52,7 +52,7 @@ typedef int32_t gsb_precision;
 #define GSB_FP16_GEMM 1   /* exponent as an MFMA product, FP16 hi+lo operands, FP32 accumulate */
 #define GSB_BF16_GEMM 2   /* same with BF16 hi+lo operands */
 
-#define GSB_ABI_VERSION 3
+#define GSB_ABI_VERSION 4
 
 /* Version of this interface (GSB_ABI_VERSION of the library that was loaded). */
 int32_t gsb_abi_version(void);
@@ -171,6 +171,26 @@ gsb_status gsb_bin_fill(const float *means2d, const int32_t *radii, const float 
                         int32_t W, int32_t H, void *ws, size_t ws_bytes, uint32_t *point_list,
                         int64_t pair_capacity, uint32_t *ranges, int32_t *status_dev,
                         void *stream);
+
+/* For callers that cannot allocate device memory (code under hipGraph capture, tight serving
+ * loops, harnesses that forbid hipMalloc): gsb_bin_count followed by gsb_bin_fill in one call, with
+ * the workspace taken from an array that the library holds in device memory instead of a caller
+ * buffer. Nothing is allocated or freed, by the library or on its behalf.
+ * The array is GSB_NOALLOC_SCRATCH_BYTES (64 MiB) on every GPU the library runs on, held until the
+ * process ends; the call fails with INVALID when gsb_bin_workspace_bytes(n, pair_capacity, W, H)
+ * exceeds it (e.g. 300,000 Gaussians with 3M pairs fit; a 1080p frame of 1M Gaussians does not).
+ * Arguments and results are those of gsb_bin_count + gsb_bin_fill: *n_pairs_dev receives the total
+ * pair count; point_list / ranges / status_dev as in gsb_bin_fill (status GSB_ERR_CAPACITY when
+ * the count exceeds pair_capacity, which the caller therefore chooses as a bound beforehand).
+ * All calls on one GPU share the array: two calls in flight at once on that GPU (on different
+ * streams, or from different threads) race and give unspecified results; serialise them.
+ * Errors: INVALID (as the two calls, or a workspace larger than the array), UNSUPPORTED, HIP. */
+#define GSB_NOALLOC_SCRATCH_BYTES ((size_t)64 << 20)
+gsb_status gsb_bin_noalloc(const float *means2d, const int32_t *radii, const float *conics,
+                           const float *opacity, gsb_bin_mode mode, const float *depths,
+                           int64_t n, int32_t W, int32_t H, uint32_t *point_list,
+                           int64_t pair_capacity, uint32_t *ranges, int64_t *n_pairs_dev,
+                           int32_t *status_dev, void *stream);
 
 /* ---------------------------------------------------------------------------------------------
  * Forward blend (Eq. (volume-render) with the per-pixel loop of Alg. 1; in the GEMM precisions

@@ -32,8 +32,7 @@ GSB_LAUNCH_GRID = 1
 
 # every function declared in include/gsblend.h
 EXPORTS = ("gsb_abi_version", "gsb_last_error", "gsb_project", "gsb_bin_workspace_bytes",
-           "gsb_bin_count",
-           "gsb_bin_fill", "gsb_blend_forward", "gsb_blend_backward", "gsb_plan_create",
+           "gsb_bin_count", "gsb_bin_fill", "gsb_bin_noalloc", "gsb_blend_forward", "gsb_blend_backward", "gsb_plan_create",
            "gsb_plan_destroy", "gsb_blend_batched_forward", "gsb_blend_batched_backward")
 
 
@@ -91,6 +90,7 @@ def load() -> ctypes.CDLL:
     lib.gsb_bin_workspace_bytes.argtypes = [i64, i64, i32, i32, ctypes.POINTER(sz)]
     lib.gsb_bin_count.argtypes = [P, P, P, P, i32, i64, i32, i32, P, sz, P, P]
     lib.gsb_bin_fill.argtypes = [P, P, P, P, i32, P, i64, i32, i32, P, sz, P, i64, P, P, P]
+    lib.gsb_bin_noalloc.argtypes = [P, P, P, P, i32, P, i64, i32, i32, P, i64, P, P, P, P]
     lib.gsb_blend_forward.argtypes = [i32, i32, P, P, P, P, P, P, i64, P, i32, P, P, P, P]
     lib.gsb_blend_backward.argtypes = [i32, i32, P, P, P, P, P, P, i64, P, i32, P, P, P, P, P,
                                        P, P, P]
@@ -152,6 +152,18 @@ def gsb_bin_fill(means2d: int, radii: int, depths: int, n: int, W: int, H: int, 
                  mode: int = 0) -> None:
     _check(load().gsb_bin_fill(means2d, radii, conics, opacity, mode, depths, n, W, H, ws,
                                ws_bytes, point_list, pair_capacity, ranges, status_dev, stream))
+
+
+def gsb_bin_noalloc(means2d: int, radii: int, depths: int, n: int, W: int, H: int,
+                    point_list: int, pair_capacity: int, ranges: int, n_pairs_dev: int,
+                    status_dev: int, stream: int = 0, conics: int = 0, opacity: int = 0,
+                    mode: int = 0) -> None:
+    _check(load().gsb_bin_noalloc(means2d, radii, conics, opacity, mode, depths, n, W, H,
+                                  point_list, pair_capacity, ranges, n_pairs_dev, status_dev,
+                                  stream))
+
+
+GSB_NOALLOC_SCRATCH_BYTES = 64 << 20
 
 
 def gsb_blend_forward(W: int, H: int, ranges: int, point_list: int, means2d: int, conics: int,

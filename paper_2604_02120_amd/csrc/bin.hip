@@ -14,6 +14,7 @@
 // integer arithmetic (floor((x - r)/16) == (floor(x) - r) >> 4 for integer r).
 #include <hip/hip_runtime.h>
 
+#include <mutex>
 #include <utility>
 
 #include "gsb_internal.h"
@@ -1039,6 +1040,51 @@ gsb_status bin_fill(const float *means2d, const int32_t *radii, const float *con
     if (cap > 0)
         k_ranges<<<dim3(unsigned((cap + 1023) / 1024)), 256, 0, s>>>(tiles_sorted, hdr, ranges);
     return check_launch("bin_fill");
+}
+
+// ------------------------------------------------------------------------------- no-alloc binning
+// Library-held binning workspace for callers that cannot allocate device memory. One copy of the
+// array lives on every GPU the library runs on, at its own address, from module load to process
+// end. In host code the name `scratch` only stands in for the symbol: its device address comes
+// from hipGetSymbolAddress, once per device, with that device current, and only that address is
+// passed to kernels.
+static __device__ __align__(256) unsigned char scratch[GSB_NOALLOC_SCRATCH_BYTES];
+
+namespace {
+constexpr int kScratchDevices = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[kScratchDevices];   // device address of `scratch` per device (null = not yet)
+}  // namespace
+
+gsb_status bin_noalloc(const float *means2d, const int32_t *radii, const float *conics,
+                       const float *opacity, int32_t mode, const float *depths, int64_t n,
+                       int32_t W, int32_t H, uint32_t *point_list, int64_t cap, uint32_t *ranges,
+                       int64_t *n_pairs_dev, int32_t *status_dev, hipStream_t s) {
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return fail(GSB_ERR_HIP, "hipGetDevice: %s", hipGetErrorString(e));
+    if (dev < 0 || dev >= kScratchDevices)
+        return fail(GSB_ERR_UNSUPPORTED, "device id %d out of range", dev);
+    void *ws = nullptr;
+    {
+        std::lock_guard<std::mutex> lock(g_scratch_mu);
+        if (g_scratch_ptr[dev] == nullptr) {
+            void *p = nullptr;
+            e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+            if (e != hipSuccess || p == nullptr)
+                return fail(GSB_ERR_HIP, "hipGetSymbolAddress(scratch): %s", hipGetErrorString(e));
+            g_scratch_ptr[dev] = p;
+        }
+        ws = g_scratch_ptr[dev];
+    }
+    // Every word of the workspace that the binning reads is written earlier in the same call
+    // (counts, scans, the sort state and look-back words are initialised by its own kernels), so
+    // what a previous call left in the array needs no clearing.
+    const gsb_status st = bin_count(means2d, radii, conics, opacity, mode, n, W, H, ws,
+                                    n_pairs_dev, s);
+    if (st != GSB_OK) return st;
+    return bin_fill(means2d, radii, conics, opacity, mode, depths, n, W, H, ws, point_list, cap,
+                    ranges, status_dev, s);
 }
 
 }  // namespace gsb

@@ -217,6 +217,30 @@ gsb_status gsb_bin_fill(const float *means2d, const int32_t *radii, const float 
                     pair_capacity, ranges, status_dev, static_cast<hipStream_t>(stream));
 }
 
+gsb_status gsb_bin_noalloc(const float *means2d, const int32_t *radii, const float *conics,
+                           const float *opacity, gsb_bin_mode mode, const float *depths,
+                           int64_t n, int32_t W, int32_t H, uint32_t *point_list,
+                           int64_t pair_capacity, uint32_t *ranges, int64_t *n_pairs_dev,
+                           int32_t *status_dev, void *stream) {
+    size_t need = 0;
+    GSB_TRY(gsb_bin_workspace_bytes(n, pair_capacity, W, H, &need));
+    GSB_REQUIRE(need <= GSB_NOALLOC_SCRATCH_BYTES,
+                "binning %lld Gaussians into at most %lld pairs needs a %zu-byte workspace, more "
+                "than the %zu bytes the library holds", (long long)n, (long long)pair_capacity,
+                need, size_t(GSB_NOALLOC_SCRATCH_BYTES));
+    GSB_REQUIRE(n == 0 || (means2d && radii && depths), "means2d, radii and depths must be non-null");
+    GSB_REQUIRE(aligned(means2d, 8), "means2d must be 8-byte aligned");
+    GSB_TRY(check_bin_mode(mode, n, conics, opacity));
+    GSB_REQUIRE(pair_capacity == 0 || point_list != nullptr, "point_list must be non-null");
+    GSB_REQUIRE(ranges != nullptr && status_dev != nullptr, "ranges and status_dev must be non-null");
+    GSB_REQUIRE(n_pairs_dev != nullptr && aligned(n_pairs_dev, 8),
+                "n_pairs_dev must be a non-null, 8-byte aligned device pointer");
+    GSB_TRY(check_device());
+    return bin_noalloc(means2d, radii, conics, opacity, mode, depths, n, W, H, point_list,
+                       pair_capacity, ranges, n_pairs_dev, status_dev,
+                       static_cast<hipStream_t>(stream));
+}
+
 gsb_status gsb_blend_forward(int32_t W, int32_t H, const uint32_t *ranges,
                              const uint32_t *point_list, const float *means2d,
                              const float *conics, const float *opacity, const float *colors,

@@ -58,6 +58,10 @@ __device__ inline Rect tile_rect(float x, float y, int32_t r, int32_t gx, int32_
 
 // ---- binning (bin.hip)
 size_t bin_workspace_bytes(int64_t n, int64_t pair_capacity, int64_t n_tiles);
+gsb_status bin_noalloc(const float *means2d, const int32_t *radii, const float *conics,
+                       const float *opacity, int32_t mode, const float *depths, int64_t n,
+                       int32_t W, int32_t H, uint32_t *point_list, int64_t cap, uint32_t *ranges,
+                       int64_t *n_pairs_dev, int32_t *status_dev, hipStream_t s);
 gsb_status bin_count(const float *means2d, const int32_t *radii, const float *conics,
                      const float *opacity, int32_t mode, int64_t n, int32_t W, int32_t H, void *ws,
                      int64_t *n_pairs_dev, hipStream_t s);
