@@ -43,7 +43,7 @@ import numpy as np  # noqa: E402
 import torch  # noqa: E402
 
 import gsinputs  # noqa: E402
-from paper_2604_02120_amd import api  # noqa: E402
+from paper_2604_02120_amd import api, autotune  # noqa: E402
 
 METRIC = "Mpix/s fwd+bwd blend, GEMM-form vs plain FP32 on 1 MI355X at ≥50 dB vs oracle"
 # Published FP32 vector peak of the MI355X (packed FP32: 256 CUs x 4 SIMDs x 16 lanes x 2 (FMA)
@@ -87,6 +87,13 @@ def parse():
     p.add_argument("--sweep", action="store_true",
                    help="instead of the benchmark line: sensitivity sweeps of the LDS batch size "
                         "and of the resolution (1x, 2x, 3x), GEMM form vs plain FP32")
+    p.add_argument("--reduce-study", action="store_true",
+                   help="instead of the benchmark line: backward time with the per-Gaussian sums "
+                        "reduced on the vector ALUs vs on the matrix cores, on the 1080p, 4K and "
+                        "a dense-footprint scene")
+    p.add_argument("--peaks", action="store_true",
+                   help="instead of the benchmark line: attainable FP32 FMA, exp2 and FP16 MFMA "
+                        "rates of this GPU from a microbenchmark, beside the published peaks")
     p.add_argument("--calib-copy-mib", type=int, default=0,
                    help="also run one device-to-device copy of this many MiB (a known-size "
                         "kernel for scaling HBM byte counters)")
@@ -208,7 +215,8 @@ def time_batched(steps: int, warmup: int, dev) -> dict:
         torch.cuda.synchronize()
         return 1e3 * (time.perf_counter() - t0) / steps, a.elapsed_time(b) / steps
 
-    eager_wall, eager_ev = timed(bv.step)
+    eager_wall, eager_ev = timed(lambda: bv.step(check=False))
+    bv.check()
     side = torch.cuda.Stream()
     side.wait_stream(torch.cuda.current_stream())
     with torch.cuda.stream(side):
@@ -239,7 +247,7 @@ def time_batched(steps: int, warmup: int, dev) -> dict:
         bv.backward()
     fb_wall, fb_ev = timed(fwd_bwd)
     del graph
-    tune = {k: bv.tuning[k] for k in ("batch_fwd", "batch_bwd", "blocks_per_cu", "launch")}
+    tune = {k: bv.tuning.get(k) for k in autotune.KEYS}
     trials = bv.tuning.get("trials")
     out = {"workload": "16 views from {854x480, 1280x720, 1920x1080} (seed 4), 300k Gaussians "
                        "each (seeds 400+v); step = bin all views + batched fwd + batched bwd",
@@ -403,6 +411,83 @@ def run_sweeps(dev, steps: int, warmup: int) -> dict:
     return out
 
 
+# Large, overlapping footprints: most of a 16-Gaussian group is live in most wavefronts.
+DENSE = gsinputs.SceneConfig("dense", 1920, 1080, 200_000, "loguniform", 4.0, 32.0, "uniform", 48)
+
+
+def reduce_study(dev, steps: int, warmup: int) -> list:
+    """Backward blend time with the per-Gaussian gradient sums reduced on the vector ALUs
+    (bwd_reduce 0) and with the geometric sums as a matrix-core product (bwd_reduce 1), through
+    one-view plans launched one block per tile, for each precision, on three scenes."""
+    rows = []
+    for name, cfg in (("C2", gsinputs.CONFIGS["C2"]), ("C5", gsinputs.CONFIGS["C5"]),
+                      ("dense", DENSE)):
+        sc = gsinputs.make_scene(cfg)
+        d = {"width": sc["width"], "height": sc["height"]}
+        for k in ("means2d", "conics", "opacity", "colors", "depths", "radii"):
+            d[k] = torch.from_numpy(np.ascontiguousarray(sc[k])).to(dev)
+        g = torch.from_numpy(gsinputs.make_dloss(sc["width"], sc["height"], 1002)).to(dev)
+        for prec in ("bf16", "fp16", "fp32"):
+            row = {"scene": name, "width": sc["width"], "height": sc["height"],
+                   "gaussians": len(sc["radii"]), "precision": prec}
+            for red, nb in ((0, 128), (1, 128), (1, 64)):
+                bv = api.BatchedViews([d], prec=prec, tuning={"launch": 1, "batch_bwd": nb,
+                                                               "bwd_reduce": red})
+                bv.views[0]["dL_dimage"].copy_(g)
+                bv.bin()
+                bv.forward()
+                for _ in range(warmup):
+                    bv.backward()
+                torch.cuda.synchronize()
+                ms = []
+                for _ in range(steps):
+                    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                    a.record()
+                    bv.backward()
+                    b.record()
+                    b.synchronize()
+                    ms.append(a.elapsed_time(b))
+                row[f"bwd_ms_{'mfma' if red else 'valu'}_b{nb}"] = round(float(np.median(ms)), 4)
+                row["pairs"] = bv.views[0]["pairs"]
+                bv.close()
+            rows.append(row)
+        del d
+        torch.cuda.empty_cache()
+    return rows
+
+
+def measure_peaks() -> dict:
+    """Attainable issue rates from the microbenchmark library (libgsbpeaks.so): independent chains
+    of FP32 FMA (not packed), of exp2 each followed by a multiply, and of
+    v_mfma_f32_32x32x16_f16, over 8 blocks of 256 threads per compute unit."""
+    import ctypes
+    lib = ctypes.CDLL(os.path.join(ROOT, "paper_2604_02120_amd", "libgsbpeaks.so"))
+    lib.gsbpk_run.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int,
+                              ctypes.POINTER(ctypes.c_float), ctypes.POINTER(ctypes.c_double)]
+    cus = torch.cuda.get_device_properties(0).multi_processor_count
+    out = {"compute_units": cus, "blocks": 8 * cus}
+    simd_cycles = 4 * cus * 2.4e9          # SIMD-cycles per second at 2.4 GHz
+    for which, name, iters in ((0, "fma_f32", 1 << 16), (1, "exp2_f32_plus_mul", 1 << 14),
+                               (2, "mfma_f32_32x32x16_f16", 1 << 14)):
+        ms, ops = ctypes.c_float(0.0), ctypes.c_double(0.0)
+        if lib.gsbpk_run(which, 8 * cus, iters, ctypes.byref(ms), ctypes.byref(ops)) != 0:
+            raise RuntimeError(f"microbenchmark {name} failed")
+        rate = ops.value / (ms.value * 1e-3)
+        r = {"ms": round(ms.value, 4), "ops": ops.value}
+        if which == 0:
+            r["tflops"] = round(2 * rate / 1e12, 2)
+            r["published_tflops_packed"] = PEAK_FP32_TFLOPS
+            r["wave64_instr_per_simd_cycle"] = round(rate / 64 / simd_cycles, 4)
+        elif which == 1:
+            r["exp2_per_s"] = rate
+            r["wave64_exp2_per_simd_cycle"] = round(rate / 64 / simd_cycles, 4)
+        else:
+            r["tflops"] = round(rate * 32 * 32 * 16 * 2 / 1e12, 1)
+            r["published_tflops_dense_fp16"] = 2500.0
+        out[name] = r
+    return out
+
+
 def kernel_hash(src: str = None) -> str:
     return hashlib.sha256(open(src or KERNEL_SRC, "rb").read()).hexdigest()[:16]
 
@@ -560,6 +645,13 @@ def main():
     dev = torch.device("cuda:0")
     if args.sweep:
         print(json.dumps({"sweep": run_sweeps(dev, max(5, args.steps // 2), 2)}), flush=True)
+        return
+    if args.peaks:
+        print(json.dumps({"peaks": measure_peaks()}), flush=True)
+        return
+    if args.reduce_study:
+        print(json.dumps({"reduce_study": reduce_study(dev, max(5, args.steps // 2), 3)}),
+              flush=True)
         return
     if args.calib_copy_mib:
         n = args.calib_copy_mib * (1 << 20) // 4

@@ -52,7 +52,7 @@ typedef int32_t gsb_precision;
 #define GSB_FP16_GEMM 1   /* exponent as an MFMA product, FP16 hi+lo operands, FP32 accumulate */
 #define GSB_BF16_GEMM 2   /* same with BF16 hi+lo operands */
 
-#define GSB_ABI_VERSION 4
+#define GSB_ABI_VERSION 5
 
 /* Version of this interface (GSB_ABI_VERSION of the library that was loaded). */
 int32_t gsb_abi_version(void);
@@ -267,11 +267,20 @@ typedef struct gsb_view {
 /* Launch shape. Zero fields take the defaults. */
 #define GSB_LAUNCH_PERSISTENT 0   /* resident blocks pull items from the per-XCD queues */
 #define GSB_LAUNCH_GRID 1         /* one block per item: block b takes item b/8 of queue b%8 */
+/* How the backward sums each Gaussian's per-pixel gradient terms over a wavefront's 64 pixels:
+ * GSB_REDUCE_VALU: all nine sums by cross-lane adds on the vector ALUs (default);
+ * GSB_REDUCE_MFMA: the five geometric sums (of dL/dpower times dx^2, dx dy, dy^2, dx, dy) as a
+ *   matrix product of dL/dpower (8 Gaussians x 64 pixels, FP16 hi + lo) with the pixel basis
+ *   [1, xb, yb, xb^2, xb yb, yb^2] on the matrix cores, i.e. Eq. (power rewritten) applied in
+ *   reverse: dL/dM_g = dL/dM_power . M_p^T; the other four sums stay on the vector ALUs. */
+#define GSB_REDUCE_VALU 0
+#define GSB_REDUCE_MFMA 1
 typedef struct gsb_tuning {
     int32_t batch_fwd;       /* Gaussians staged in LDS per batch, forward: 64, 128, 256 (128) */
     int32_t batch_bwd;       /* same, backward (128) */
     int32_t blocks_per_cu;   /* persistent: resident blocks per compute unit; 0 = as many as fit */
     int32_t launch;          /* GSB_LAUNCH_PERSISTENT (default) or GSB_LAUNCH_GRID */
+    int32_t bwd_reduce;      /* GSB_REDUCE_VALU (default) or GSB_REDUCE_MFMA */
 } gsb_tuning;
 
 typedef struct gsb_plan_s *gsb_plan;

@@ -29,6 +29,8 @@ GSB_BF16_GEMM = 2
 PRECISIONS = {"fp32": GSB_FP32_PLAIN, "fp16": GSB_FP16_GEMM, "bf16": GSB_BF16_GEMM}
 GSB_LAUNCH_PERSISTENT = 0
 GSB_LAUNCH_GRID = 1
+GSB_REDUCE_VALU = 0
+GSB_REDUCE_MFMA = 1
 
 # every function declared in include/gsblend.h
 EXPORTS = ("gsb_abi_version", "gsb_last_error", "gsb_project", "gsb_bin_workspace_bytes",
@@ -59,7 +61,8 @@ class GsbView(ctypes.Structure):
 class GsbTuning(ctypes.Structure):
     """struct gsb_tuning (zero fields take the library defaults)."""
     _fields_ = [("batch_fwd", ctypes.c_int32), ("batch_bwd", ctypes.c_int32),
-                ("blocks_per_cu", ctypes.c_int32), ("launch", ctypes.c_int32)]
+                ("blocks_per_cu", ctypes.c_int32), ("launch", ctypes.c_int32),
+                ("bwd_reduce", ctypes.c_int32)]
 
 
 class GsbError(RuntimeError):

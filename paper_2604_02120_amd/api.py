@@ -212,13 +212,15 @@ class BatchedViews:
     depths, radii) plus ``width``/``height``. Each view's binning buffers are sized once, eagerly,
     from its exact pair count (times ``capacity_slack``), so that ``bin()``, ``forward()`` and
     ``backward()`` afterwards enqueue kernels only: the whole step can be captured in a hipGraph.
-    ``tuning``: None (library defaults), a dict (batch_fwd, batch_bwd, blocks_per_cu, launch) or
-    "auto" (``autotune.tune``). ``dL_dimage[v]`` is allocated here (zeros) for the caller to fill.
+    ``tuning``: None (library defaults), a dict (batch_fwd, batch_bwd, blocks_per_cu, launch,
+    bwd_reduce) or "auto" (``autotune.tune``). ``dL_dimage[v]`` is allocated here (zeros) for the caller to fill.
     """
 
     def __init__(self, scenes, prec="fp16", tuning=None, bg=(0.0, 0.0, 0.0),
-                 capacity_slack: float = 1.0, stream=None, bin_mode="rect"):
+                 capacity_slack: float = 1.0, stream=None, bin_mode="rect", bin_streams: int = 4):
         self.prec = prec_code(prec)
+        self.bin_streams = max(1, int(bin_streams))
+        self._side = None
         self.bin_mode = bin_mode
         self.bg = tuple(float(v) for v in bg)
         self.views = []
@@ -274,21 +276,55 @@ class BatchedViews:
         t = None
         if tuning:
             t = _lib.GsbTuning(int(tuning.get("batch_fwd", 0)), int(tuning.get("batch_bwd", 0)),
-                               int(tuning.get("blocks_per_cu", 0)), int(tuning.get("launch", 0)))
+                               int(tuning.get("blocks_per_cu", 0)), int(tuning.get("launch", 0)),
+                               int(tuning.get("bwd_reduce", 0)))
         self.plan = _lib.gsb_plan_create(self._gsb_views(), self.prec, t)
 
+    def _bin_view(self, v, s: int):
+        W, H = v["width"], v["height"]
+        ws = v["ws"]
+        code, cp, op = _bin_mode(self.bin_mode, v["conics"], v["opacity"])
+        _lib.gsb_bin_count(v["means2d"].data_ptr(), v["radii"].data_ptr(), v["n"], W, H,
+                           ws.ptr(), ws.nbytes, v["n_pairs"].data_ptr(), s, cp, op, code)
+        _lib.gsb_bin_fill(v["means2d"].data_ptr(), v["radii"].data_ptr(),
+                          v["depths"].data_ptr(), v["n"], W, H, ws.ptr(), ws.nbytes,
+                          v["point_list"].data_ptr(), v["point_list"].numel(),
+                          v["ranges"].data_ptr(), v["status"].data_ptr(), s, cp, op, code)
+
     def bin(self, stream=None):
-        s = _stream(stream)
-        for v in self.views:
-            W, H = v["width"], v["height"]
-            ws = v["ws"]
-            code, cp, op = _bin_mode(self.bin_mode, v["conics"], v["opacity"])
-            _lib.gsb_bin_count(v["means2d"].data_ptr(), v["radii"].data_ptr(), v["n"], W, H,
-                               ws.ptr(), ws.nbytes, v["n_pairs"].data_ptr(), s, cp, op, code)
-            _lib.gsb_bin_fill(v["means2d"].data_ptr(), v["radii"].data_ptr(),
-                              v["depths"].data_ptr(), v["n"], W, H, ws.ptr(), ws.nbytes,
-                              v["point_list"].data_ptr(), v["point_list"].numel(),
-                              v["ranges"].data_ptr(), v["status"].data_ptr(), s, cp, op, code)
+        """Bins every view. One view's binning is a chain of small dependent kernels that leaves
+        most of the GPU idle, so the views are spread over ``bin_streams`` side streams forked
+        from the calling stream and joined back into it (event waits, which a hipGraph capture
+        records as parallel branches)."""
+        cur = torch.cuda.current_stream() if stream is None else stream
+        k = min(self.bin_streams, len(self.views))
+        if k <= 1:
+            for v in self.views:
+                self._bin_view(v, cur.cuda_stream)
+            return
+        if self._side is None:
+            self._side = [torch.cuda.Stream(device=self.views[0]["means2d"].device)
+                          for _ in range(self.bin_streams)]
+        side = self._side[:k]
+        for st in side:
+            st.wait_stream(cur)
+        # heaviest views first, dealt round-robin
+        order = sorted(range(len(self.views)), key=lambda i: -self.views[i]["pairs"])
+        for j, i in enumerate(order):
+            self._bin_view(self.views[i], side[j % k].cuda_stream)
+        for st in side:
+            cur.wait_stream(st)
+
+    def check(self):
+        """Raises if the last binning of any view overflowed its pair capacity (or failed a
+        device-side check). Synchronises on the status words; not for use under capture: a
+        captured step replays with the capacities sized at construction."""
+        for i, v in enumerate(self.views):
+            st = int(v["status"].item())
+            if st != _lib.GSB_OK:
+                raise _lib.GsbError(st, f"view {i}: binning status {st} (pairs "
+                                        f"{int(v['n_pairs'].item())}, capacity "
+                                        f"{v['point_list'].numel()})")
 
     def forward(self, stream=None):
         _lib.gsb_blend_batched_forward(self.plan, _stream(stream))
@@ -296,10 +332,14 @@ class BatchedViews:
     def backward(self, stream=None):
         _lib.gsb_blend_batched_backward(self.plan, _stream(stream))
 
-    def step(self, stream=None):
+    def step(self, stream=None, check: bool = True):
+        """bin + forward + backward of every view. With ``check`` (and outside a hipGraph
+        capture) the binning status words are read afterwards and an overflow raises."""
         self.bin(stream)
         self.forward(stream)
         self.backward(stream)
+        if check and not torch.cuda.is_current_stream_capturing():
+            self.check()
 
     def pixels(self) -> int:
         return sum(v["width"] * v["height"] for v in self.views)

@@ -1,9 +1,10 @@
 """Autotuner for the launch shape of batched (multi-view) blends.
 
-For a ``api.BatchedViews`` it times the forward + backward persistent launches for every
-candidate shape (LDS batch size of each direction, resident blocks per compute unit) and keeps
-the fastest. Results are cached in a JSON file keyed by (GPU arch, precision, the views' sizes
-with Gaussian counts rounded to powers of two), so a shape is measured once per workload family.
+For a ``api.BatchedViews`` it times the forward + backward launches for every candidate shape
+(LDS batch size of each direction, resident blocks per compute unit, persistent or one block per
+item, the backward's reduction on the vector ALUs or the matrix cores) and keeps the fastest.
+Results are cached in a JSON file keyed by (GPU arch, precision, the views' sizes with Gaussian
+counts rounded to powers of two), so a shape is measured once per workload family.
 
 The cache file is ``$GSBLEND_TUNING_CACHE`` if set, else ``~/.cache/gsblend/tuning.json``.
 """
@@ -18,11 +19,17 @@ import torch
 BATCHES_FWD = (128, 256)
 BATCHES_BWD = (64, 128, 256)
 BLOCKS_PER_CU = (0, 2)          # persistent launches: 0 = as many as fit
-# launch 0: persistent blocks pulling from the per-XCD queues; 1: one block per item
-CANDIDATES = ([dict(batch_fwd=f, batch_bwd=b, blocks_per_cu=c, launch=0)
+# launch 0: persistent blocks pulling from the per-XCD queues; 1: one block per item.
+# bwd_reduce 0: the backward's nine per-Gaussian sums by cross-lane adds; 1: its five geometric
+# sums as a product with the pixel basis on the matrix cores (tried with one-block-per-item
+# launches and LDS batches of 64 and 128, the shapes whose LDS keeps 4-5 blocks per CU).
+CANDIDATES = ([dict(batch_fwd=f, batch_bwd=b, blocks_per_cu=c, launch=0, bwd_reduce=0)
                for f in BATCHES_FWD for b in BATCHES_BWD for c in BLOCKS_PER_CU] +
-              [dict(batch_fwd=f, batch_bwd=b, blocks_per_cu=0, launch=1)
-               for f in BATCHES_FWD for b in BATCHES_BWD])
+              [dict(batch_fwd=f, batch_bwd=b, blocks_per_cu=0, launch=1, bwd_reduce=0)
+               for f in BATCHES_FWD for b in BATCHES_BWD] +
+              [dict(batch_fwd=f, batch_bwd=b, blocks_per_cu=0, launch=1, bwd_reduce=1)
+               for f in BATCHES_FWD for b in (64, 128)])
+KEYS = ("batch_fwd", "batch_bwd", "blocks_per_cu", "launch", "bwd_reduce")
 
 
 def cache_path() -> str:

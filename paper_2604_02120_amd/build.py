@@ -17,6 +17,9 @@ CSRC = os.path.join(PKG, "csrc")
 BUILD = os.path.join(PKG, "_build")
 LIB = os.path.join(PKG, "libgsblend.so")
 SOURCES = ["capi.hip", "bin.hip", "blend.hip", "project.hip"]
+# the attainable-rate microbenchmark (bench.py --peaks): a library of its own, not part of the ABI
+PEAKS_LIB = os.path.join(PKG, "libgsbpeaks.so")
+PEAKS_SRC = "peaks.hip"
 # per-file extras: the blend kernels never produce NaN from in-contract inputs (-inf is used, NaN
 # never), so min/max need no NaN canonicalisation
 EXTRA = {"blend.hip": ["-fno-honor-nans"]}
@@ -43,18 +46,23 @@ def _compile(src: str) -> str:
     return obj
 
 
-def build(verbose: bool = False) -> str:
-    os.makedirs(BUILD, exist_ok=True)
-    with cf.ThreadPoolExecutor(max_workers=min(len(SOURCES), 8)) as ex:
-        objs = list(ex.map(_compile, SOURCES))
-    tmp = LIB + f".tmp{os.getpid()}"
+def _link(objs, lib: str) -> None:
+    tmp = lib + f".tmp{os.getpid()}"
     cmd = [HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", *objs, "-o", tmp]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"link failed:\n{r.stderr}")
-    os.replace(tmp, LIB)
+    os.replace(tmp, lib)
+
+
+def build(verbose: bool = False) -> str:
+    os.makedirs(BUILD, exist_ok=True)
+    with cf.ThreadPoolExecutor(max_workers=min(len(SOURCES) + 1, 8)) as ex:
+        objs = list(ex.map(_compile, SOURCES + [PEAKS_SRC]))
+    _link(objs[:-1], LIB)
+    _link(objs[-1:], PEAKS_LIB)
     if verbose:
-        print(f"built {LIB}")
+        print(f"built {LIB} and {PEAKS_LIB}")
     return LIB
 
 

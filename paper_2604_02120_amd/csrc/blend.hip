@@ -43,6 +43,7 @@
 #include <math.h>
 
 #include <algorithm>
+#include <type_traits>
 #include <vector>
 
 #include "gsb_internal.h"
@@ -63,6 +64,7 @@ constexpr float kLoScaleInv = 1.0f / 4096.0f;
 constexpr float kF16Max = 65504.0f;
 
 typedef _Float16 h8 __attribute__((ext_vector_type(8)));
+typedef float f4x __attribute__((ext_vector_type(4)));
 typedef __bf16 b8 __attribute__((ext_vector_type(8)));
 typedef float f16x __attribute__((ext_vector_type(16)));
 
@@ -134,6 +136,16 @@ struct BwdAcc {
     uint32_t hit[2][NB];
     uint16_t list[kBlock / 64][64];
     __device__ float *slot(int ab, int t) { return v[ab] + t * kGrad; }
+};
+
+// Backward reduction on the matrix cores: each wavefront's dL/dpower values of 8 Gaussians for its
+// 64 pixels (one word per (Gaussian, pixel): FP16 hi in the low half, FP16 lo x 2^12 in the high
+// half), transposed through LDS into the operand of v_mfma_f32_16x16x32_f16. Rows padded to 68
+// words. Row 0 doubles as the 8 x 8 table of the product's results (moments) once the operand has
+// been read. The rows are zero whenever a half-group starts.
+constexpr int kDgStride = 68;
+struct alignas(16) BwdMM {
+    uint32_t dg[kBlock / 64][8][kDgStride];
 };
 
 // Raw attributes of one list entry, fetched in the prefetch step.
@@ -542,10 +554,164 @@ __device__ inline void reverse_pair(float q, bool in_range, const float4 *ga, co
     }
 }
 
+// Sum of 4 values over the wavefront (wave_sum9's first stages on two value pairs): lanes 16r ..
+// 16r + 15 of the result hold s[{0,2,1,3}[r]]. Every lane must be active.
+__device__ inline float wave_sum4(const float (&s)[4]) {
+    float x0 = s[0], x2 = s[2];
+    const float p01 = swap_add32(x0, s[1]), p23 = swap_add32(x2, s[3]);
+    float a = swap_add16(p01, p23);
+    a = dpp_add2<kDppRowRor8>(a, a);
+    a = dpp_add2<kDppRowHalfMirror>(a, a);
+    a = dpp_add2<kDppQuadRev>(a, a);
+    a = dpp_add2<kDppQuadSwap>(a, a);
+    return a;
+}
+
+// Reverse step of reverse_pair for the matrix-core reduction: the same state update, but of the
+// pair's gradient terms only the four plain sums (dL/do and the colours) are reduced on the vector
+// ALUs here; dL/dpower (with no gradient through a clamped power) goes into the wavefront's
+// transposition row `dgrow`, from which the five geometric sums are formed as a product with the
+// pixel basis (mm_reduce). Returns whether any lane of the wavefront had a live pair.
+template <bool kRanged>
+__device__ inline bool reverse_pair_mm(float q, bool in_range, const float4 *ga, const float4 *gb,
+                                       int u, const Lane &L, BwdState &st, float *acc,
+                                       uint32_t *hit, uint32_t *dgrow) {
+    const bool alive = kRanged ? (in_range && q >= kQCull) : (q >= kQCull);
+    unsigned long long live;
+    if constexpr (kRanged) {
+        unsigned long long m_range = __builtin_amdgcn_ballot_w64(in_range);
+        unsigned long long m_cull = __builtin_amdgcn_ballot_w64(q >= kQCull);
+        asm volatile("" : "+s"(m_range));
+        asm volatile("" : "+s"(m_cull));
+        live = m_range & m_cull;
+    } else {
+        live = __builtin_amdgcn_ballot_w64(alive);
+    }
+    if (live == 0ull) return false;
+    const float4 attr = ga[u];
+    const float4 bw = gb[u];
+    const float araw = __builtin_amdgcn_exp2f(fminf(q, attr.x));
+    const float a = alive ? fminf(araw, kAlphaMax) : 0.f;
+    const float r = __builtin_amdgcn_rcpf(1.0f - a);
+    const float Tb = st.T * r;
+    const float gc = st.gr * attr.y + st.gg * attr.z + st.gb * attr.w;
+    const float dLda = Tb * gc - st.behind * r;
+    const float wc = a * Tb;
+    st.behind = fmaf(wc, gc, st.behind);
+    st.T = Tb;
+    const float da = araw < kAlphaMax ? a * dLda : 0.f;
+    const float dg = q > attr.x ? 0.f : da;
+    // dg = hi + lo 2^-12 with FP16 hi and lo (truncations; the residual dg - hi is exact in FP32)
+    const auto hp = __builtin_amdgcn_cvt_pkrtz(dg, 0.f);
+    const float lo = (dg - float(hp[0])) * kLoScale;
+    const auto pk = __builtin_amdgcn_cvt_pkrtz(dg, lo);
+    dgrow[L.l] = __builtin_bit_cast(uint32_t, pk);
+    const float s[4] = {da * bw.z, wc * st.gr, wc * st.gg, wc * st.gb};
+    const float tot = wave_sum4(s);
+    if ((L.l & 15) == 0) {
+        atomicAdd(acc + 5 + ((L.l >> 4) == 1 ? 2 : (L.l >> 4) == 2 ? 1 : (L.l >> 4)), tot);
+        if (L.l == 0) *hit = 1u;
+    }
+    return true;
+}
+
+// The pixel basis of the matrix-core reduction as the B operand of v_mfma_f32_16x16x32_f16, for
+// the two 32-pixel halves c of the wavefront's quadrant: lane l supplies basis function l % 16
+// (1, xb, yb, xb^2, xb yb, yb^2, then zeros) at the 8 pixels 32c + 8(l / 16) + j, j = 0..7, which
+// lie in one row of the quadrant. xb = x_c - px and yb = y_c - py are quarter-integers of at most
+// 7.5 in magnitude, so every value is exact in FP16.
+__device__ inline void mm_basis(const Lane &L, h8 (&B)[2]) {
+    const int n = L.l & 15;
+#pragma unroll
+    for (int c = 0; c < 2; ++c) {
+        const float yb = 7.5f - float(8 * (L.w >> 1) + 4 * c + (L.l >> 4));
+        float v[8];
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+            const float xb = 7.5f - float(8 * (L.w & 1) + j);
+            v[j] = n == 0 ? 1.f : n == 1 ? xb : n == 2 ? yb : n == 3 ? xb * xb
+                 : n == 4 ? xb * yb : n == 5 ? yb * yb : 0.f;
+        }
+#pragma unroll
+        for (int j = 0; j < 8; ++j) B[c][j] = _Float16(v[j]);
+    }
+}
+
+// The five geometric sums of the 8 Gaussians of one half-group (staged slots base .. base + 7)
+// from the wavefront's transposition rows: two v_mfma_f32_16x16x32_f16 give, per Gaussian, the
+// moments sum_p dg [1, xb, yb, xb^2, xb yb, yb^2] over the 64 pixels (rows 0-7 from the hi terms,
+// rows 8-15 from the lo terms, combined in FP32); with dx = xh + xb (xh = x - x_c) the sums
+// of dg [dx^2, dx dy, dy^2, dx, dy] follow per Gaussian, and are added into the batch's
+// accumulator. `hmask` has bit i set when Gaussian base + i had a live pair in this wavefront;
+// the rows are left zero.
+__device__ inline void mm_reduce(uint32_t (*rows)[kDgStride], const h8 (&B)[2], unsigned hmask,
+                                 const float4 *gb, float xc, float yc, float *acc, const Lane &L) {
+    __builtin_amdgcn_wave_barrier();
+    const int row = L.l & 15, q = L.l >> 4;
+    // hi rows take the low halves of the packed words, lo rows the high halves
+    const uint32_t sel = row < 8 ? 0x05040100u : 0x07060302u;
+    f4x d = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int c = 0; c < 2; ++c) {
+        const uint4 *src = reinterpret_cast<const uint4 *>(&rows[row & 7][32 * c + 8 * q]);
+        const uint4 w0 = src[0], w1 = src[1];
+        uint32_t av[4];
+        av[0] = __builtin_amdgcn_perm(w0.y, w0.x, sel);
+        av[1] = __builtin_amdgcn_perm(w0.w, w0.z, sel);
+        av[2] = __builtin_amdgcn_perm(w1.y, w1.x, sel);
+        av[3] = __builtin_amdgcn_perm(w1.w, w1.z, sel);
+        h8 A;
+        __builtin_memcpy(&A, av, sizeof(A));
+        d = __builtin_amdgcn_mfma_f32_16x16x32_f16(A, B[c], d, 0, 0, 0);
+    }
+    // lane l < 32 holds rows 4q + v (hi) of column l % 16; lane l + 32 the lo rows of the same
+    // Gaussians: moment = hi + 2^-12 lo
+    float m[4];
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+        const auto r = __builtin_amdgcn_permlane32_swap(__float_as_uint(d[v]), __float_as_uint(d[v]),
+                                                        false, false);
+        m[v] = fmaf(__uint_as_float(r[1]), kLoScaleInv, __uint_as_float(r[0]));
+    }
+    // moments table mom[g][n] in row 0 (the operand reads above have completed: the MFMA used them)
+    float *mom = reinterpret_cast<float *>(rows[0]);
+    if (L.l < 32 && row < 6) {
+#pragma unroll
+        for (int v = 0; v < 4; ++v) mom[(4 * q + v) * 8 + row] = m[v];
+    }
+    __builtin_amdgcn_wave_barrier();
+    // lane g * 5 + k forms sum k of Gaussian g
+    if (L.l < 40) {
+        const int g = L.l / 5, k = L.l - 5 * g;
+        if ((hmask >> g) & 1u) {
+            const float4 m0 = *reinterpret_cast<const float4 *>(mom + 8 * g);
+            const float2 m1 = *reinterpret_cast<const float2 *>(mom + 8 * g + 4);
+            const float S1 = m0.x, Sx = m0.y, Sy = m0.z, Sxx = m0.w, Sxy = m1.x, Syy = m1.y;
+            const float4 bw = gb[g];
+            const float xh = bw.x - xc, yh = bw.y - yc;
+            const float sx = fmaf(xh, S1, Sx), sy = fmaf(yh, S1, Sy);
+            float val;
+            if (k == 0) val = fmaf(xh, sx, fmaf(xh, Sx, Sxx));            // sum dg dx^2
+            else if (k == 1) val = fmaf(xh, sy, fmaf(yh, Sx, Sxy));       // sum dg dx dy
+            else if (k == 2) val = fmaf(yh, sy, fmaf(yh, Sy, Syy));       // sum dg dy^2
+            else if (k == 3) val = sx;
+            else val = sy;
+            atomicAdd(acc + g * kGrad + k, val);
+        }
+    }
+    __builtin_amdgcn_wave_barrier();
+    // leave the rows zero for the next half-group
+    uint4 *z = reinterpret_cast<uint4 *>(&rows[L.l >> 3][(L.l & 7) * 8]);
+    z[0] = make_uint4(0u, 0u, 0u, 0u);
+    z[1] = make_uint4(0u, 0u, 0u, 0u);
+}
+
 // Backward of one tile of one view.
-template <Mode M, int NB>
+// kMM: the five geometric sums are formed on the matrix cores (mm_reduce) instead of being
+// reduced on the vector ALUs with the other four; `mm` is then the block's transposition tiles.
+template <Mode M, int NB, bool kMM>
 __device__ inline void bwd_tile(const ViewDesc &v, int64_t tile, Stage<M, NB> &S, StageBwd<NB> &SB,
-                                BwdAcc<NB> &s_acc, int &s_maxlast) {
+                                BwdAcc<NB> &s_acc, int &s_maxlast, BwdMM *mm) {
     static_assert(NB % kGroup == 0 && NB <= kBlock, "batch must be whole groups, <= block");
     constexpr int kGroups = NB / kGroup;
     const uint32_t *plist = v.point_list;
@@ -563,6 +729,15 @@ __device__ inline void bwd_tile(const ViewDesc &v, int64_t tile, Stage<M, NB> &S
         float z[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
         if constexpr (M != Mode::Plain) S.zero = Op<M>::cvt(z);
         s_maxlast = 0;
+    }
+    h8 mmB[2];
+    uint32_t (*rows)[kDgStride] = nullptr;
+    if constexpr (kMM) {
+        mm_basis(L, mmB);
+        rows = mm->dg[L.w];
+        uint4 *z = reinterpret_cast<uint4 *>(&rows[L.l >> 3][(L.l & 7) * 8]);
+        z[0] = make_uint4(0u, 0u, 0u, 0u);
+        z[1] = make_uint4(0u, 0u, 0u, 0u);
     }
     if (n == 0) return;            // no Gaussian, no gradient (uniform: every thread returns)
     BwdState st{1.f, 0.f, 0.f, 0.f, 0.f, 0};
@@ -664,37 +839,53 @@ __device__ inline void bwd_tile(const ViewDesc &v, int64_t tile, Stage<M, NB> &S
             if (__ballot(st.last > base + g * kGroup) == 0) continue;
             const float4 *ga = &S.attr[buf][g * kGroup];   // the group's staged values
             const float4 *gb = &SB.bwd[buf][g * kGroup];
-            float *acc = s_acc.slot(buf, g * kGroup) + word;   // this lane's word, Gaussian 0
+            float *accw = s_acc.slot(buf, g * kGroup);          // the group's sums, Gaussian 0
+            float *acc = accw + (kMM ? 0 : word);   // this lane's word (VALU reduction)
             uint32_t *hit = &s_acc.hit[buf][g * kGroup];
             const int rel = st.last - (base + g * kGroup);   // positions < last are in range
             // the whole group is in range for every lane (the common case once past the lanes'
             // last contributors; never for a partial tile, whose outside lanes have last = 0)
             const bool whole = __builtin_amdgcn_ballot_w64(rel < kGroup) == 0ull;
-            if constexpr (M == Mode::Plain) {
-                if (whole) {
+            f16x qm;
+            if constexpr (M != Mode::Plain) qm = group_q_mfma<M, NB>(S, buf, g, L, bhi, blo);
+            const auto q_of = [&](int u) {
+                if constexpr (M == Mode::Plain) return plain_q(S, buf, g * kGroup + u, L);
+                else return qm[u];
+            };
+            if constexpr (kMM) {
+                // two half-groups of 8: Gaussians 15..8, then 7..0, each followed by its product
 #pragma unroll
-                    for (int u = kGroup - 1; u >= 0; --u)
-                        reverse_pair<false>(plain_q(S, buf, g * kGroup + u, L), true, ga, gb, u,
-                                            L, st, acc + u * kGrad, hit + u);
-                } else {
+                for (int h = 1; h >= 0; --h) {
+                    unsigned hmask = 0u;
+                    if (whole) {
 #pragma unroll
-                    for (int u = kGroup - 1; u >= 0; --u)
-                        reverse_pair<true>(plain_q(S, buf, g * kGroup + u, L), u < rel, ga, gb, u,
-                                           L, st, acc + u * kGrad, hit + u);
+                        for (int i = 7; i >= 0; --i) {
+                            const int u = 8 * h + i;
+                            if (reverse_pair_mm<false>(q_of(u), true, ga, gb, u, L, st,
+                                                       acc + u * kGrad, hit + u, rows[i]))
+                                hmask |= 1u << i;
+                        }
+                    } else {
+#pragma unroll
+                        for (int i = 7; i >= 0; --i) {
+                            const int u = 8 * h + i;
+                            if (reverse_pair_mm<true>(q_of(u), u < rel, ga, gb, u, L, st,
+                                                      acc + u * kGrad, hit + u, rows[i]))
+                                hmask |= 1u << i;
+                        }
+                    }
+                    if (hmask != 0u)
+                        mm_reduce(rows, mmB, hmask, gb + 8 * h, xc, yc, accw + 8 * h * kGrad, L);
                 }
+            } else if (whole) {
+#pragma unroll
+                for (int u = kGroup - 1; u >= 0; --u)
+                    reverse_pair<false>(q_of(u), true, ga, gb, u, L, st, acc + u * kGrad, hit + u);
             } else {
-                const f16x q = group_q_mfma<M, NB>(S, buf, g, L, bhi, blo);
-                if (whole) {
 #pragma unroll
-                    for (int u = kGroup - 1; u >= 0; --u)
-                        reverse_pair<false>(q[u], true, ga, gb, u, L, st, acc + u * kGrad,
-                                            hit + u);
-                } else {
-#pragma unroll
-                    for (int u = kGroup - 1; u >= 0; --u)
-                        reverse_pair<true>(q[u], u < rel, ga, gb, u, L, st, acc + u * kGrad,
-                                           hit + u);
-                }
+                for (int u = kGroup - 1; u >= 0; --u)
+                    reverse_pair<true>(q_of(u), u < rel, ga, gb, u, L, st, acc + u * kGrad,
+                                       hit + u);
             }
         }
         // Buffers: the next iteration stages into the other stage buffer. The accumulator buffer
@@ -716,33 +907,49 @@ constexpr int fit_waves(int target, size_t lds) {
 // LDS of one block: the staged batches (and, backward, the gradient accumulators), plus the few
 // scalars the kernels share
 template <Mode M, int NB> constexpr size_t lds_fwd() { return sizeof(Stage<M, NB>) + 64; }
-template <Mode M, int NB> constexpr size_t lds_bwd() {
-    return sizeof(Stage<M, NB>) + sizeof(StageBwd<NB>) + sizeof(BwdAcc<NB>) + 64;
+template <Mode M, int NB, bool kMM> constexpr size_t lds_bwd() {
+    return sizeof(Stage<M, NB>) + sizeof(StageBwd<NB>) + sizeof(BwdAcc<NB>) +
+           (kMM ? sizeof(BwdMM) : 0) + 64;
+}
+// The transposition tiles exist only in the matrix-core reduction's kernels.
+struct NoMM {};
+template <bool kMM> using MMTiles = typename std::conditional<kMM, BwdMM, NoMM>::type;
+template <bool kMM> __device__ inline BwdMM *mm_ptr(MMTiles<kMM> &t) {
+    if constexpr (kMM) return &t;
+    else return nullptr;
+}
+// Register targets of the one-tile-per-block backward kernels; the matrix-core reduction keeps
+// the product's operands and results live across each half-group and needs more registers
+// (fewer targets spill).
+template <Mode M, bool kMM> constexpr int waves_bwd_tile() {
+    return kMM ? (M == Mode::Plain ? 5 : 4) : (M == Mode::Plain ? 7 : 5);
 }
 // Single view: block b renders tile xcd_tile(b).
 template <Mode M, int NB>
 __global__ __launch_bounds__(kBlock, fit_waves(M == Mode::Plain ? 8 : 7, lds_fwd<M, NB>()))
 void k_blend_fwd(ViewDesc v) {
     __shared__ Stage<M, NB> S;
-    const int64_t tile = xcd_tile(blockIdx.x, v.n_tiles);
+    const int64_t tile = xcd_tile(blockIdx.x, v.n_tiles, v.gx);
     if (tile >= v.n_tiles) return;
     fwd_tile<M, NB>(v, tile, S);
 }
 
-template <Mode M, int NB>
-__global__ __launch_bounds__(kBlock, fit_waves(M == Mode::Plain ? 7 : 5, lds_bwd<M, NB>()))
+template <Mode M, int NB, bool kMM>
+__global__ __launch_bounds__(kBlock, fit_waves(waves_bwd_tile<M, kMM>(), lds_bwd<M, NB, kMM>()))
 void k_blend_bwd(ViewDesc v) {
     __shared__ Stage<M, NB> S;
     __shared__ StageBwd<NB> SB;
     __shared__ BwdAcc<NB> s_acc;   // per-Gaussian gradient sums of the current batch
+    __shared__ MMTiles<kMM> s_mm;
     __shared__ int s_maxlast;
-    const int64_t tile = xcd_tile(blockIdx.x, v.n_tiles);
+    const int64_t tile = xcd_tile(blockIdx.x, v.n_tiles, v.gx);
     if (tile >= v.n_tiles) return;
-    bwd_tile<M, NB>(v, tile, S, SB, s_acc, s_maxlast);
+    bwd_tile<M, NB, kMM>(v, tile, S, SB, s_acc, s_maxlast, mm_ptr<kMM>(s_mm));
 }
 
 // Many views, one persistent launch. The (view, tile) items are split into 8 queues, one per XCD:
-// queue x holds the tiles [n_tiles * x / 8, n_tiles * (x + 1) / 8) of every view, views in plan
+// queue x holds the ranks [n_tiles * x / 8, n_tiles * (x + 1) / 8) of every view (tiles in the
+// strip order of strip_tile), views in plan
 // order (heaviest per-tile cost first). A block serves the queue of its own XCD (block b runs on
 // XCD b % 8) so that neighbouring tiles share that XCD's L2, and moves on to the next queue when
 // its own is empty, so every block exits once all queues are drained.
@@ -775,7 +982,8 @@ __device__ inline bool next_item(const Queues &Q, int &q, int &tried, int &view,
                 if (pre[mid] <= i) lo = mid; else hi = mid - 1;
             }
             view = lo;
-            tile = band_lo(Q.views[lo].n_tiles, q) + (i - pre[lo]);
+            const ViewDesc &vw = Q.views[lo];
+            tile = strip_tile(band_lo(vw.n_tiles, q) + (i - pre[lo]), vw.n_tiles, vw.gx);
             return true;
         }
         q = (q + 1) % kXcds;
@@ -818,12 +1026,13 @@ void k_blend_fwd_batched(Queues Q) {
     }
 }
 
-template <Mode M, int NB>
-__global__ __launch_bounds__(kBlock, fit_waves(waves_bwd<M>(), lds_bwd<M, NB>()))
+template <Mode M, int NB, bool kMM>
+__global__ __launch_bounds__(kBlock, fit_waves(kMM ? 3 : waves_bwd<M>(), lds_bwd<M, NB, kMM>()))
 void k_blend_bwd_batched(Queues Q) {
     __shared__ Stage<M, NB> S;
     __shared__ StageBwd<NB> SB;
     __shared__ BwdAcc<NB> s_acc;
+    __shared__ MMTiles<kMM> s_mm;
     __shared__ int s_maxlast;
     __shared__ int s_view;
     __shared__ int64_t s_tile;
@@ -842,7 +1051,7 @@ void k_blend_bwd_batched(Queues Q) {
         __syncthreads();
         if (view < 0) break;
         const ViewDesc vd = Q.views[view];
-        bwd_tile<M, NB>(vd, tile, S, SB, s_acc, s_maxlast);
+        bwd_tile<M, NB, kMM>(vd, tile, S, SB, s_acc, s_maxlast, mm_ptr<kMM>(s_mm));
         __syncthreads();
     }
 }
@@ -862,7 +1071,8 @@ __device__ inline bool grid_item(const Queues &Q, int64_t b, int &view, int64_t 
         if (pre[mid] <= i) lo = mid; else hi = mid - 1;
     }
     view = lo;
-    tile = band_lo(Q.views[lo].n_tiles, x) + (i - pre[lo]);
+    const ViewDesc &vw = Q.views[lo];
+    tile = strip_tile(band_lo(vw.n_tiles, x) + (i - pre[lo]), vw.n_tiles, vw.gx);
     return true;
 }
 
@@ -877,18 +1087,19 @@ void k_blend_fwd_grid(Queues Q) {
     fwd_tile<M, NB>(vd, tile, S);
 }
 
-template <Mode M, int NB>
-__global__ __launch_bounds__(kBlock, fit_waves(M == Mode::Plain ? 7 : 5, lds_bwd<M, NB>()))
+template <Mode M, int NB, bool kMM>
+__global__ __launch_bounds__(kBlock, fit_waves(waves_bwd_tile<M, kMM>(), lds_bwd<M, NB, kMM>()))
 void k_blend_bwd_grid(Queues Q) {
     __shared__ Stage<M, NB> S;
     __shared__ StageBwd<NB> SB;
     __shared__ BwdAcc<NB> s_acc;
+    __shared__ MMTiles<kMM> s_mm;
     __shared__ int s_maxlast;
     int view;
     int64_t tile;
     if (!grid_item(Q, blockIdx.x, view, tile)) return;
     const ViewDesc vd = Q.views[view];
-    bwd_tile<M, NB>(vd, tile, S, SB, s_acc, s_maxlast);
+    bwd_tile<M, NB, kMM>(vd, tile, S, SB, s_acc, s_maxlast, mm_ptr<kMM>(s_mm));
 }
 
 // Raw sums -> gradients of the stored scalars: d/dA = -S_xx/2, d/dB = -S_xy, d/dC = -S_yy/2,
@@ -933,12 +1144,17 @@ void launch_fwd_single(const ViewDesc &v, int nb, hipStream_t s) {
     else k_blend_fwd<M, 256><<<grid, kBlock, 0, s>>>(v);
 }
 
-template <Mode M>
+template <Mode M, bool kMM>
 void launch_bwd_single(const ViewDesc &v, int nb, hipStream_t s) {
     const dim3 grid(unsigned(xcd_grid(v.n_tiles)));
-    if (nb == 64) k_blend_bwd<M, 64><<<grid, kBlock, 0, s>>>(v);
-    else if (nb == 128) k_blend_bwd<M, 128><<<grid, kBlock, 0, s>>>(v);
-    else k_blend_bwd<M, 256><<<grid, kBlock, 0, s>>>(v);
+    if (nb == 64) k_blend_bwd<M, 64, kMM><<<grid, kBlock, 0, s>>>(v);
+    else if (nb == 128) k_blend_bwd<M, 128, kMM><<<grid, kBlock, 0, s>>>(v);
+    else k_blend_bwd<M, 256, kMM><<<grid, kBlock, 0, s>>>(v);
+}
+template <Mode M>
+void launch_bwd_single(const ViewDesc &v, int nb, bool mm, hipStream_t s) {
+    if (mm) launch_bwd_single<M, true>(v, nb, s);
+    else launch_bwd_single<M, false>(v, nb, s);
 }
 
 template <Mode M>
@@ -947,17 +1163,21 @@ const void *fwd_batched_fn(int nb) {
     if (nb == 128) return reinterpret_cast<const void *>(&k_blend_fwd_batched<M, 128>);
     return reinterpret_cast<const void *>(&k_blend_fwd_batched<M, 256>);
 }
-template <Mode M>
+template <Mode M, bool kMM>
 const void *bwd_batched_fn(int nb) {
-    if (nb == 64) return reinterpret_cast<const void *>(&k_blend_bwd_batched<M, 64>);
-    if (nb == 128) return reinterpret_cast<const void *>(&k_blend_bwd_batched<M, 128>);
-    return reinterpret_cast<const void *>(&k_blend_bwd_batched<M, 256>);
+    if (nb == 64) return reinterpret_cast<const void *>(&k_blend_bwd_batched<M, 64, kMM>);
+    if (nb == 128) return reinterpret_cast<const void *>(&k_blend_bwd_batched<M, 128, kMM>);
+    return reinterpret_cast<const void *>(&k_blend_bwd_batched<M, 256, kMM>);
 }
-const void *batched_fn(gsb_precision prec, bool fwd, int nb) {
+template <Mode M>
+const void *bwd_batched_fn(int nb, bool mm) {
+    return mm ? bwd_batched_fn<M, true>(nb) : bwd_batched_fn<M, false>(nb);
+}
+const void *batched_fn(gsb_precision prec, bool fwd, int nb, bool mm) {
     switch (prec) {
-        case GSB_FP32_PLAIN: return fwd ? fwd_batched_fn<Mode::Plain>(nb) : bwd_batched_fn<Mode::Plain>(nb);
-        case GSB_FP16_GEMM: return fwd ? fwd_batched_fn<Mode::F16>(nb) : bwd_batched_fn<Mode::F16>(nb);
-        default: return fwd ? fwd_batched_fn<Mode::BF16>(nb) : bwd_batched_fn<Mode::BF16>(nb);
+        case GSB_FP32_PLAIN: return fwd ? fwd_batched_fn<Mode::Plain>(nb) : bwd_batched_fn<Mode::Plain>(nb, mm);
+        case GSB_FP16_GEMM: return fwd ? fwd_batched_fn<Mode::F16>(nb) : bwd_batched_fn<Mode::F16>(nb, mm);
+        default: return fwd ? fwd_batched_fn<Mode::BF16>(nb) : bwd_batched_fn<Mode::BF16>(nb, mm);
     }
 }
 
@@ -986,16 +1206,16 @@ gsb_status blend_forward(const ViewDesc &v, gsb_precision prec, int nb, hipStrea
     return check_launch("blend_forward");
 }
 
-gsb_status blend_backward(const ViewDesc &v, gsb_precision prec, int nb, hipStream_t s) {
+gsb_status blend_backward(const ViewDesc &v, gsb_precision prec, int nb, bool mm, hipStream_t s) {
     if (!valid_batch(nb)) return fail(GSB_ERR_INVALID, "batch %d not in {64, 128, 256}", nb);
     if (prec != GSB_FP32_PLAIN && prec != GSB_FP16_GEMM && prec != GSB_BF16_GEMM)
         return fail(GSB_ERR_INVALID, "unknown precision %d", int(prec));
     const unsigned gz = unsigned((v.n + 255) / 256);
     if (v.n > 0) k_zero_grads<<<dim3(gz, 1), 256, 0, s>>>(nullptr, v);
     switch (prec) {
-        case GSB_FP32_PLAIN: launch_bwd_single<Mode::Plain>(v, nb, s); break;
-        case GSB_FP16_GEMM: launch_bwd_single<Mode::F16>(v, nb, s); break;
-        default: launch_bwd_single<Mode::BF16>(v, nb, s); break;
+        case GSB_FP32_PLAIN: launch_bwd_single<Mode::Plain>(v, nb, mm, s); break;
+        case GSB_FP16_GEMM: launch_bwd_single<Mode::F16>(v, nb, mm, s); break;
+        default: launch_bwd_single<Mode::BF16>(v, nb, mm, s); break;
     }
     if (v.n > 0) k_bwd_finish<<<dim3(gz, 1), 256, 0, s>>>(nullptr, v);
     return check_launch("blend_backward");
@@ -1055,8 +1275,8 @@ gsb_status plan_create(const ViewDesc *views, int n_views, gsb_precision prec, c
     if (e == hipSuccess) e = hipMemcpy(p->d_prefix, prefix.data(), sizeof(int64_t) * prefix.size(), hipMemcpyHostToDevice);
     int cus = 0, occ_f = 0, occ_b = 0;
     if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, p->device);
-    if (e == hipSuccess) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ_f, batched_fn(prec, true, t.batch_fwd), kBlock, 0);
-    if (e == hipSuccess) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ_b, batched_fn(prec, false, t.batch_bwd), kBlock, 0);
+    if (e == hipSuccess) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ_f, batched_fn(prec, true, t.batch_fwd, false), kBlock, 0);
+    if (e == hipSuccess) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ_b, batched_fn(prec, false, t.batch_bwd, t.bwd_mm != 0), kBlock, 0);
     if (e != hipSuccess) {
         (void)plan_destroy(p);      // the creation error is the one reported
         return fail(GSB_ERR_HIP, "plan_create: %s", hipGetErrorString(e));
@@ -1099,19 +1319,24 @@ void launch_fwd_batched(const Queues &Q, int nb, const Plan &p, hipStream_t s) {
     else if (nb == 128) k_blend_fwd_batched<M, 128><<<grid, kBlock, 0, s>>>(Q);
     else k_blend_fwd_batched<M, 256><<<grid, kBlock, 0, s>>>(Q);
 }
-template <Mode M>
+template <Mode M, bool kMM>
 void launch_bwd_batched(const Queues &Q, int nb, const Plan &p, hipStream_t s) {
     if (p.tune.launch == kLaunchGrid) {
         const dim3 g(unsigned(p.grid_items));
-        if (nb == 64) k_blend_bwd_grid<M, 64><<<g, kBlock, 0, s>>>(Q);
-        else if (nb == 128) k_blend_bwd_grid<M, 128><<<g, kBlock, 0, s>>>(Q);
-        else k_blend_bwd_grid<M, 256><<<g, kBlock, 0, s>>>(Q);
+        if (nb == 64) k_blend_bwd_grid<M, 64, kMM><<<g, kBlock, 0, s>>>(Q);
+        else if (nb == 128) k_blend_bwd_grid<M, 128, kMM><<<g, kBlock, 0, s>>>(Q);
+        else k_blend_bwd_grid<M, 256, kMM><<<g, kBlock, 0, s>>>(Q);
         return;
     }
     const int grid = p.grid_bwd;
-    if (nb == 64) k_blend_bwd_batched<M, 64><<<grid, kBlock, 0, s>>>(Q);
-    else if (nb == 128) k_blend_bwd_batched<M, 128><<<grid, kBlock, 0, s>>>(Q);
-    else k_blend_bwd_batched<M, 256><<<grid, kBlock, 0, s>>>(Q);
+    if (nb == 64) k_blend_bwd_batched<M, 64, kMM><<<grid, kBlock, 0, s>>>(Q);
+    else if (nb == 128) k_blend_bwd_batched<M, 128, kMM><<<grid, kBlock, 0, s>>>(Q);
+    else k_blend_bwd_batched<M, 256, kMM><<<grid, kBlock, 0, s>>>(Q);
+}
+template <Mode M>
+void launch_bwd_batched(const Queues &Q, int nb, const Plan &p, hipStream_t s) {
+    if (p.tune.bwd_mm) launch_bwd_batched<M, true>(Q, nb, p, s);
+    else launch_bwd_batched<M, false>(Q, nb, p, s);
 }
 
 gsb_status plan_forward(Plan *p, hipStream_t s) {

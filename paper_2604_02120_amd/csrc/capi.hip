@@ -279,7 +279,7 @@ gsb_status gsb_blend_backward(int32_t W, int32_t H, const uint32_t *ranges,
     v.dL_dconics = dL_dconics;
     v.dL_dopacity = dL_dopacity;
     v.dL_dcolors = dL_dcolors;
-    return blend_backward(v, prec, kDefaultBatchBwd, static_cast<hipStream_t>(stream));
+    return blend_backward(v, prec, kDefaultBatchBwd, false, static_cast<hipStream_t>(stream));
 }
 
 gsb_status gsb_plan_create(const gsb_view *views, int32_t n_views, gsb_precision prec,
@@ -291,12 +291,15 @@ gsb_status gsb_plan_create(const gsb_view *views, int32_t n_views, gsb_precision
     GSB_REQUIRE(views != nullptr, "views must be non-null");
     GSB_REQUIRE(prec == GSB_FP32_PLAIN || prec == GSB_FP16_GEMM || prec == GSB_BF16_GEMM,
                 "unknown precision %d", int(prec));
-    Tuning t{kDefaultBatchFwd, kDefaultBatchBwd, 0, kLaunchPersistent};
+    Tuning t{kDefaultBatchFwd, kDefaultBatchBwd, 0, kLaunchPersistent, 0};
     if (tuning) {
         if (tuning->batch_fwd) t.batch_fwd = tuning->batch_fwd;
         if (tuning->batch_bwd) t.batch_bwd = tuning->batch_bwd;
         t.blocks_per_cu = tuning->blocks_per_cu;
         t.launch = tuning->launch;
+        t.bwd_mm = tuning->bwd_reduce;
+        GSB_REQUIRE(t.bwd_mm == GSB_REDUCE_VALU || t.bwd_mm == GSB_REDUCE_MFMA,
+                    "backward reduction %d unknown", int(t.bwd_mm));
         GSB_REQUIRE(t.blocks_per_cu >= 0, "blocks_per_cu must be >= 0");
         GSB_REQUIRE(t.launch == GSB_LAUNCH_PERSISTENT || t.launch == GSB_LAUNCH_GRID,
                     "launch mode %d unknown", int(t.launch));

@@ -21,17 +21,32 @@ inline int64_t grid_x(int32_t W) { return (W + kTile - 1) / kTile; }
 inline int64_t grid_y(int32_t H) { return (H + kTile - 1) / kTile; }
 
 // Blocks of a tile launch are spread over the 8 XCDs of the MI355X round-robin by the hardware
-// dispatcher (block b runs on XCD b % 8). Mapping block b to tile (b % 8) * chunk + b / 8 gives
-// every XCD one contiguous band of rows, so the Gaussians shared by neighbouring tiles are reused
-// from that XCD's own L2. Blocks past the last tile exit at once.
+// dispatcher (block b runs on XCD b % 8). Block b takes rank (b % 8) * chunk + b / 8 of the tile
+// order, so every XCD walks one contiguous range of ranks, and the Gaussians shared by the tiles
+// it renders at the same time are reused from that XCD's own L2. The order (strip_tile) walks the
+// image in strips of kStrip tile rows, column by column within a strip: the few hundred blocks an
+// XCD holds at once then cover a compact kStrip-row region instead of one long row of tiles (the
+// forward 2-5% and the backward 1-3% faster than plain row-major ranks at 1080p and 4K).
+// Blocks past the last tile exit at once.
 constexpr int kXcds = 8;
+constexpr int kStrip = 8;
 inline int64_t xcd_grid(int64_t n_tiles) {
     const int64_t chunk = (n_tiles + kXcds - 1) / kXcds;
     return chunk * kXcds;
 }
-__device__ inline int64_t xcd_tile(int64_t block, int64_t n_tiles) {
+// Tile of rank r (< n_tiles) of the strip order on a grid gx tiles wide.
+__device__ inline int64_t strip_tile(int64_t r, int64_t n_tiles, int64_t gx) {
+    const int64_t gy = n_tiles / gx;
+    const int64_t s = r / (kStrip * gx), r0 = s * kStrip;
+    const int64_t hs = gy - r0 < kStrip ? gy - r0 : kStrip;   // rows of this strip
+    const int64_t j = r - s * kStrip * gx;
+    return (r0 + j % hs) * gx + j / hs;
+}
+// Tile of block `block` (>= n_tiles: past the end).
+__device__ inline int64_t xcd_tile(int64_t block, int64_t n_tiles, int64_t gx) {
     const int64_t chunk = (n_tiles + kXcds - 1) / kXcds;
-    return (block % kXcds) * chunk + block / kXcds;
+    const int64_t r = (block % kXcds) * chunk + block / kXcds;
+    return r < n_tiles ? strip_tile(r, n_tiles, gx) : r;
 }
 
 // Covered tiles [tx0, tx1) x [ty0, ty1) of a Gaussian at (x, y) with radius r: tx in
@@ -118,6 +133,7 @@ struct Tuning {
     int batch_bwd;       // same for the backward
     int blocks_per_cu;   // persistent batched launches: resident blocks per compute unit
     int launch;          // batched: kLaunchPersistent or kLaunchGrid
+    int bwd_mm;          // backward: geometric gradient sums on the matrix cores (1) or VALU (0)
 };
 constexpr int kLaunchPersistent = 0;
 constexpr int kLaunchGrid = 1;
@@ -125,7 +141,7 @@ constexpr int kDefaultBatchFwd = 128;
 constexpr int kDefaultBatchBwd = 128;
 
 gsb_status blend_forward(const ViewDesc &v, gsb_precision prec, int batch, hipStream_t s);
-gsb_status blend_backward(const ViewDesc &v, gsb_precision prec, int batch, hipStream_t s);
+gsb_status blend_backward(const ViewDesc &v, gsb_precision prec, int batch, bool mm, hipStream_t s);
 
 // Batched (multi-view) persistent launches.
 struct Plan;

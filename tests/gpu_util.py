@@ -40,10 +40,19 @@ MAX_LAST_MISMATCH = {"fp16": 0.0, "bf16": 1e-5}
 GEMM_PSNR = 50.0        # FP16/BF16 GEMM path vs FP64 oracle, all pixels
 GEMM_GRAD = 1e-3        # normwise relative gradient error, GEMM path
 PLAIN_GRAD = 1e-5       # normwise relative gradient error, plain FP32 path
-# The clustered stress scene (saturated pixels, lists up to ~8700 entries): the transmittance that
-# the backward recovers by division, T_i = T_(i+1) / (1 - alpha_i), carries the FP32 rounding of
-# every opaque layer between the pixel's end and the pair; measured 2.9e-5 (means).
-PLAIN_GRAD_SATURATED = 5e-5
+# Two stress scenes take 5e-5 in the plain form:
+#   clustered (saturated pixels, lists up to ~8700 entries): the transmittance that the backward
+#     recovers by division, T_i = T_(i+1) / (1 - alpha_i), carries the FP32 rounding of every
+#     opaque layer between the pixel's end and the pair; measured 2.9e-5 (means);
+#   bigrects (sigma up to 64 px, footprints of up to ~600 tiles): each such Gaussian's gradient is
+#     a sum of hundreds of per-tile partials of both signs in FP32; measured 3.2e-5 (conics), the
+#     same with either reduction of the per-tile sums.
+PLAIN_GRAD_STRESS = 5e-5
+STRESS_SCENES = ("clustered", "bigrects")
+
+
+def plain_grad_bound(scene: str) -> float:
+    return PLAIN_GRAD_STRESS if scene in STRESS_SCENES else PLAIN_GRAD
 
 
 def say(*a):

@@ -36,7 +36,7 @@ def test_library_exports_every_declared_symbol():
 
 
 def test_abi_version():
-    assert _lib.gsb_abi_version() == 4
+    assert _lib.gsb_abi_version() == 5
 
 
 def test_project_validation_before_device():

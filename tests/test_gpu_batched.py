@@ -87,12 +87,18 @@ def test_batched_every_shape_same_results(gpu, small_views, prec):
         bv.forward()
         bv.backward()
         torch.cuda.synchronize()
+        # the matrix-core reduction rounds dL/dpower to FP16 hi + lo (2^-20 relative) and forms
+        # the geometric sums from moments about the tile centre: not the same rounding
+        bound = 1e-5 if cand["bwd_reduce"] == 0 else 1e-4
+        worst = 0.0
         for i, v in enumerate(bv.views):
             assert torch.equal(v["image"], ref[i]), (cand, i)
             for k, r in zip(GRADS, ref_g[i]):
                 e = normwise(v[k].cpu().numpy().astype(np.float64),
                              r.cpu().numpy().astype(np.float64))
-                assert e <= 1e-5, (cand, i, k, e)
+                worst = max(worst, e)
+                assert e <= bound, (cand, i, k, e)
+        say(f"  worst gradient difference from the default shape: {worst:.3e}")
     bv.close()
 
 
@@ -164,7 +170,7 @@ def test_autotune_picks_a_candidate(gpu, small_views, tmp_path, monkeypatch):
     bv = api.BatchedViews(views, prec="fp16")
     best = autotune.tune(bv, reps=2)
     say(f"[autotune] {best}")
-    keys = ("batch_fwd", "batch_bwd", "blocks_per_cu", "launch")
+    keys = autotune.KEYS
     assert {k: best[k] for k in keys} in autotune.CANDIDATES
     assert len(best["trials"]) == len(autotune.CANDIDATES)
     again = autotune.tune(bv)            # from the cache

@@ -13,7 +13,7 @@ import torch
 
 import gsinputs
 import oracle
-from gpu_util import (GEMM_GRAD, PLAIN_GRAD, PLAIN_GRAD_SATURATED, check_gemm, check_plain,
+from gpu_util import (GEMM_GRAD, PLAIN_GRAD, check_gemm, check_plain, plain_grad_bound,
                       gpu_forward, normwise, say, upload, upload_bins)
 from paper_2604_02120_amd import api
 from paper_2604_02120_amd.autograd import blend
@@ -210,8 +210,7 @@ def test_backward_parity(gpu, prec, name):
     s = SCENES[name]
     say(f"[bwd] {name} {prec}")
     got, ref = backward_case(s, gpu, prec)
-    bound = (PLAIN_GRAD_SATURATED if name == "clustered" else PLAIN_GRAD) if prec == "fp32" \
-        else GEMM_GRAD
+    bound = plain_grad_bound(name) if prec == "fp32" else GEMM_GRAD
     for k in ref:
         e = normwise(got[k], ref[k])
         say(f"  {k}: normwise rel err {e:.3e}")
@@ -405,3 +404,44 @@ def test_three_tile_sort_passes(gpu):
                                  s["colors"])
             img, T, last = gpu_forward(sd, pl, rg, "fp32")
             check_plain(ref, img, T, last, "66k tiles")
+
+
+# ----------------------------------------------------------------------------- backward reduction
+def plan_grads(sd, prec, g, bg, bwd_reduce, batch_bwd=128):
+    """Gradients from a one-view plan (one block per tile) with the given backward reduction."""
+    bv = api.BatchedViews([sd], prec=prec, bg=bg,
+                          tuning={"launch": 1, "batch_bwd": batch_bwd, "bwd_reduce": bwd_reduce})
+    bv.views[0]["dL_dimage"].copy_(torch.from_numpy(g))
+    bv.step()
+    torch.cuda.synchronize()
+    v = bv.views[0]
+    out = {k: v["dL_" + k].cpu().numpy().astype(np.float64)
+           for k in ("dmeans2d", "dconics", "dopacity", "dcolors")}
+    bv.close()
+    return out
+
+
+@pytest.mark.parametrize("prec", PRECS)
+@pytest.mark.parametrize("name", ["C1", "lognormal", "bigrects", "clustered"])
+@pytest.mark.parametrize("batch_bwd", [64, 128])
+def test_backward_mfma_reduction(gpu, prec, name, batch_bwd):
+    """The backward with its five geometric sums formed on the matrix cores (dL/dM_g as the
+    product of dL/dpower with the pixel basis) against the FP64 oracle, at the bounds of the
+    vector-ALU reduction, and against that reduction itself."""
+    s = SCENES[name]
+    W, H = s["width"], s["height"]
+    bg = (0.1, 0.3, 0.2)
+    g = gsinputs.make_dloss(W, H, 77)
+    pl_ref, rg_ref = oracle.bin_tiles(s["means2d"], s["radii"], s["depths"], W, H)
+    ref = oracle.backward(W, H, rg_ref, pl_ref, s["means2d"], s["conics"], s["opacity"],
+                          s["colors"], g, bg)
+    sd = upload(s, gpu)
+    mm = plan_grads(sd, prec, g, bg, 1, batch_bwd)
+    valu = plan_grads(sd, prec, g, bg, 0, batch_bwd)
+    bound = plain_grad_bound(name) if prec == "fp32" else GEMM_GRAD
+    for k in ref:
+        e = normwise(mm[k], ref[k])
+        d = normwise(mm[k], valu[k])
+        say(f"  mfma reduction {name} {prec} b={batch_bwd} {k}: vs oracle {e:.3e}, "
+            f"vs vector reduction {d:.3e}")
+        assert e <= bound, (k, e)

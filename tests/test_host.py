@@ -98,15 +98,14 @@ def test_autotune_picks_fastest_and_caches(tmp_path, monkeypatch):
     best = autotune.tune(bv)
     assert len(calls) == len(autotune.CANDIDATES)
     assert best["launch"] == 1 and best["batch_bwd"] == 256
-    assert bv.plans[-1] == {k: best[k] for k in ("batch_fwd", "batch_bwd", "blocks_per_cu", "launch")}
+    assert bv.plans[-1] == {k: best[k] for k in autotune.KEYS}
     assert [t["ms"] for t in best["trials"]] == sorted(t["ms"] for t in best["trials"])
     # the second call reads the cache: no measurement, no binning, same plan
     calls.clear()
     bv2 = FakeViews()
     again = autotune.tune(bv2)
     assert calls == [] and bv2.binned == 0
-    assert {k: again[k] for k in ("batch_fwd", "batch_bwd", "blocks_per_cu", "launch")} == \
-        {k: best[k] for k in ("batch_fwd", "batch_bwd", "blocks_per_cu", "launch")}
+    assert {k: again[k] for k in autotune.KEYS} == {k: best[k] for k in autotune.KEYS}
     # a damaged cache file is ignored, not fatal
     (tmp_path / "sub" / "tuning.json").write_text("{not json")
     assert autotune._load() == {}
@@ -117,6 +116,9 @@ def test_autotune_candidates_are_valid_shapes():
     for c in autotune.CANDIDATES:
         assert c["batch_fwd"] in (64, 128, 256) and c["batch_bwd"] in (64, 128, 256)
         assert c["launch"] in (0, 1) and c["blocks_per_cu"] >= 0
+        assert c["bwd_reduce"] in (0, 1) and set(c) == set(autotune.KEYS)
+        # the matrix-core reduction's LDS tiles are tried only where 4-5 blocks fit per CU
+        assert c["bwd_reduce"] == 0 or (c["launch"] == 1 and c["batch_bwd"] in (64, 128))
         key = tuple(sorted(c.items()))
         assert key not in seen
         seen.add(key)
