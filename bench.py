@@ -76,6 +76,8 @@ def parse():
     p.add_argument("--precs", default="bf16,fp32,fp16",
                    help="comma list; the first is the headline")
     p.add_argument("--no-cpu-baseline", action="store_true")
+    p.add_argument("--arrays", action="store_true",
+                   help="blend from the four attribute arrays instead of packed records")
     p.add_argument("--no-batched", action="store_true",
                    help="skip the 16-view batched measurement")
     p.add_argument("--no-visible", action="store_true",
@@ -127,6 +129,8 @@ class Frame:
                         torch.empty((self.H, self.W), dtype=torch.int32, device=dev))
         self.bwd_out = (torch.empty((self.n, 2), device=dev), torch.empty((self.n, 3), device=dev),
                         torch.empty((self.n,), device=dev), torch.empty((self.n, 3), device=dev))
+        self.records = torch.empty((self.n, 12), device=dev)
+        self.packed = True       # blend from packed records (the pack is timed with the forward)
         self.status = None
 
     @classmethod
@@ -143,14 +147,25 @@ class Frame:
                                    opacity=self.opacity, mode=self.bin_mode)
         if ev is not None:
             ev[1].record()
-        img, T, last = api.blend_forward(self.means2d, self.conics, self.opacity, self.colors,
-                                         self.ranges, self.point_list, self.W, self.H,
-                                         (0.0, 0.0, 0.0), prec, out=self.fwd_out)
+        if self.packed:
+            api.pack_gaussians(self.means2d, self.conics, self.opacity, self.colors,
+                               out=self.records)
+            img, T, last = api.blend_forward_packed(self.records, self.ranges, self.point_list,
+                                                    self.W, self.H, (0.0, 0.0, 0.0), prec,
+                                                    out=self.fwd_out)
+        else:
+            img, T, last = api.blend_forward(self.means2d, self.conics, self.opacity, self.colors,
+                                             self.ranges, self.point_list, self.W, self.H,
+                                             (0.0, 0.0, 0.0), prec, out=self.fwd_out)
         if ev is not None:
             ev[2].record()
-        api.blend_backward(self.means2d, self.conics, self.opacity, self.colors, self.ranges,
-                           self.point_list, self.W, self.H, T, last, self.dloss, (0.0, 0.0, 0.0),
-                           prec, out=self.bwd_out)
+        if self.packed:
+            api.blend_backward_packed(self.records, self.ranges, self.point_list, self.W, self.H,
+                                      T, last, self.dloss, (0.0, 0.0, 0.0), prec, out=self.bwd_out)
+        else:
+            api.blend_backward(self.means2d, self.conics, self.opacity, self.colors, self.ranges,
+                               self.point_list, self.W, self.H, T, last, self.dloss,
+                               (0.0, 0.0, 0.0), prec, out=self.bwd_out)
         if ev is not None:
             ev[3].record()
 
@@ -544,7 +559,7 @@ def counter_fractions(config: str, prec: str) -> dict | None:
     the counters were taken."""
     if not os.path.exists(TRAFFIC):
         return None
-    out = {"source": f"rocprofv3 --pmc over the {config} step, profiles/blend_{config.lower()}_*"}
+    out = {"source": f"rocprofv3 --pmc over the {config} step, profiles/blend_{config.lower()}_*_pmc.md"}
     for kern in ("forward", "backward"):
         ent = traffic_entry(config, f"{kern}_{prec}")
         out[kern] = ent.get("fractions") if ent else None
@@ -666,6 +681,7 @@ def main():
         return
     cfg = gsinputs.CONFIGS[args.config]
     fr = Frame(cfg, dev)
+    fr.packed = not args.arrays
     counts = json.load(open(COUNTS))[args.config]
     precs = args.precs.split(",")
     results, outputs = {}, {}

@@ -52,7 +52,7 @@ typedef int32_t gsb_precision;
 #define GSB_FP16_GEMM 1   /* exponent as an MFMA product, FP16 hi+lo operands, FP32 accumulate */
 #define GSB_BF16_GEMM 2   /* same with BF16 hi+lo operands */
 
-#define GSB_ABI_VERSION 5
+#define GSB_ABI_VERSION 6
 
 /* Version of this interface (GSB_ABI_VERSION of the library that was loaded). */
 int32_t gsb_abi_version(void);
@@ -234,6 +234,35 @@ gsb_status gsb_blend_backward(int32_t W, int32_t H, const uint32_t *ranges,
                               const float *final_T, const int32_t *last_contrib,
                               const float *dL_dimage, float *dL_dmeans2d, float *dL_dconics,
                               float *dL_dopacity, float *dL_dcolors, void *stream);
+
+/* ---------------------------------------------------------------------------------------------
+ * Packed attributes. The blend fetches, per list entry, the 9 attributes of one Gaussian (the
+ * fetch step of Alg. 1 and Alg. 2). Read from the four input arrays that is four scattered loads,
+ * each touching a cache line of its own; gsb_pack_gaussians writes them once per frame as one
+ * 48-byte record per Gaussian, which the _packed blends read with three 16-byte loads.
+ *
+ * records: device f32[n][GSB_RECORD_FLOATS], 16-byte aligned; record i is
+ *   (x, y, A, B), (C, o, r, g), (b, 0, 0, 0) of Gaussian i.
+ * gsb_blend_forward_packed / gsb_blend_backward_packed compute exactly what gsb_blend_forward /
+ * gsb_blend_backward compute from the arrays the records were packed from (same arithmetic, same
+ * outputs; the gradients up to the order of their FP32 atomic sums), with the default launch shape.
+ * Errors: INVALID (null or misaligned pointers, sizes, prec), UNSUPPORTED, HIP.
+ * ------------------------------------------------------------------------------------------- */
+#define GSB_RECORD_FLOATS 12
+gsb_status gsb_pack_gaussians(const float *means2d, const float *conics, const float *opacity,
+                              const float *colors, int64_t n, float *records, void *stream);
+
+gsb_status gsb_blend_forward_packed(int32_t W, int32_t H, const uint32_t *ranges,
+                                    const uint32_t *point_list, const float *records, int64_t n,
+                                    const float *bg, gsb_precision prec, float *image,
+                                    float *final_T, int32_t *last_contrib, void *stream);
+
+gsb_status gsb_blend_backward_packed(int32_t W, int32_t H, const uint32_t *ranges,
+                                     const uint32_t *point_list, const float *records, int64_t n,
+                                     const float *bg, gsb_precision prec, const float *final_T,
+                                     const int32_t *last_contrib, const float *dL_dimage,
+                                     float *dL_dmeans2d, float *dL_dconics, float *dL_dopacity,
+                                     float *dL_dcolors, void *stream);
 
 /* ---------------------------------------------------------------------------------------------
  * Batched views: many images (views) of uneven size, each with its own Gaussians and binning,

@@ -34,7 +34,8 @@ GSB_REDUCE_MFMA = 1
 
 # every function declared in include/gsblend.h
 EXPORTS = ("gsb_abi_version", "gsb_last_error", "gsb_project", "gsb_bin_workspace_bytes",
-           "gsb_bin_count", "gsb_bin_fill", "gsb_bin_noalloc", "gsb_blend_forward", "gsb_blend_backward", "gsb_plan_create",
+           "gsb_bin_count", "gsb_bin_fill", "gsb_bin_noalloc", "gsb_pack_gaussians",
+           "gsb_blend_forward_packed", "gsb_blend_backward_packed", "gsb_blend_forward", "gsb_blend_backward", "gsb_plan_create",
            "gsb_plan_destroy", "gsb_blend_batched_forward", "gsb_blend_batched_backward")
 
 
@@ -94,6 +95,10 @@ def load() -> ctypes.CDLL:
     lib.gsb_bin_count.argtypes = [P, P, P, P, i32, i64, i32, i32, P, sz, P, P]
     lib.gsb_bin_fill.argtypes = [P, P, P, P, i32, P, i64, i32, i32, P, sz, P, i64, P, P, P]
     lib.gsb_bin_noalloc.argtypes = [P, P, P, P, i32, P, i64, i32, i32, P, i64, P, P, P, P]
+    lib.gsb_pack_gaussians.argtypes = [P, P, P, P, i64, P, P]
+    lib.gsb_blend_forward_packed.argtypes = [i32, i32, P, P, P, i64, P, i32, P, P, P, P]
+    lib.gsb_blend_backward_packed.argtypes = [i32, i32, P, P, P, i64, P, i32, P, P, P, P, P, P,
+                                              P, P]
     lib.gsb_blend_forward.argtypes = [i32, i32, P, P, P, P, P, P, i64, P, i32, P, P, P, P]
     lib.gsb_blend_backward.argtypes = [i32, i32, P, P, P, P, P, P, i64, P, i32, P, P, P, P, P,
                                        P, P, P]
@@ -167,6 +172,28 @@ def gsb_bin_noalloc(means2d: int, radii: int, depths: int, n: int, W: int, H: in
 
 
 GSB_NOALLOC_SCRATCH_BYTES = 64 << 20
+GSB_RECORD_FLOATS = 12
+
+
+def gsb_pack_gaussians(means2d: int, conics: int, opacity: int, colors: int, n: int,
+                       records: int, stream: int = 0) -> None:
+    _check(load().gsb_pack_gaussians(means2d, conics, opacity, colors, n, records, stream))
+
+
+def gsb_blend_forward_packed(W: int, H: int, ranges: int, point_list: int, records: int, n: int,
+                             bg, prec: int, image: int, final_T: int, last_contrib: int,
+                             stream: int = 0) -> None:
+    _check(load().gsb_blend_forward_packed(W, H, ranges, point_list, records, n, _bg(bg), prec,
+                                           image, final_T, last_contrib, stream))
+
+
+def gsb_blend_backward_packed(W: int, H: int, ranges: int, point_list: int, records: int, n: int,
+                              bg, prec: int, final_T: int, last_contrib: int, dL_dimage: int,
+                              dL_dmeans2d: int, dL_dconics: int, dL_dopacity: int,
+                              dL_dcolors: int, stream: int = 0) -> None:
+    _check(load().gsb_blend_backward_packed(W, H, ranges, point_list, records, n, _bg(bg), prec,
+                                            final_T, last_contrib, dL_dimage, dL_dmeans2d,
+                                            dL_dconics, dL_dopacity, dL_dcolors, stream))
 
 
 def gsb_blend_forward(W: int, H: int, ranges: int, point_list: int, means2d: int, conics: int,

@@ -205,6 +205,55 @@ def blend_backward(means2d, conics, opacity, colors, ranges, point_list, W: int,
     return dm, dc, do, dcol
 
 
+def pack_gaussians(means2d, conics, opacity, colors, stream=None, out=None) -> torch.Tensor:
+    """The per-Gaussian records (f32[n][12], one 48-byte record per Gaussian) that the _packed
+    blends read instead of the four arrays."""
+    n = opacity.shape[0]
+    for t, name in ((means2d, "means2d"), (conics, "conics"), (opacity, "opacity"),
+                    (colors, "colors")):
+        _req(t, torch.float32, name)
+    rec = torch.empty((n, _lib.GSB_RECORD_FLOATS), dtype=torch.float32,
+                      device=means2d.device) if out is None else out
+    _req(rec, torch.float32, "records")
+    _lib.gsb_pack_gaussians(means2d.data_ptr(), conics.data_ptr(), opacity.data_ptr(),
+                            colors.data_ptr(), n, rec.data_ptr(), _stream(stream))
+    return rec
+
+
+def blend_forward_packed(records, ranges, point_list, W: int, H: int, bg=(0.0, 0.0, 0.0),
+                         prec="fp16", stream=None, out=None):
+    """As blend_forward, reading the Gaussians from pack_gaussians' records."""
+    n = records.shape[0]
+    _req(records, torch.float32, "records")
+    dev = records.device
+    img, T, last = out if out is not None else (
+        torch.empty((3, H, W), dtype=torch.float32, device=dev),
+        torch.empty((H, W), dtype=torch.float32, device=dev),
+        torch.empty((H, W), dtype=torch.int32, device=dev))
+    _lib.gsb_blend_forward_packed(W, H, ranges.data_ptr(), point_list.data_ptr(),
+                                  records.data_ptr(), n, bg, prec_code(prec), img.data_ptr(),
+                                  T.data_ptr(), last.data_ptr(), _stream(stream))
+    return img, T, last
+
+
+def blend_backward_packed(records, ranges, point_list, W: int, H: int, final_T, last_contrib,
+                          dL_dimage, bg=(0.0, 0.0, 0.0), prec="fp16", stream=None, out=None):
+    """As blend_backward, reading the Gaussians from pack_gaussians' records."""
+    n = records.shape[0]
+    _req(records, torch.float32, "records")
+    dev = records.device
+    dm, dc, do, dcol = out if out is not None else (
+        torch.empty((n, 2), dtype=torch.float32, device=dev),
+        torch.empty((n, 3), dtype=torch.float32, device=dev),
+        torch.empty((n,), dtype=torch.float32, device=dev),
+        torch.empty((n, 3), dtype=torch.float32, device=dev))
+    _lib.gsb_blend_backward_packed(W, H, ranges.data_ptr(), point_list.data_ptr(),
+                                   records.data_ptr(), n, bg, prec_code(prec), final_T.data_ptr(),
+                                   last_contrib.data_ptr(), dL_dimage.data_ptr(), dm.data_ptr(),
+                                   dc.data_ptr(), do.data_ptr(), dcol.data_ptr(), _stream(stream))
+    return dm, dc, do, dcol
+
+
 class BatchedViews:
     """Many views blended by one persistent launch per direction (gsb_plan_*).
 

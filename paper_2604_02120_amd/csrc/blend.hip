@@ -201,6 +201,40 @@ __device__ inline GRaw fetch_attrs(uint32_t id, uint32_t n, const float2 *means,
     return g;
 }
 
+// Where a tile's Gaussian attributes come from: the four input arrays (four scattered loads per
+// list entry, each touching a cache line of its own), or the packed records of
+// gsb_pack_gaussians (three 16-byte loads from one 48-byte record). Loads are unconditional in
+// both, as in fetch_attrs.
+template <bool kPacked> struct Attrs;
+template <> struct Attrs<false> {
+    const float2 *means;
+    const F3 *conics;
+    const float *opac;
+    const F3 *colors;
+    __device__ explicit Attrs(const ViewDesc &v)
+        : means(reinterpret_cast<const float2 *>(v.means2d)),
+          conics(reinterpret_cast<const F3 *>(v.conics)), opac(v.opacity),
+          colors(reinterpret_cast<const F3 *>(v.colors)) {}
+    __device__ GRaw fetch(uint32_t id, uint32_t n) const {
+        return fetch_attrs(id, n, means, conics, opac, colors);
+    }
+};
+template <> struct Attrs<true> {
+    const float4 *rec;
+    __device__ explicit Attrs(const ViewDesc &v) : rec(v.records) {}
+    __device__ GRaw fetch(uint32_t id, uint32_t n) const {
+        GRaw g;
+        g.valid = id < n;
+        g.id = g.valid ? id : 0u;
+        const float4 *r = rec + 3 * size_t(g.id);
+        const float4 a = r[0], b = r[1], c = r[2];
+        g.x = a.x; g.y = a.y; g.A = a.z; g.B = a.w;
+        g.C = b.x; g.o = b.y; g.r = b.z; g.g = b.w;
+        g.b = c.x;
+        return g;
+    }
+};
+
 // Writes one Gaussian into slot `slot` of buffer `buf`. (xc, yc) is the tile centre.
 template <Mode M, int NB, bool Bwd>
 __device__ inline void stage(const GRaw &g, int buf, int slot, float xc, float yc, Stage<M, NB> &S,
@@ -352,16 +386,13 @@ __device__ inline void composite_group(const float4 *attr, int base, FwdState &s
 
 // Forward of one tile of one view (all 256 threads of the block take part; block-uniform control
 // flow around every barrier).
-template <Mode M, int NB>
+template <Mode M, int NB, bool kPacked = false>
 __device__ inline void fwd_tile(const ViewDesc &v, int64_t tile, Stage<M, NB> &S) {
     static_assert(NB % kGroup == 0 && NB <= kBlock, "batch must be whole groups, <= block");
     constexpr int kGroups = NB / kGroup;
     const uint32_t *plist = v.point_list;
     const uint32_t n = uint32_t(v.n);
-    const float2 *means = reinterpret_cast<const float2 *>(v.means2d);
-    const F3 *conics = reinterpret_cast<const F3 *>(v.conics);
-    const F3 *colors = reinterpret_cast<const F3 *>(v.colors);
-    const float *opac = v.opacity;
+    const Attrs<kPacked> src(v);
     const Lane L = lane_setup(tile, v.gx, v.W, v.H);
     const float xc = float(int(tile % v.gx) * kTile) + 7.5f, yc = float(int(tile / v.gx) * kTile) + 7.5f;
     typename Op<M>::vec bhi, blo;
@@ -385,7 +416,7 @@ __device__ inline void fwd_tile(const ViewDesc &v, int64_t tile, Stage<M, NB> &S
     GRaw nxt{};
     Entry ent{kNoEntry, false};
     if (nb > 0) {                               // (len > 0, so entry `start` exists)
-        nxt = fetch_attrs(entry(0).id(), n, means, conics, opac, colors);
+        nxt = src.fetch(entry(0).id(), n);
         ent = entry(1);
     }
     for (int b = 0; b < nb; ++b) {
@@ -394,7 +425,7 @@ __device__ inline void fwd_tile(const ViewDesc &v, int64_t tile, Stage<M, NB> &S
         // barrier; also counts the pixels still live (the whole block leaves once none is)
         if (__syncthreads_count(st.thr != INFINITY) == 0) break;
         // unconditional: past the last batch these read entry `start` and Gaussian 0, unused
-        nxt = fetch_attrs(ent.id(), n, means, conics, opac, colors);
+        nxt = src.fetch(ent.id(), n);
         ent = entry(b + 2);
         const int base = b * NB;
         const int ng = int((len - base + kGroup - 1) / kGroup) < kGroups
@@ -709,17 +740,14 @@ __device__ inline void mm_reduce(uint32_t (*rows)[kDgStride], const h8 (&B)[2], 
 // Backward of one tile of one view.
 // kMM: the five geometric sums are formed on the matrix cores (mm_reduce) instead of being
 // reduced on the vector ALUs with the other four; `mm` is then the block's transposition tiles.
-template <Mode M, int NB, bool kMM>
+template <Mode M, int NB, bool kMM, bool kPacked = false>
 __device__ inline void bwd_tile(const ViewDesc &v, int64_t tile, Stage<M, NB> &S, StageBwd<NB> &SB,
                                 BwdAcc<NB> &s_acc, int &s_maxlast, BwdMM *mm) {
     static_assert(NB % kGroup == 0 && NB <= kBlock, "batch must be whole groups, <= block");
     constexpr int kGroups = NB / kGroup;
     const uint32_t *plist = v.point_list;
     const uint32_t n = uint32_t(v.n);
-    const float2 *means = reinterpret_cast<const float2 *>(v.means2d);
-    const F3 *conics = reinterpret_cast<const F3 *>(v.conics);
-    const F3 *colors = reinterpret_cast<const F3 *>(v.colors);
-    const float *opac = v.opacity;
+    const Attrs<kPacked> src(v);
     const Lane L = lane_setup(tile, v.gx, v.W, v.H);
     const int word = sum_word(L.l);   // the sum this lane adds when it leads a reduction
     const float xc = float(int(tile % v.gx) * kTile) + 7.5f, yc = float(int(tile / v.gx) * kTile) + 7.5f;
@@ -809,7 +837,7 @@ __device__ inline void bwd_tile(const ViewDesc &v, int64_t tile, Stage<M, NB> &S
             }
         }
     };
-    GRaw nxt = fetch_attrs(entry(nb - 1).id(), n, means, conics, opac, colors);
+    GRaw nxt = src.fetch(entry(nb - 1).id(), n);
     Entry ent = entry(nb - 2);
     // both accumulator buffers and their flags start at zero
     for (int e = L.t; e < NB * kGrad; e += kBlock) {
@@ -828,7 +856,7 @@ __device__ inline void bwd_tile(const ViewDesc &v, int64_t tile, Stage<M, NB> &S
         }
         __syncthreads();
         // unconditional: before the first batch these read entry `start` and Gaussian 0, unused
-        nxt = fetch_attrs(ent.id(), n, means, conics, opac, colors);
+        nxt = src.fetch(ent.id(), n);
         ent = entry(b - 2);
         if (b + 1 < nb) flush(b + 1);
         const int base = b * NB;
@@ -945,6 +973,44 @@ void k_blend_bwd(ViewDesc v) {
     const int64_t tile = xcd_tile(blockIdx.x, v.n_tiles, v.gx);
     if (tile >= v.n_tiles) return;
     bwd_tile<M, NB, kMM>(v, tile, S, SB, s_acc, s_maxlast, mm_ptr<kMM>(s_mm));
+}
+
+// Single view, packed records (gsb_pack_gaussians): the default launch shape (LDS batches of 128,
+// vector-ALU reduction), attributes from one 48-byte record per list entry.
+template <Mode M>
+__global__ __launch_bounds__(kBlock, fit_waves(M == Mode::Plain ? 8 : 7, lds_fwd<M, 128>()))
+void k_blend_fwd_rec(ViewDesc v) {
+    __shared__ Stage<M, 128> S;
+    const int64_t tile = xcd_tile(blockIdx.x, v.n_tiles, v.gx);
+    if (tile >= v.n_tiles) return;
+    fwd_tile<M, 128, true>(v, tile, S);
+}
+
+template <Mode M>
+__global__ __launch_bounds__(kBlock, fit_waves(waves_bwd_tile<M, false>(), lds_bwd<M, 128, false>()))
+void k_blend_bwd_rec(ViewDesc v) {
+    __shared__ Stage<M, 128> S;
+    __shared__ StageBwd<128> SB;
+    __shared__ BwdAcc<128> s_acc;
+    __shared__ int s_maxlast;
+    const int64_t tile = xcd_tile(blockIdx.x, v.n_tiles, v.gx);
+    if (tile >= v.n_tiles) return;
+    bwd_tile<M, 128, false, true>(v, tile, S, SB, s_acc, s_maxlast, nullptr);
+}
+
+// One record per Gaussian: (x, y, A, B), (C, o, r, g), (b, 0, 0, 0). Consecutive threads write
+// consecutive 48-byte records.
+__global__ __launch_bounds__(256) void k_pack(const float2 *means, const F3 *conics,
+                                              const float *opac, const F3 *colors, int64_t n,
+                                              float4 *rec) {
+    const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const float2 m = means[i];
+    const F3 c = conics[i], col = colors[i];
+    float4 *r = rec + 3 * i;
+    r[0] = make_float4(m.x, m.y, c.a, c.b);
+    r[1] = make_float4(c.c, opac[i], col.a, col.b);
+    r[2] = make_float4(col.c, 0.f, 0.f, 0.f);
 }
 
 // Many views, one persistent launch. The (view, tile) items are split into 8 queues, one per XCD:
@@ -1109,7 +1175,13 @@ __global__ __launch_bounds__(256) void k_bwd_finish(const ViewDesc *views, ViewD
     const ViewDesc &v = views ? views[blockIdx.y] : single;
     const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
     if (i >= v.n) return;
-    const F3 c = reinterpret_cast<const F3 *>(v.conics)[i];
+    F3 c;
+    if (v.records) {                 // (x, y, A, B), (C, ...): the conic from the packed record
+        const float4 r0 = v.records[3 * i], r1 = v.records[3 * i + 1];
+        c = F3{r0.z, r0.w, r1.x};
+    } else {
+        c = reinterpret_cast<const F3 *>(v.conics)[i];
+    }
     F3 *dc = reinterpret_cast<F3 *>(v.dL_dconics);
     float2 *dm = reinterpret_cast<float2 *>(v.dL_dmeans2d);
     const F3 s = dc[i];
@@ -1219,6 +1291,41 @@ gsb_status blend_backward(const ViewDesc &v, gsb_precision prec, int nb, bool mm
     }
     if (v.n > 0) k_bwd_finish<<<dim3(gz, 1), 256, 0, s>>>(nullptr, v);
     return check_launch("blend_backward");
+}
+
+gsb_status pack_gaussians(const float *means2d, const float *conics, const float *opacity,
+                          const float *colors, int64_t n, float *records, hipStream_t s) {
+    if (n > 0)
+        k_pack<<<dim3(unsigned((n + 255) / 256)), 256, 0, s>>>(
+            reinterpret_cast<const float2 *>(means2d), reinterpret_cast<const F3 *>(conics),
+            opacity, reinterpret_cast<const F3 *>(colors), n, reinterpret_cast<float4 *>(records));
+    return check_launch("pack_gaussians");
+}
+
+gsb_status blend_forward_packed(const ViewDesc &v, gsb_precision prec, hipStream_t s) {
+    const dim3 grid(unsigned(xcd_grid(v.n_tiles)));
+    switch (prec) {
+        case GSB_FP32_PLAIN: k_blend_fwd_rec<Mode::Plain><<<grid, kBlock, 0, s>>>(v); break;
+        case GSB_FP16_GEMM: k_blend_fwd_rec<Mode::F16><<<grid, kBlock, 0, s>>>(v); break;
+        case GSB_BF16_GEMM: k_blend_fwd_rec<Mode::BF16><<<grid, kBlock, 0, s>>>(v); break;
+        default: return fail(GSB_ERR_INVALID, "unknown precision %d", int(prec));
+    }
+    return check_launch("blend_forward_packed");
+}
+
+gsb_status blend_backward_packed(const ViewDesc &v, gsb_precision prec, hipStream_t s) {
+    if (prec != GSB_FP32_PLAIN && prec != GSB_FP16_GEMM && prec != GSB_BF16_GEMM)
+        return fail(GSB_ERR_INVALID, "unknown precision %d", int(prec));
+    const unsigned gz = unsigned((v.n + 255) / 256);
+    const dim3 grid(unsigned(xcd_grid(v.n_tiles)));
+    if (v.n > 0) k_zero_grads<<<dim3(gz, 1), 256, 0, s>>>(nullptr, v);
+    switch (prec) {
+        case GSB_FP32_PLAIN: k_blend_bwd_rec<Mode::Plain><<<grid, kBlock, 0, s>>>(v); break;
+        case GSB_FP16_GEMM: k_blend_bwd_rec<Mode::F16><<<grid, kBlock, 0, s>>>(v); break;
+        default: k_blend_bwd_rec<Mode::BF16><<<grid, kBlock, 0, s>>>(v); break;
+    }
+    if (v.n > 0) k_bwd_finish<<<dim3(gz, 1), 256, 0, s>>>(nullptr, v);
+    return check_launch("blend_backward_packed");
 }
 
 // ------------------------------------------------------------------------------- plans

@@ -282,6 +282,64 @@ gsb_status gsb_blend_backward(int32_t W, int32_t H, const uint32_t *ranges,
     return blend_backward(v, prec, kDefaultBatchBwd, false, static_cast<hipStream_t>(stream));
 }
 
+gsb_status gsb_pack_gaussians(const float *means2d, const float *conics, const float *opacity,
+                              const float *colors, int64_t n, float *records, void *stream) {
+    g_err[0] = '\0';
+    GSB_REQUIRE(n >= 0 && n <= int64_t(0xffffffffll), "n = %lld out of range", (long long)n);
+    GSB_REQUIRE(n == 0 || (means2d && conics && opacity && colors && records),
+                "array pointers must be non-null");
+    GSB_REQUIRE(aligned(means2d, 8) && aligned(records, 16),
+                "means2d must be 8-byte and records 16-byte aligned");
+    GSB_TRY(check_device());
+    return pack_gaussians(means2d, conics, opacity, colors, n, records,
+                          static_cast<hipStream_t>(stream));
+}
+
+gsb_status gsb_blend_forward_packed(int32_t W, int32_t H, const uint32_t *ranges,
+                                    const uint32_t *point_list, const float *records, int64_t n,
+                                    const float *bg, gsb_precision prec, float *image,
+                                    float *final_T, int32_t *last_contrib, void *stream) {
+    g_err[0] = '\0';
+    GSB_REQUIRE(aligned(records, 16), "records must be 16-byte aligned");
+    GSB_TRY(check_blend_common(W, H, ranges, point_list, records, records, records, records, n,
+                               bg, prec));
+    GSB_REQUIRE(image && final_T && last_contrib, "output pointers must be non-null");
+    GSB_TRY(check_device());
+    ViewDesc v = make_view(W, H, ranges, point_list, nullptr, nullptr, nullptr, nullptr, n, bg);
+    v.records = reinterpret_cast<const float4 *>(records);
+    v.image = image;
+    v.final_T = final_T;
+    v.last_contrib = last_contrib;
+    return blend_forward_packed(v, prec, static_cast<hipStream_t>(stream));
+}
+
+gsb_status gsb_blend_backward_packed(int32_t W, int32_t H, const uint32_t *ranges,
+                                     const uint32_t *point_list, const float *records, int64_t n,
+                                     const float *bg, gsb_precision prec, const float *final_T,
+                                     const int32_t *last_contrib, const float *dL_dimage,
+                                     float *dL_dmeans2d, float *dL_dconics, float *dL_dopacity,
+                                     float *dL_dcolors, void *stream) {
+    g_err[0] = '\0';
+    GSB_REQUIRE(aligned(records, 16), "records must be 16-byte aligned");
+    GSB_TRY(check_blend_common(W, H, ranges, point_list, records, records, records, records, n,
+                               bg, prec));
+    GSB_REQUIRE(final_T && last_contrib && dL_dimage, "final_T, last_contrib and dL_dimage must be non-null");
+    GSB_REQUIRE(n == 0 || (dL_dmeans2d && dL_dconics && dL_dopacity && dL_dcolors),
+                "gradient pointers must be non-null");
+    GSB_REQUIRE(aligned(dL_dmeans2d, 8), "dL_dmeans2d must be 8-byte aligned");
+    GSB_TRY(check_device());
+    ViewDesc v = make_view(W, H, ranges, point_list, nullptr, nullptr, nullptr, nullptr, n, bg);
+    v.records = reinterpret_cast<const float4 *>(records);
+    v.final_T = const_cast<float *>(final_T);
+    v.last_contrib = const_cast<int32_t *>(last_contrib);
+    v.dL_dimage = dL_dimage;
+    v.dL_dmeans2d = dL_dmeans2d;
+    v.dL_dconics = dL_dconics;
+    v.dL_dopacity = dL_dopacity;
+    v.dL_dcolors = dL_dcolors;
+    return blend_backward_packed(v, prec, static_cast<hipStream_t>(stream));
+}
+
 gsb_status gsb_plan_create(const gsb_view *views, int32_t n_views, gsb_precision prec,
                            const gsb_tuning *tuning, gsb_plan *plan) {
     g_err[0] = '\0';

@@ -115,6 +115,8 @@ struct ViewDesc {
     const uint32_t *point_list;
     int64_t n;
     const float *means2d, *conics, *opacity, *colors;
+    const float4 *records;   // packed attributes (gsb_pack_gaussians), read instead of the four
+                             // arrays above by the record kernels
     float bg[3];
     float pad1;
     float *image, *final_T;
@@ -126,6 +128,13 @@ struct ViewDesc {
 ViewDesc make_view(int32_t W, int32_t H, const uint32_t *ranges, const uint32_t *point_list,
                    const float *means2d, const float *conics, const float *opacity,
                    const float *colors, int64_t n, const float bg[3]);
+// Packed per-Gaussian records: 3 float4 per Gaussian, (x, y, A, B), (C, o, r, g), (b, 0, 0, 0).
+constexpr int kRecordFloats = 12;
+gsb_status pack_gaussians(const float *means2d, const float *conics, const float *opacity,
+                          const float *colors, int64_t n, float *records, hipStream_t s);
+// Single-view blends that read the packed records (v.records) instead of the four arrays.
+gsb_status blend_forward_packed(const ViewDesc &v, gsb_precision prec, hipStream_t s);
+gsb_status blend_backward_packed(const ViewDesc &v, gsb_precision prec, hipStream_t s);
 
 // Launch shape choices (all have defaults).
 struct Tuning {

@@ -36,7 +36,7 @@ def test_library_exports_every_declared_symbol():
 
 
 def test_abi_version():
-    assert _lib.gsb_abi_version() == 5
+    assert _lib.gsb_abi_version() == 6
 
 
 def test_project_validation_before_device():
@@ -186,3 +186,26 @@ def test_bin_mode_validation_before_device():
         _lib.gsb_bin_fill(ok, ok, ok, 100, 32, 32, ok, need2, ok, 50, ok, ok, conics=ok + 2,
                           opacity=ok, mode=_lib.GSB_BIN_VISIBLE)
     assert "aligned" in str(e.value)
+
+
+def test_packed_validation_before_device():
+    ok = 256   # a non-null, 16-byte aligned fake address: validation fails before any use
+    cases = [
+        (lambda: _lib.gsb_pack_gaussians(ok, ok, ok, ok, 10, ok + 8), "16-byte"),
+        (lambda: _lib.gsb_pack_gaussians(ok, ok, ok, 0, 10, ok), "non-null"),
+        (lambda: _lib.gsb_pack_gaussians(ok, ok, ok, ok, -1, ok), "n = -1"),
+        (lambda: _lib.gsb_blend_forward_packed(16, 16, ok, ok, ok + 4, 1, (0, 0, 0), 0, ok, ok,
+                                               ok), "16-byte"),
+        (lambda: _lib.gsb_blend_forward_packed(16, 16, ok, ok, 0, 1, (0, 0, 0), 0, ok, ok, ok),
+         "attribute"),
+        (lambda: _lib.gsb_blend_forward_packed(16, 16, ok, ok, ok, 1, (0, 0, 0), 7, ok, ok, ok),
+         "precision"),
+        (lambda: _lib.gsb_blend_backward_packed(16, 16, ok, ok, ok, 1, (0, 0, 0), 0, ok, ok, 0,
+                                                ok, ok, ok, ok), "dL_dimage"),
+        (lambda: _lib.gsb_blend_backward_packed(16, 16, ok, ok, ok, 1, (0, 0, 0), 0, ok, ok, ok,
+                                                ok + 4, ok, ok, ok), "8-byte"),
+    ]
+    for call, frag in cases:
+        with pytest.raises(_lib.GsbError) as e:
+            call()
+        assert e.value.status == _lib.GSB_ERR_INVALID and frag in str(e.value), str(e.value)

@@ -445,3 +445,35 @@ def test_backward_mfma_reduction(gpu, prec, name, batch_bwd):
         say(f"  mfma reduction {name} {prec} b={batch_bwd} {k}: vs oracle {e:.3e}, "
             f"vs vector reduction {d:.3e}")
         assert e <= bound, (k, e)
+
+
+# ----------------------------------------------------------------------------- packed records
+@pytest.mark.parametrize("prec", PRECS)
+@pytest.mark.parametrize("name", ["C1", "ragged", "lognormal", "clustered"])
+def test_packed_records_same_results(gpu, prec, name):
+    """The blends that read gsb_pack_gaussians' 48-byte records give the image, final T and last
+    contributor of the four-array blends bit for bit, and their gradients up to the order of the
+    FP32 atomic sums; the records hold the attributes unchanged."""
+    s = SCENES[name]
+    W, H = s["width"], s["height"]
+    bg = (0.1, 0.3, 0.2)
+    sd = upload(s, gpu)
+    pl, rg = api.bin_tiles(sd["means2d"], sd["radii"], sd["depths"], W, H)
+    rec = api.pack_gaussians(sd["means2d"], sd["conics"], sd["opacity"], sd["colors"])
+    r = rec.cpu().numpy()
+    assert np.array_equal(r[:, 0:2], s["means2d"]) and np.array_equal(r[:, 2:4], s["conics"][:, :2])
+    assert np.array_equal(r[:, 4], s["conics"][:, 2]) and np.array_equal(r[:, 5], s["opacity"])
+    assert np.array_equal(r[:, 6:9], s["colors"]) and not r[:, 9:].any()
+    g = torch.from_numpy(gsinputs.make_dloss(W, H, 77)).to(gpu)
+    a = api.blend_forward(sd["means2d"], sd["conics"], sd["opacity"], sd["colors"], rg, pl, W, H,
+                          bg, prec)
+    b = api.blend_forward_packed(rec, rg, pl, W, H, bg, prec)
+    for x, y in zip(a, b):
+        assert torch.equal(x, y)
+    ga = api.blend_backward(sd["means2d"], sd["conics"], sd["opacity"], sd["colors"], rg, pl, W, H,
+                            a[1], a[2], g, bg, prec)
+    gb = api.blend_backward_packed(rec, rg, pl, W, H, b[1], b[2], g, bg, prec)
+    torch.cuda.synchronize()
+    for x, y in zip(ga, gb):
+        e = normwise(y.cpu().numpy().astype(np.float64), x.cpu().numpy().astype(np.float64))
+        assert e <= 1e-5, e
