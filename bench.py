@@ -80,6 +80,8 @@ def parse():
                    help="blend from the four attribute arrays instead of packed records")
     p.add_argument("--no-batched", action="store_true",
                    help="skip the 16-view batched measurement")
+    p.add_argument("--no-deterministic", action="store_true",
+                   help="skip the deterministic backward's measurement")
     p.add_argument("--no-visible", action="store_true",
                    help="skip the step with visible-tile binning")
     p.add_argument("--no-pipeline", action="store_true",
@@ -274,6 +276,38 @@ def time_batched(steps: int, warmup: int, dev) -> dict:
            "batched_blend_ms": round(fb_ev, 4), "batched_blend_mpix_s": round(px / fb_ev / 1e3, 2)}
     bv.close()
     return out
+
+
+def time_deterministic(fr: Frame, prec: str, steps: int, warmup: int, head: dict) -> dict:
+    """The deterministic backward on the headline frame (after a step, so binning, records and
+    the forward's outputs are current): its time beside the atomic backward's, whether repeated
+    runs are identical bit for bit, and its normwise distance from the atomic gradients."""
+    img, T, last = fr.fwd_out
+    ws = api.DetWorkspace(fr.n, fr.pairs, device=fr.records.device)
+    outs = [tuple(torch.empty_like(x) for x in fr.bwd_out) for _ in range(2)]
+    run = lambda o: api.blend_backward_deterministic(  # noqa: E731
+        fr.records, fr.ranges, fr.point_list, fr.W, fr.H, T, last, fr.dloss, (0.0, 0.0, 0.0), prec,
+        ws=ws, out=o)
+    for _ in range(warmup):
+        run(outs[0])
+    torch.cuda.synchronize()
+    ms = []
+    for k in range(steps):
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record()
+        run(outs[k % 2])
+        b.record()
+        b.synchronize()
+        ms.append(a.elapsed_time(b))
+    run(outs[1])
+    torch.cuda.synchronize()
+    same = all(torch.equal(x, y) for x, y in zip(outs[0], outs[1]))
+    atomic = [g.double() for g in fr.bwd_out]
+    diff = max(float(torch.linalg.vector_norm(x.double() - y) / torch.linalg.vector_norm(y))
+               for x, y in zip(outs[0], atomic))
+    return {"precision": prec, "bwd_ms_median": round(float(np.median(ms)), 4),
+            "atomic_bwd_ms": round(head["bwd_ms"], 4), "workspace_bytes": ws.nbytes,
+            "bit_identical_across_runs": same, "max_normwise_vs_atomic": float(f"{diff:.3e}")}
 
 
 def time_visible(scene, dev, prec: str, steps: int, warmup: int, head: dict, ref_out) -> dict:
@@ -718,6 +752,11 @@ def main():
         line["speedup_vs_plain_fp32"] = {
             "step": round(results["fp32"]["ms_per_step"] / head["ms_per_step"], 3),
             "blend": round(head["blend_mpix_s"] / results["fp32"]["blend_mpix_s"], 3)}
+    if not args.no_deterministic and fr.packed:
+        fr.step(precs[0])
+        torch.cuda.synchronize()
+        line["deterministic_backward"] = time_deterministic(fr, precs[0], max(5, args.steps // 5),
+                                                            2, head)
     if not args.no_visible:
         line["visible_binning"] = time_visible(fr.scene, dev, precs[0], args.steps, args.warmup,
                                                head, outputs.get(precs[0]))

@@ -52,7 +52,7 @@ typedef int32_t gsb_precision;
 #define GSB_FP16_GEMM 1   /* exponent as an MFMA product, FP16 hi+lo operands, FP32 accumulate */
 #define GSB_BF16_GEMM 2   /* same with BF16 hi+lo operands */
 
-#define GSB_ABI_VERSION 6
+#define GSB_ABI_VERSION 7
 
 /* Version of this interface (GSB_ABI_VERSION of the library that was loaded). */
 int32_t gsb_abi_version(void);
@@ -263,6 +263,30 @@ gsb_status gsb_blend_backward_packed(int32_t W, int32_t H, const uint32_t *range
                                      const int32_t *last_contrib, const float *dL_dimage,
                                      float *dL_dmeans2d, float *dL_dconics, float *dL_dopacity,
                                      float *dL_dcolors, void *stream);
+
+/* ---------------------------------------------------------------------------------------------
+ * Deterministic backward. gsb_blend_backward sums each Gaussian's gradient over the tiles that
+ * list it with FP32 atomics, whose order (and so whose rounding) changes from run to run. This
+ * call computes the same gradient (the product rule of Eq. (volume-render) and Eq. (alpha), as
+ * gsb_blend_backward) with every sum in a fixed order, so that its result is identical bit for bit
+ * on every run with the same inputs: per list entry, the wavefronts' sums over the tile's pixels
+ * are added in wavefront order and stored at the entry's position; the positions are then grouped
+ * by Gaussian with a stable sort and each Gaussian's entries are added in list order.
+ *
+ * pairs:   number of entries of point_list; every range must lie in [0, pairs) (the binning's
+ *          pair count). Entries outside are neither read nor written.
+ * records: the packed attributes (gsb_pack_gaussians).
+ * ws:      device workspace of ws_bytes >= gsb_backward_det_workspace_bytes(n, pairs) bytes,
+ *          256-byte aligned (about 52 bytes per list entry).
+ * Other arguments and the outputs as gsb_blend_backward_packed. Errors: INVALID, UNSUPPORTED, HIP.
+ * ------------------------------------------------------------------------------------------- */
+gsb_status gsb_backward_det_workspace_bytes(int64_t n, int64_t pairs, size_t *bytes);
+
+gsb_status gsb_blend_backward_deterministic(
+    int32_t W, int32_t H, const uint32_t *ranges, const uint32_t *point_list, int64_t pairs,
+    const float *records, int64_t n, const float *bg, gsb_precision prec, const float *final_T,
+    const int32_t *last_contrib, const float *dL_dimage, void *ws, size_t ws_bytes,
+    float *dL_dmeans2d, float *dL_dconics, float *dL_dopacity, float *dL_dcolors, void *stream);
 
 /* ---------------------------------------------------------------------------------------------
  * Batched views: many images (views) of uneven size, each with its own Gaussians and binning,

@@ -35,7 +35,9 @@ GSB_REDUCE_MFMA = 1
 # every function declared in include/gsblend.h
 EXPORTS = ("gsb_abi_version", "gsb_last_error", "gsb_project", "gsb_bin_workspace_bytes",
            "gsb_bin_count", "gsb_bin_fill", "gsb_bin_noalloc", "gsb_pack_gaussians",
-           "gsb_blend_forward_packed", "gsb_blend_backward_packed", "gsb_blend_forward", "gsb_blend_backward", "gsb_plan_create",
+           "gsb_blend_forward_packed", "gsb_blend_backward_packed",
+           "gsb_backward_det_workspace_bytes", "gsb_blend_backward_deterministic",
+           "gsb_blend_forward", "gsb_blend_backward", "gsb_plan_create",
            "gsb_plan_destroy", "gsb_blend_batched_forward", "gsb_blend_batched_backward")
 
 
@@ -99,6 +101,9 @@ def load() -> ctypes.CDLL:
     lib.gsb_blend_forward_packed.argtypes = [i32, i32, P, P, P, i64, P, i32, P, P, P, P]
     lib.gsb_blend_backward_packed.argtypes = [i32, i32, P, P, P, i64, P, i32, P, P, P, P, P, P,
                                               P, P]
+    lib.gsb_backward_det_workspace_bytes.argtypes = [i64, i64, ctypes.POINTER(sz)]
+    lib.gsb_blend_backward_deterministic.argtypes = [i32, i32, P, P, i64, P, i64, P, i32, P, P,
+                                                     P, P, sz, P, P, P, P, P]
     lib.gsb_blend_forward.argtypes = [i32, i32, P, P, P, P, P, P, i64, P, i32, P, P, P, P]
     lib.gsb_blend_backward.argtypes = [i32, i32, P, P, P, P, P, P, i64, P, i32, P, P, P, P, P,
                                        P, P, P]
@@ -194,6 +199,22 @@ def gsb_blend_backward_packed(W: int, H: int, ranges: int, point_list: int, reco
     _check(load().gsb_blend_backward_packed(W, H, ranges, point_list, records, n, _bg(bg), prec,
                                             final_T, last_contrib, dL_dimage, dL_dmeans2d,
                                             dL_dconics, dL_dopacity, dL_dcolors, stream))
+
+
+def gsb_backward_det_workspace_bytes(n: int, pairs: int) -> int:
+    out = ctypes.c_size_t(0)
+    _check(load().gsb_backward_det_workspace_bytes(n, pairs, ctypes.byref(out)))
+    return int(out.value)
+
+
+def gsb_blend_backward_deterministic(W: int, H: int, ranges: int, point_list: int, pairs: int,
+                                     records: int, n: int, bg, prec: int, final_T: int,
+                                     last_contrib: int, dL_dimage: int, ws: int, ws_bytes: int,
+                                     dL_dmeans2d: int, dL_dconics: int, dL_dopacity: int,
+                                     dL_dcolors: int, stream: int = 0) -> None:
+    _check(load().gsb_blend_backward_deterministic(
+        W, H, ranges, point_list, pairs, records, n, _bg(bg), prec, final_T, last_contrib,
+        dL_dimage, ws, ws_bytes, dL_dmeans2d, dL_dconics, dL_dopacity, dL_dcolors, stream))
 
 
 def gsb_blend_forward(W: int, H: int, ranges: int, point_list: int, means2d: int, conics: int,

@@ -254,6 +254,45 @@ def blend_backward_packed(records, ranges, point_list, W: int, H: int, final_T, 
     return dm, dc, do, dcol
 
 
+class DetWorkspace:
+    """Device workspace of gsb_blend_backward_deterministic for n Gaussians and `pairs` list
+    entries (a uint8 tensor, 256-byte aligned by the caching allocator)."""
+
+    def __init__(self, n: int, pairs: int, device=None):
+        self.n, self.pairs = n, pairs
+        self.nbytes = _lib.gsb_backward_det_workspace_bytes(n, pairs)
+        self.buf = torch.empty(max(self.nbytes, 1), dtype=torch.uint8, device=device)
+
+    def ptr(self) -> int:
+        p = self.buf.data_ptr()
+        assert p % 256 == 0
+        return p
+
+
+def blend_backward_deterministic(records, ranges, point_list, W: int, H: int, final_T,
+                                 last_contrib, dL_dimage, bg=(0.0, 0.0, 0.0), prec="fp16",
+                                 ws: DetWorkspace = None, stream=None, out=None):
+    """As blend_backward_packed, with every gradient sum in a fixed order: the result is
+    identical bit for bit from run to run. ``ws`` is allocated when not given."""
+    n = records.shape[0]
+    pairs = point_list.numel()
+    _req(records, torch.float32, "records")
+    dev = records.device
+    if ws is None or ws.n < n or ws.pairs < pairs:
+        ws = DetWorkspace(n, pairs, device=dev)
+    dm, dc, do, dcol = out if out is not None else (
+        torch.empty((n, 2), dtype=torch.float32, device=dev),
+        torch.empty((n, 3), dtype=torch.float32, device=dev),
+        torch.empty((n,), dtype=torch.float32, device=dev),
+        torch.empty((n, 3), dtype=torch.float32, device=dev))
+    _lib.gsb_blend_backward_deterministic(
+        W, H, ranges.data_ptr(), point_list.data_ptr(), pairs, records.data_ptr(), n, bg,
+        prec_code(prec), final_T.data_ptr(), last_contrib.data_ptr(), dL_dimage.data_ptr(),
+        ws.ptr(), ws.nbytes, dm.data_ptr(), dc.data_ptr(), do.data_ptr(), dcol.data_ptr(),
+        _stream(stream))
+    return dm, dc, do, dcol
+
+
 class BatchedViews:
     """Many views blended by one persistent launch per direction (gsb_plan_*).
 

@@ -936,9 +936,9 @@ __global__ __launch_bounds__(256) void k_bin_init(uint32_t *ranges, int64_t m, S
 
 // Tile boundaries in the sorted tile ids: four consecutive pairs per thread (one 16-byte load and
 // the two neighbours outside it). `tiles` is 16-byte aligned.
-__global__ __launch_bounds__(256) void k_ranges(const uint32_t *tiles, const BinHeader *hdr,
+__global__ __launch_bounds__(256) void k_ranges(const uint32_t *tiles, const unsigned long long *count,
                                                 uint32_t *ranges) {
-    const int64_t P = int64_t(hdr->pairs);
+    const int64_t P = int64_t(*count);
     const int64_t i0 = 4 * (int64_t(blockIdx.x) * blockDim.x + threadIdx.x);
     if (i0 >= P) return;
     uint32_t t[6];                       // tiles[i0 - 1 .. i0 + 4]; outside [0, P): no tile
@@ -1038,8 +1038,33 @@ gsb_status bin_fill(const float *means2d, const int32_t *radii, const float *con
                status_dev, s);
     const uint32_t *tiles_sorted = (tp % 2 == 0) ? tka : tkb;
     if (cap > 0)
-        k_ranges<<<dim3(unsigned((cap + 1023) / 1024)), 256, 0, s>>>(tiles_sorted, hdr, ranges);
+        k_ranges<<<dim3(unsigned((cap + 1023) / 1024)), 256, 0, s>>>(tiles_sorted, &hdr->pairs,
+                                                                      ranges);
     return check_launch("bin_fill");
+}
+
+// ------------------------------------------------------------------------------- pair sort
+// The binning's stable pair sort and range extraction, for other steps that group (key, value)
+// pairs by key (the deterministic backward groups list positions by Gaussian).
+size_t pair_sort_scratch_bytes(int64_t cap) {
+    return align256(sizeof(uint32_t) * kRadix * size_t(sort_blocks(cap > 0 ? cap : 1))) +
+           align256(sizeof(unsigned long long) * kScanMaxBlocks);
+}
+
+int pair_sort(uint32_t *ka, uint32_t *kb, uint32_t *va, uint32_t *vb,
+              const unsigned long long *count, int64_t cap, int bits, void *scratch,
+              hipStream_t s) {
+    uint32_t *hist = static_cast<uint32_t *>(scratch);
+    uint32_t *partial = reinterpret_cast<uint32_t *>(
+        static_cast<char *>(scratch) +
+        align256(sizeof(uint32_t) * kRadix * size_t(sort_blocks(cap > 0 ? cap : 1))));
+    return sort_tiles(ka, kb, va, vb, count, cap, bits, hist, partial, nullptr, s);
+}
+
+void key_ranges(const uint32_t *sorted_keys, const unsigned long long *count, int64_t cap,
+                uint32_t *ranges, hipStream_t s) {
+    if (cap > 0)
+        k_ranges<<<dim3(unsigned((cap + 1023) / 1024)), 256, 0, s>>>(sorted_keys, count, ranges);
 }
 
 // ------------------------------------------------------------------------------- no-alloc binning

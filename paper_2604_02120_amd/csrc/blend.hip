@@ -138,6 +138,13 @@ struct BwdAcc {
     __device__ float *slot(int ab, int t) { return v[ab] + t * kGrad; }
 };
 
+// Deterministic backward: each wavefront stores its per-batch sums in a slice of its own (no
+// atomics); the flush adds the four slices in a fixed order. Two buffers, as BwdAcc.
+template <int NB>
+struct BwdAccDet {
+    float v[2][kBlock / 64][NB * kGrad];
+};
+
 // Backward reduction on the matrix cores: each wavefront's dL/dpower values of 8 Gaussians for its
 // 64 pixels (one word per (Gaussian, pixel): FP16 hi in the low half, FP16 lo x 2^12 in the high
 // half), transposed through LDS into the operand of v_mfma_f32_16x16x32_f16. Rows padded to 68
@@ -533,7 +540,9 @@ struct BwdState {
 // gradients.
 // kRanged = false: the caller has checked that the whole group lies before every lane's last
 // contributor, so the skip test alone decides (one compare, whose mask is the ballot).
-template <bool kRanged>
+// kDet: `acc` points into the wavefront's own slice of the batch's sums, which this Gaussian's
+// totals are stored into (no other wavefront writes there), so no atomic and no flag.
+template <bool kRanged, bool kDet = false>
 __device__ inline void reverse_pair(float q, bool in_range, const float4 *ga, const float4 *gb,
                                     int u, const Lane &L, BwdState &st, float *acc,
                                     uint32_t *hit) {
@@ -577,10 +586,15 @@ __device__ inline void reverse_pair(float q, bool in_range, const float4 *ga, co
     wave_sum9(s, L.l, rab, rc);
     if ((L.l & 7) == 0) {
         // acc is this lane's word of the Gaussian's sums (see sum_word); lane 0's is word 0
-        atomicAdd(acc, rab);
-        if (L.l == 0) {
-            atomicAdd(acc + 8, rc);
-            *hit = 1u;
+        if constexpr (kDet) {
+            *acc = rab;
+            if (L.l == 0) acc[8] = rc;
+        } else {
+            atomicAdd(acc, rab);
+            if (L.l == 0) {
+                atomicAdd(acc + 8, rc);
+                *hit = 1u;
+            }
         }
     }
 }
@@ -740,10 +754,15 @@ __device__ inline void mm_reduce(uint32_t (*rows)[kDgStride], const h8 (&B)[2], 
 // Backward of one tile of one view.
 // kMM: the five geometric sums are formed on the matrix cores (mm_reduce) instead of being
 // reduced on the vector ALUs with the other four; `mm` is then the block's transposition tiles.
-template <Mode M, int NB, bool kMM, bool kPacked = false>
+// kDet: the batch sums go to the wavefronts' own slices (`det`) instead of `acc_`, and the flush
+// writes each list position's nine sums to v.det_partial in place of the global atomics (every
+// position of the tile's list is written, those past the last contributor with zeros).
+template <Mode M, int NB, bool kMM, bool kPacked = false, bool kDet = false>
 __device__ inline void bwd_tile(const ViewDesc &v, int64_t tile, Stage<M, NB> &S, StageBwd<NB> &SB,
-                                BwdAcc<NB> &s_acc, int &s_maxlast, BwdMM *mm) {
+                                BwdAcc<NB> *acc_, int &s_maxlast, BwdMM *mm,
+                                BwdAccDet<NB> *det = nullptr) {
     static_assert(NB % kGroup == 0 && NB <= kBlock, "batch must be whole groups, <= block");
+    static_assert(!(kMM && kDet), "the deterministic backward reduces on the vector ALUs");
     constexpr int kGroups = NB / kGroup;
     const uint32_t *plist = v.point_list;
     const uint32_t n = uint32_t(v.n);
@@ -786,6 +805,14 @@ __device__ inline void bwd_tile(const ViewDesc &v, int64_t tile, Stage<M, NB> &S
     const int64_t len = s_maxlast < int64_t(rg.y) - int64_t(rg.x) ? s_maxlast
                                                                    : int64_t(rg.y) - int64_t(rg.x);
     const int nb = int((len + NB - 1) / NB);
+    if constexpr (kDet) {
+        // list positions [len, end) are never visited: their sums are zero (positions at or
+        // past det_pairs, which an inconsistent range could name, are never written)
+        const int64_t end = int64_t(rg.y) < v.det_pairs ? int64_t(rg.y) : v.det_pairs;
+        const int64_t tail = (end - start - len) * kGrad;
+        float *dst = v.det_partial + (start + len) * kGrad;
+        for (int64_t j = L.t; j < tail; j += kBlock) dst[j] = 0.f;
+    }
     if (nb == 0) return;
 
     // Memory operations of a batch are issued before its compute: the attribute loads of the next
@@ -804,7 +831,32 @@ __device__ inline void bwd_tile(const ViewDesc &v, int64_t tile, Stage<M, NB> &S
     // no lane is spent on the slots without a sum (over half of a 3-sigma list's). Each item is
     // zeroed by the lane that reads it, and each flag by the lane that lists it, ready for batch
     // bb - 2, which reuses the buffers after the next barrier.
+    // Deterministic form: item j of the batch (slot j / 9, sum j % 9) is the four wavefronts'
+    // values added in wavefront order, stored at list position start + bb NB + slot (consecutive
+    // threads, consecutive words) and zeroed in the slices.
+    const auto flush_det = [&](int bb) {
+        const int64_t base = int64_t(bb) * NB;
+        float *dst = v.det_partial + (start + base) * kGrad;
+        int64_t last = len - base < NB ? len - base : NB;          // slots of this batch
+        if (start + base + last > v.det_pairs) last = v.det_pairs - start - base;
+        const int64_t items = last * kGrad;
+        for (int j = L.t; j < NB * kGrad; j += kBlock) {
+            float sum = 0.f;
+#pragma unroll
+            for (int w = 0; w < kBlock / 64; ++w) {
+                float *p = det->v[bb & 1][w] + j;
+                sum += *p;
+                *p = 0.f;
+            }
+            if (j < items) dst[j] = sum;
+        }
+    };
     const auto flush = [&](int bb) {     // batch bb's sums, accumulator buffer bb & 1
+        if constexpr (kDet) {
+            flush_det(bb);
+            return;
+        }
+        BwdAcc<NB> &s_acc = *acc_;
         constexpr int kPer = NB / (kBlock / 64);   // slots per wavefront, at most 64
         float *acc = s_acc.v[bb & 1];
         uint32_t *hit = s_acc.hit[bb & 1];
@@ -840,13 +892,23 @@ __device__ inline void bwd_tile(const ViewDesc &v, int64_t tile, Stage<M, NB> &S
     GRaw nxt = src.fetch(entry(nb - 1).id(), n);
     Entry ent = entry(nb - 2);
     // both accumulator buffers and their flags start at zero
-    for (int e = L.t; e < NB * kGrad; e += kBlock) {
-        s_acc.v[0][e] = 0.f;
-        s_acc.v[1][e] = 0.f;
-    }
-    if (L.t < NB) {
-        s_acc.hit[0][L.t] = 0u;
-        s_acc.hit[1][L.t] = 0u;
+    if constexpr (kDet) {
+        for (int e = L.t; e < NB * kGrad; e += kBlock) {
+#pragma unroll
+            for (int w = 0; w < kBlock / 64; ++w) {
+                det->v[0][w][e] = 0.f;
+                det->v[1][w][e] = 0.f;
+            }
+        }
+    } else {
+        for (int e = L.t; e < NB * kGrad; e += kBlock) {
+            acc_->v[0][e] = 0.f;
+            acc_->v[1][e] = 0.f;
+        }
+        if (L.t < NB) {
+            acc_->hit[0][L.t] = 0u;
+            acc_->hit[1][L.t] = 0u;
+        }
     }
     for (int b = nb - 1; b >= 0; --b) {
         const int buf = b & 1;
@@ -867,9 +929,11 @@ __device__ inline void bwd_tile(const ViewDesc &v, int64_t tile, Stage<M, NB> &S
             if (__ballot(st.last > base + g * kGroup) == 0) continue;
             const float4 *ga = &S.attr[buf][g * kGroup];   // the group's staged values
             const float4 *gb = &SB.bwd[buf][g * kGroup];
-            float *accw = s_acc.slot(buf, g * kGroup);          // the group's sums, Gaussian 0
+            // the group's sums, Gaussian 0 (deterministic: this wavefront's slice)
+            float *accw = kDet ? det->v[buf][L.w] + g * kGroup * kGrad
+                               : acc_->slot(buf, g * kGroup);
             float *acc = accw + (kMM ? 0 : word);   // this lane's word (VALU reduction)
-            uint32_t *hit = &s_acc.hit[buf][g * kGroup];
+            uint32_t *hit = kDet ? nullptr : &acc_->hit[buf][g * kGroup];
             const int rel = st.last - (base + g * kGroup);   // positions < last are in range
             // the whole group is in range for every lane (the common case once past the lanes'
             // last contributors; never for a partial tile, whose outside lanes have last = 0)
@@ -908,12 +972,13 @@ __device__ inline void bwd_tile(const ViewDesc &v, int64_t tile, Stage<M, NB> &S
             } else if (whole) {
 #pragma unroll
                 for (int u = kGroup - 1; u >= 0; --u)
-                    reverse_pair<false>(q_of(u), true, ga, gb, u, L, st, acc + u * kGrad, hit + u);
+                    reverse_pair<false, kDet>(q_of(u), true, ga, gb, u, L, st, acc + u * kGrad,
+                                              hit + u);
             } else {
 #pragma unroll
                 for (int u = kGroup - 1; u >= 0; --u)
-                    reverse_pair<true>(q_of(u), u < rel, ga, gb, u, L, st, acc + u * kGrad,
-                                       hit + u);
+                    reverse_pair<true, kDet>(q_of(u), u < rel, ga, gb, u, L, st, acc + u * kGrad,
+                                             hit + u);
             }
         }
         // Buffers: the next iteration stages into the other stage buffer. The accumulator buffer
@@ -972,7 +1037,7 @@ void k_blend_bwd(ViewDesc v) {
     __shared__ int s_maxlast;
     const int64_t tile = xcd_tile(blockIdx.x, v.n_tiles, v.gx);
     if (tile >= v.n_tiles) return;
-    bwd_tile<M, NB, kMM>(v, tile, S, SB, s_acc, s_maxlast, mm_ptr<kMM>(s_mm));
+    bwd_tile<M, NB, kMM>(v, tile, S, SB, &s_acc, s_maxlast, mm_ptr<kMM>(s_mm));
 }
 
 // Single view, packed records (gsb_pack_gaussians): the default launch shape (LDS batches of 128,
@@ -995,7 +1060,74 @@ void k_blend_bwd_rec(ViewDesc v) {
     __shared__ int s_maxlast;
     const int64_t tile = xcd_tile(blockIdx.x, v.n_tiles, v.gx);
     if (tile >= v.n_tiles) return;
-    bwd_tile<M, 128, false, true>(v, tile, S, SB, s_acc, s_maxlast, nullptr);
+    bwd_tile<M, 128, false, true>(v, tile, S, SB, &s_acc, s_maxlast, nullptr);
+}
+
+// Deterministic backward, one tile per block: LDS batches of 64 (the four wavefront slices of the
+// batch sums take four times the LDS of the shared accumulator), records as attributes.
+constexpr int kDetBatch = 64;
+template <Mode M> constexpr size_t lds_bwd_det() {
+    return sizeof(Stage<M, kDetBatch>) + sizeof(StageBwd<kDetBatch>) +
+           sizeof(BwdAccDet<kDetBatch>) + 64;
+}
+template <Mode M>
+__global__ __launch_bounds__(kBlock, fit_waves(waves_bwd_tile<M, false>(), lds_bwd_det<M>()))
+void k_blend_bwd_det(ViewDesc v) {
+    __shared__ Stage<M, kDetBatch> S;
+    __shared__ StageBwd<kDetBatch> SB;
+    __shared__ BwdAccDet<kDetBatch> s_det;
+    __shared__ int s_maxlast;
+    const int64_t tile = xcd_tile(blockIdx.x, v.n_tiles, v.gx);
+    if (tile >= v.n_tiles) return;
+    bwd_tile<M, kDetBatch, false, true, true>(v, tile, S, SB, nullptr, s_maxlast, nullptr, &s_det);
+}
+
+// Grouping of the list positions by Gaussian: keys = the list's Gaussian indices, values = the
+// positions; the count for the sort and empty per-Gaussian ranges.
+__global__ __launch_bounds__(256) void k_det_init(const uint32_t *plist, int64_t pairs,
+                                                  uint32_t *keys, uint32_t *vals,
+                                                  unsigned long long *count, uint32_t *seg,
+                                                  int64_t n) {
+    const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i < pairs) {
+        // an index outside [0, n) (inconsistent input) is grouped with the last Gaussian: the
+        // backward stages such an entry inert, so its sums are zero
+        const uint32_t g = plist[i];
+        keys[i] = g < uint64_t(n) ? g : uint32_t(n - 1);
+        vals[i] = uint32_t(i);
+    }
+    if (i < 2 * n) seg[i] = 0u;
+    if (i == 0) *count = (unsigned long long)pairs;
+}
+
+// Per Gaussian g: the nine sums of its list positions, added in increasing position order (the
+// order the stable sort left them in), then turned into the gradients as k_bwd_finish does.
+__global__ __launch_bounds__(256) void k_det_gather(const float4 *rec, const float *partial,
+                                                    const uint32_t *pos, const uint32_t *seg,
+                                                    int64_t n, float *dmeans, float *dconics,
+                                                    float *dopac, float *dcolors) {
+    const int64_t g = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (g >= n) return;
+    const uint32_t a = seg[2 * g], b = seg[2 * g + 1];
+    float sum[kGrad];
+#pragma unroll
+    for (int k = 0; k < kGrad; ++k) sum[k] = 0.f;
+    for (uint32_t j = a; j < b; ++j) {
+        const float *p = partial + int64_t(pos[j]) * kGrad;
+#pragma unroll
+        for (int k = 0; k < kGrad; ++k) sum[k] += p[k];
+    }
+    const float4 r0 = rec[3 * g], r1 = rec[3 * g + 1];
+    const float A = r0.z, B = r0.w, C = r1.x;
+    dconics[3 * g] = -0.5f * sum[0];
+    dconics[3 * g + 1] = -sum[1];
+    dconics[3 * g + 2] = -0.5f * sum[2];
+    dmeans[2 * g] = -(A * sum[3] + B * sum[4]);
+    dmeans[2 * g + 1] = -(B * sum[3] + C * sum[4]);
+    dopac[g] = sum[5];
+    dcolors[3 * g] = sum[6];
+    dcolors[3 * g + 1] = sum[7];
+    dcolors[3 * g + 2] = sum[8];
 }
 
 // One record per Gaussian: (x, y, A, B), (C, o, r, g), (b, 0, 0, 0). Consecutive threads write
@@ -1117,7 +1249,7 @@ void k_blend_bwd_batched(Queues Q) {
         __syncthreads();
         if (view < 0) break;
         const ViewDesc vd = Q.views[view];
-        bwd_tile<M, NB, kMM>(vd, tile, S, SB, s_acc, s_maxlast, mm_ptr<kMM>(s_mm));
+        bwd_tile<M, NB, kMM>(vd, tile, S, SB, &s_acc, s_maxlast, mm_ptr<kMM>(s_mm));
         __syncthreads();
     }
 }
@@ -1165,7 +1297,7 @@ void k_blend_bwd_grid(Queues Q) {
     int64_t tile;
     if (!grid_item(Q, blockIdx.x, view, tile)) return;
     const ViewDesc vd = Q.views[view];
-    bwd_tile<M, NB, kMM>(vd, tile, S, SB, s_acc, s_maxlast, mm_ptr<kMM>(s_mm));
+    bwd_tile<M, NB, kMM>(vd, tile, S, SB, &s_acc, s_maxlast, mm_ptr<kMM>(s_mm));
 }
 
 // Raw sums -> gradients of the stored scalars: d/dA = -S_xx/2, d/dB = -S_xy, d/dC = -S_yy/2,
@@ -1326,6 +1458,75 @@ gsb_status blend_backward_packed(const ViewDesc &v, gsb_precision prec, hipStrea
     }
     if (v.n > 0) k_bwd_finish<<<dim3(gz, 1), 256, 0, s>>>(nullptr, v);
     return check_launch("blend_backward_packed");
+}
+
+// Deterministic-backward workspace: per list position its nine sums, the (Gaussian, position)
+// pairs in two buffers each for the sort, the sort's scratch, the pair count and the per-Gaussian
+// ranges of the sorted positions.
+namespace {
+struct DetLayout {
+    size_t partial, ka, kb, va, vb, count, seg, scratch, end;
+};
+size_t al256(size_t b) { return (b + 255) & ~size_t(255); }
+DetLayout det_layout(int64_t n, int64_t pairs) {
+    const size_t P = size_t(pairs > 0 ? pairs : 1), N = size_t(n > 0 ? n : 1);
+    DetLayout L;
+    size_t o = 0;
+    L.partial = o; o += al256(sizeof(float) * kGrad * P);
+    L.ka = o;      o += al256(sizeof(uint32_t) * P);
+    L.kb = o;      o += al256(sizeof(uint32_t) * P);
+    L.va = o;      o += al256(sizeof(uint32_t) * P);
+    L.vb = o;      o += al256(sizeof(uint32_t) * P);
+    L.count = o;   o += al256(sizeof(unsigned long long));
+    L.seg = o;     o += al256(sizeof(uint32_t) * 2 * N);
+    L.scratch = o; o += al256(pair_sort_scratch_bytes(pairs));
+    L.end = o;
+    return L;
+}
+int bits_for(int64_t n) {
+    int b = 1;
+    while (b < 32 && (int64_t(1) << b) < n) ++b;
+    return b;
+}
+}  // namespace
+
+size_t backward_det_workspace_bytes(int64_t n, int64_t pairs) { return det_layout(n, pairs).end; }
+
+gsb_status blend_backward_det(const ViewDesc &v0, gsb_precision prec, int64_t pairs, void *ws,
+                              hipStream_t s) {
+    const DetLayout D = det_layout(v0.n, pairs);
+    char *w = static_cast<char *>(ws);
+    ViewDesc v = v0;
+    v.det_partial = reinterpret_cast<float *>(w + D.partial);
+    v.det_pairs = pairs;
+    uint32_t *ka = reinterpret_cast<uint32_t *>(w + D.ka), *kb = reinterpret_cast<uint32_t *>(w + D.kb);
+    uint32_t *va = reinterpret_cast<uint32_t *>(w + D.va), *vb = reinterpret_cast<uint32_t *>(w + D.vb);
+    auto *count = reinterpret_cast<unsigned long long *>(w + D.count);
+    uint32_t *seg = reinterpret_cast<uint32_t *>(w + D.seg);
+    const int64_t m = std::max(pairs, 2 * v.n);
+    if (m > 0)
+        k_det_init<<<dim3(unsigned((m + 255) / 256)), 256, 0, s>>>(v.point_list, pairs, ka, va,
+                                                                    count, seg, v.n);
+    const dim3 grid(unsigned(xcd_grid(v.n_tiles)));
+    switch (prec) {
+        case GSB_FP32_PLAIN: k_blend_bwd_det<Mode::Plain><<<grid, kBlock, 0, s>>>(v); break;
+        case GSB_FP16_GEMM: k_blend_bwd_det<Mode::F16><<<grid, kBlock, 0, s>>>(v); break;
+        case GSB_BF16_GEMM: k_blend_bwd_det<Mode::BF16><<<grid, kBlock, 0, s>>>(v); break;
+        default: return fail(GSB_ERR_INVALID, "unknown precision %d", int(prec));
+    }
+    if (pairs > 0 && v.n > 0) {
+        const int passes = pair_sort(ka, kb, va, vb, count, pairs, bits_for(v.n), w + D.scratch, s);
+        const uint32_t *skeys = passes % 2 ? kb : ka;
+        const uint32_t *spos = passes % 2 ? vb : va;
+        key_ranges(skeys, count, pairs, seg, s);
+        if (v.n > 0)
+            k_det_gather<<<dim3(unsigned((v.n + 255) / 256)), 256, 0, s>>>(
+                v.records, v.det_partial, spos, seg, v.n, v.dL_dmeans2d, v.dL_dconics,
+                v.dL_dopacity, v.dL_dcolors);
+    } else if (v.n > 0) {
+        k_zero_grads<<<dim3(unsigned((v.n + 255) / 256), 1), 256, 0, s>>>(nullptr, v);
+    }
+    return check_launch("blend_backward_deterministic");
 }
 
 // ------------------------------------------------------------------------------- plans

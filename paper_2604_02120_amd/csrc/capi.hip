@@ -340,6 +340,46 @@ gsb_status gsb_blend_backward_packed(int32_t W, int32_t H, const uint32_t *range
     return blend_backward_packed(v, prec, static_cast<hipStream_t>(stream));
 }
 
+gsb_status gsb_backward_det_workspace_bytes(int64_t n, int64_t pairs, size_t *bytes) {
+    g_err[0] = '\0';
+    GSB_REQUIRE(bytes != nullptr, "bytes must be non-null");
+    GSB_REQUIRE(n >= 0 && n <= int64_t(0xffffffffll), "n = %lld out of range", (long long)n);
+    GSB_REQUIRE(pairs >= 0 && pairs <= bin_max_pairs() && pairs <= int64_t(0x7fffffff),
+                "pairs = %lld outside [0, %lld]", (long long)pairs,
+                (long long)(bin_max_pairs() < 0x7fffffff ? bin_max_pairs() : 0x7fffffff));
+    *bytes = backward_det_workspace_bytes(n, pairs);
+    return GSB_OK;
+}
+
+gsb_status gsb_blend_backward_deterministic(
+    int32_t W, int32_t H, const uint32_t *ranges, const uint32_t *point_list, int64_t pairs,
+    const float *records, int64_t n, const float *bg, gsb_precision prec, const float *final_T,
+    const int32_t *last_contrib, const float *dL_dimage, void *ws, size_t ws_bytes,
+    float *dL_dmeans2d, float *dL_dconics, float *dL_dopacity, float *dL_dcolors, void *stream) {
+    size_t need = 0;
+    GSB_TRY(gsb_backward_det_workspace_bytes(n, pairs, &need));
+    GSB_REQUIRE(aligned(records, 16), "records must be 16-byte aligned");
+    GSB_TRY(check_blend_common(W, H, ranges, point_list, records, records, records, records, n,
+                               bg, prec));
+    GSB_REQUIRE(final_T && last_contrib && dL_dimage, "final_T, last_contrib and dL_dimage must be non-null");
+    GSB_REQUIRE(n == 0 || (dL_dmeans2d && dL_dconics && dL_dopacity && dL_dcolors),
+                "gradient pointers must be non-null");
+    GSB_REQUIRE(aligned(dL_dmeans2d, 8), "dL_dmeans2d must be 8-byte aligned");
+    GSB_REQUIRE(ws != nullptr && aligned(ws, 256), "workspace must be non-null and 256-byte aligned");
+    GSB_REQUIRE(ws_bytes >= need, "workspace of %zu bytes is smaller than the %zu needed", ws_bytes, need);
+    GSB_TRY(check_device());
+    ViewDesc v = make_view(W, H, ranges, point_list, nullptr, nullptr, nullptr, nullptr, n, bg);
+    v.records = reinterpret_cast<const float4 *>(records);
+    v.final_T = const_cast<float *>(final_T);
+    v.last_contrib = const_cast<int32_t *>(last_contrib);
+    v.dL_dimage = dL_dimage;
+    v.dL_dmeans2d = dL_dmeans2d;
+    v.dL_dconics = dL_dconics;
+    v.dL_dopacity = dL_dopacity;
+    v.dL_dcolors = dL_dcolors;
+    return blend_backward_det(v, prec, pairs, ws, static_cast<hipStream_t>(stream));
+}
+
 gsb_status gsb_plan_create(const gsb_view *views, int32_t n_views, gsb_precision prec,
                            const gsb_tuning *tuning, gsb_plan *plan) {
     g_err[0] = '\0';

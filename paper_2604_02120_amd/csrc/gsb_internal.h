@@ -123,6 +123,8 @@ struct ViewDesc {
     int32_t *last_contrib;
     const float *dL_dimage;
     float *dL_dmeans2d, *dL_dconics, *dL_dopacity, *dL_dcolors;
+    float *det_partial;       // deterministic backward: per list position, its nine sums
+    int64_t det_pairs;        // ... for positions [0, det_pairs)
 };
 
 ViewDesc make_view(int32_t W, int32_t H, const uint32_t *ranges, const uint32_t *point_list,
@@ -135,6 +137,18 @@ gsb_status pack_gaussians(const float *means2d, const float *conics, const float
 // Single-view blends that read the packed records (v.records) instead of the four arrays.
 gsb_status blend_forward_packed(const ViewDesc &v, gsb_precision prec, hipStream_t s);
 gsb_status blend_backward_packed(const ViewDesc &v, gsb_precision prec, hipStream_t s);
+// Deterministic backward (records): workspace size for n Gaussians and `pairs` list entries, and
+// the call (gradients bit-reproducible run to run).
+size_t backward_det_workspace_bytes(int64_t n, int64_t pairs);
+gsb_status blend_backward_det(const ViewDesc &v, gsb_precision prec, int64_t pairs, void *ws,
+                              hipStream_t s);
+// The binning's stable pair sort (bin.hip), for grouping (key, value) pairs by key.
+size_t pair_sort_scratch_bytes(int64_t cap);
+int pair_sort(uint32_t *ka, uint32_t *kb, uint32_t *va, uint32_t *vb,
+              const unsigned long long *count, int64_t cap, int bits, void *scratch,
+              hipStream_t s);
+void key_ranges(const uint32_t *sorted_keys, const unsigned long long *count, int64_t cap,
+                uint32_t *ranges, hipStream_t s);
 
 // Launch shape choices (all have defaults).
 struct Tuning {

@@ -36,7 +36,7 @@ def test_library_exports_every_declared_symbol():
 
 
 def test_abi_version():
-    assert _lib.gsb_abi_version() == 6
+    assert _lib.gsb_abi_version() == 7
 
 
 def test_project_validation_before_device():
@@ -208,4 +208,23 @@ def test_packed_validation_before_device():
     for call, frag in cases:
         with pytest.raises(_lib.GsbError) as e:
             call()
+        assert e.value.status == _lib.GSB_ERR_INVALID and frag in str(e.value), str(e.value)
+
+
+def test_deterministic_validation_before_device():
+    ok = 256
+    assert _lib.gsb_backward_det_workspace_bytes(1000, 100_000) > 100_000 * 36
+    with pytest.raises(_lib.GsbError) as e:
+        _lib.gsb_backward_det_workspace_bytes(10, -1)
+    assert e.value.status == _lib.GSB_ERR_INVALID and "pairs" in str(e.value)
+    need = _lib.gsb_backward_det_workspace_bytes(1, 16)
+
+    def call(ws=ok, ws_bytes=need, rec=ok, pairs=16):
+        _lib.gsb_blend_backward_deterministic(16, 16, ok, ok, pairs, rec, 1, (0, 0, 0), 0, ok, ok,
+                                              ok, ws, ws_bytes, ok, ok, ok, ok)
+    for kwargs, frag in ((dict(ws_bytes=need - 1), "smaller"), (dict(ws=ok + 16), "256-byte"),
+                         (dict(rec=ok + 8), "16-byte"), (dict(ws=0), "non-null"),
+                         (dict(pairs=-2), "pairs")):
+        with pytest.raises(_lib.GsbError) as e:
+            call(**kwargs)
         assert e.value.status == _lib.GSB_ERR_INVALID and frag in str(e.value), str(e.value)

@@ -477,3 +477,43 @@ def test_packed_records_same_results(gpu, prec, name):
     for x, y in zip(ga, gb):
         e = normwise(y.cpu().numpy().astype(np.float64), x.cpu().numpy().astype(np.float64))
         assert e <= 1e-5, e
+
+
+# ----------------------------------------------------------------------------- deterministic backward
+@pytest.mark.parametrize("prec", PRECS)
+@pytest.mark.parametrize("name", ["C1", "ragged", "lognormal", "bigrects", "clustered"])
+def test_deterministic_backward(gpu, prec, name):
+    """The deterministic backward: identical bit for bit on repeated runs (the atomic backward is
+    not), the oracle's gradients at the bounds of the atomic backward, and within 1e-5 (normwise)
+    of the atomic backward's gradients."""
+    s = SCENES[name]
+    W, H = s["width"], s["height"]
+    bg = (0.1, 0.3, 0.2)
+    g = gsinputs.make_dloss(W, H, 77)
+    pl_ref, rg_ref = oracle.bin_tiles(s["means2d"], s["radii"], s["depths"], W, H)
+    ref = oracle.backward(W, H, rg_ref, pl_ref, s["means2d"], s["conics"], s["opacity"],
+                          s["colors"], g, bg)
+    sd = upload(s, gpu)
+    pl, rg = upload_bins(pl_ref, rg_ref, gpu)
+    rec = api.pack_gaussians(sd["means2d"], sd["conics"], sd["opacity"], sd["colors"])
+    img, T, last = api.blend_forward_packed(rec, rg, pl, W, H, bg, prec)
+    gd = torch.from_numpy(g).to(gpu)
+    ws = api.DetWorkspace(rec.shape[0], pl.numel(), device=gpu)
+    runs = []
+    for _ in range(3):
+        out = api.blend_backward_deterministic(rec, rg, pl, W, H, T, last, gd, bg, prec, ws=ws)
+        torch.cuda.synchronize()
+        runs.append([x.clone() for x in out])
+        ws.buf.fill_(0x7f)           # what a call leaves in the workspace must not matter
+    for r in runs[1:]:
+        for x, y in zip(runs[0], r):
+            assert torch.equal(x, y)
+    atomic = api.blend_backward_packed(rec, rg, pl, W, H, T, last, gd, bg, prec)
+    torch.cuda.synchronize()
+    bound = plain_grad_bound(name) if prec == "fp32" else GEMM_GRAD
+    for k, x, y in zip(("dmeans2d", "dconics", "dopacity", "dcolors"), runs[0], atomic):
+        e = normwise(x.cpu().numpy().astype(np.float64), ref[k])
+        d = normwise(x.cpu().numpy().astype(np.float64), y.cpu().numpy().astype(np.float64))
+        say(f"  deterministic {name} {prec} {k}: vs oracle {e:.3e}, vs atomic {d:.3e}")
+        assert e <= bound, (k, e)
+        assert d <= 1e-5, (k, d)
