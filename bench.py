@@ -73,7 +73,7 @@ def parse():
     p.add_argument("--steps", type=int, default=50)
     p.add_argument("--warmup", type=int, default=10)
     p.add_argument("--config", default="C5", choices=["C2", "C3", "C5"])
-    p.add_argument("--precs", default="bf16,fp32,fp16",
+    p.add_argument("--precs", default="bf16,fp32,fp16,fp32_scan",
                    help="comma list; the first is the headline")
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--arrays", action="store_true",
@@ -718,13 +718,15 @@ def main():
     fr.packed = not args.arrays
     counts = json.load(open(COUNTS))[args.config]
     precs = args.precs.split(",")
-    results, outputs = {}, {}
+    results, outputs, scans = {}, {}, {}
     for prec in precs:
         results[prec] = time_path(fr, prec, args.steps, args.warmup)
         if not args.no_cpu_baseline:
             img, T, last = (x.cpu().numpy() for x in fr.fwd_out)
             grads = [g.cpu().numpy().astype(np.float64) for g in fr.bwd_out]
-            outputs[prec] = (img.astype(np.float64), T, last, grads)
+            # a full-scan path is compared with its culled path, not with the oracle
+            (scans if prec.endswith("_scan") else outputs)[prec] = (
+                img.astype(np.float64), T, last, grads)
     head = results[precs[0]]
     line = {
         "metric": METRIC, "value": round(head["blend_mpix_s"], 3), "unit": "Mpix/s", "n_gpus": 1,
@@ -752,6 +754,26 @@ def main():
         line["speedup_vs_plain_fp32"] = {
             "step": round(results["fp32"]["ms_per_step"] / head["ms_per_step"], 3),
             "blend": round(head["blend_mpix_s"] / results["fp32"]["blend_mpix_s"], 3)}
+    if "fp32_scan" in results:
+        # the plain form without reach culling: every staged Gaussian evaluated at every pixel
+        sc = results["fp32_scan"]
+        fs = {"precision": "fp32 with GSB_FULL_SCAN",
+              "blend_mpix_s": round(sc["blend_mpix_s"], 3),
+              "fwd_ms": round(sc["fwd_ms"], 4), "bwd_ms": round(sc["bwd_ms"], 4)}
+        if "fp32" in results:
+            fs["reach_culling_speedup"] = {
+                "fwd": round(sc["fwd_ms"] / results["fp32"]["fwd_ms"], 3),
+                "bwd": round(sc["bwd_ms"] / results["fp32"]["bwd_ms"], 3)}
+        if precs[0] not in ("fp32", "fp32_scan"):
+            fs["gemm_speedup_blend"] = round(head["blend_mpix_s"] / sc["blend_mpix_s"], 3)
+        if "fp32" in outputs and "fp32_scan" in scans:
+            a, b = outputs["fp32"], scans["fp32_scan"]
+            fs["forward_identical_to_culled"] = bool(all(np.array_equal(x, y)
+                                                         for x, y in zip(a[:3], b[:3])))
+            fs["grad_max_normwise_vs_culled"] = float(max(
+                np.linalg.norm(x - y) / max(np.linalg.norm(x), 1e-300)
+                for x, y in zip(a[3], b[3])))
+        line["plain_full_scan"] = fs
     if not args.no_deterministic and fr.packed:
         fr.step(precs[0])
         torch.cuda.synchronize()

@@ -51,8 +51,16 @@ typedef int32_t gsb_precision;
 #define GSB_FP32_PLAIN 0  /* exponent per pixel in FP32 on the vector ALUs (Alg. 1, Eq. (power)) */
 #define GSB_FP16_GEMM 1   /* exponent as an MFMA product, FP16 hi+lo operands, FP32 accumulate */
 #define GSB_BF16_GEMM 2   /* same with BF16 hi+lo operands */
+/* Flag that may be OR'ed into any precision argument below. Without it, the plain form skips,
+ * for each 8x8 quadrant of a tile, the staged Gaussians whose alpha cannot reach 1/255 at any of
+ * its pixels (a conservative ellipse test made once per staged Gaussian, Eq. (power) and the
+ * 1/255 skip of Alg. 1), so that their exponent is never evaluated there; the outputs are the
+ * same bit for bit. GSB_FULL_SCAN evaluates every staged Gaussian at every pixel, the per-pixel
+ * loop of Alg. 1 as written. The GEMM forms always evaluate the whole group (one MFMA product
+ * gives every exponent of 16 Gaussians), so the flag changes nothing for them. */
+#define GSB_FULL_SCAN 0x100
 
-#define GSB_ABI_VERSION 7
+#define GSB_ABI_VERSION 8
 
 /* Version of this interface (GSB_ABI_VERSION of the library that was loaded). */
 int32_t gsb_abi_version(void);

@@ -26,7 +26,11 @@ GSB_BIN_VISIBLE = 1
 GSB_FP32_PLAIN = 0
 GSB_FP16_GEMM = 1
 GSB_BF16_GEMM = 2
-PRECISIONS = {"fp32": GSB_FP32_PLAIN, "fp16": GSB_FP16_GEMM, "bf16": GSB_BF16_GEMM}
+# OR'ed into a precision: evaluate every staged Gaussian at every pixel (no reach culling in the
+# plain form; the GEMM forms always do)
+GSB_FULL_SCAN = 0x100
+PRECISIONS = {"fp32": GSB_FP32_PLAIN, "fp16": GSB_FP16_GEMM, "bf16": GSB_BF16_GEMM,
+              "fp32_scan": GSB_FP32_PLAIN | GSB_FULL_SCAN}
 GSB_LAUNCH_PERSISTENT = 0
 GSB_LAUNCH_GRID = 1
 GSB_REDUCE_VALU = 0

@@ -112,6 +112,7 @@ struct Stage<Mode::Plain, NB> {  // plain form
     float4 geo[2][NB];         // (x, y, A, B)
     float2 geo2[2][NB];        // (C, log2 o)
     float4 attr[2][NB];        // (log2 o, r, g, b)
+    uint16_t reach[2][4][NB / kGroup];   // reach masks per quadrant and group (stage_reach)
 };
 
 template <int NB>
@@ -242,10 +243,67 @@ template <> struct Attrs<true> {
     }
 };
 
-// Writes one Gaussian into slot `slot` of buffer `buf`. (xc, yc) is the tile centre.
+// Reach culling (plain form). A staged Gaussian cannot reach some quadrants of the tile:
+// bit w of its mask is clear when no pixel of quadrant (w & 1, w >> 1) can have q >= kQCull, i.e.
+// when the pair is skipped (alpha < 1/255) at every pixel of that quadrant. With Q the conic form
+// of Eq. (power), q >= kQCull means Q(d) <= t, t = 2 (log2 o - kQCull) / log2 e, and the ellipse
+// Q(d) <= t lies within |dx| <= sqrt(t Sxx), |dy| <= sqrt(t Syy) of the centre, with
+// Sxx = C / det, Syy = A / det the covariance's diagonal (det = AC - B^2). The test is made
+// conservative for the q the kernels compute: t is enlarged by a bound on its rounding error
+// (taken as 2^-14 of the magnitudes of the terms it is formed from, far above the FP32 error of
+// the per-pixel form), det is formed with the rounding error of B^2 recovered, and the
+// half-widths get a relative and an absolute slack. A non-definite or non-finite conic (or a
+// negative t) reaches every quadrant. (xh, yh) is the centre relative to the tile centre.
+// A wavefront then skips, without evaluating q, the Gaussians that cannot reach its quadrant.
+// Only the plain form uses it: there q costs a dozen instructions per pixel, while the GEMM form
+// gets the q of a whole group from one product and skips a Gaussian with one compare.
+__device__ inline uint32_t reach_mask(const GRaw &g, float lo2o, float xh, float yh) {
+    const float gxh = fmaf(g.A, xh, g.B * yh), gyh = fmaf(g.C, yh, g.B * xh);
+    const float Qh = fmaf(xh, gxh, yh * gyh);
+    const float mag = kLog2e * (28.125f * (fabsf(g.A) + fabsf(g.C)) + 56.25f * fabsf(g.B) +
+                                7.5f * (fabsf(gxh) + fabsf(gyh)) + 0.5f * fabsf(Qh)) + fabsf(lo2o);
+    const float t = (lo2o - kQCull + fmaf(mag, 0x1p-14f, 0x1p-16f)) * (2.0f / kLog2e);
+    const float bb = g.B * g.B;
+    const float det = fmaf(g.A, g.C, -bb) - fmaf(g.B, g.B, -bb);
+    if (!(det > 0.f)) return 0xfu;
+    const float rdet = 1.0f / det;
+    const float hx = fmaf(sqrtf(t * g.C * rdet), 1.0f + 0x1p-10f, fmaf(fabsf(xh), 0x1p-18f, 0x1p-6f));
+    const float hy = fmaf(sqrtf(t * g.A * rdet), 1.0f + 0x1p-10f, fmaf(fabsf(yh), 0x1p-18f, 0x1p-6f));
+    if (!(hx < 3.0e38f && hy < 3.0e38f)) return 0xfu;   // also NaN (A or C not positive, t < 0)
+    // pixel columns (rows) of the tile are 0..15 relative to its corner; the centre is at 7.5
+    const float xl = xh + 7.5f, yl = yh + 7.5f;
+    const bool c0 = xl - hx <= 7.f && xl + hx >= 0.f, c1 = xl - hx <= 15.f && xl + hx >= 8.f;
+    const bool r0 = yl - hy <= 7.f && yl + hy >= 0.f, r1 = yl - hy <= 15.f && yl + hy >= 8.f;
+    return uint32_t(c0 && r0) | uint32_t(c1 && r0) << 1 | uint32_t(c0 && r1) << 2 |
+           uint32_t(c1 && r1) << 3;
+}
+
+// The reach masks of a staged batch as one 16-bit word per (quadrant, group): bit u of
+// reach[buf][w][g] is set when Gaussian u of group g can reach quadrant w (wavefront w's pixels).
+// Called by whole wavefronts (slot = thread).
+template <int NB>
+__device__ inline void stage_reach(uint32_t m4, int buf, int slot,
+                                   uint16_t (&reach)[2][4][NB / kGroup]) {
+    const int l = slot & 63;
+#pragma unroll
+    for (int w = 0; w < 4; ++w) {
+        const unsigned long long bal = __builtin_amdgcn_ballot_w64(((m4 >> w) & 1u) != 0u);
+        if (l < 4) reach[buf][w][(slot >> 6) * 4 + l] = uint16_t(bal >> (16 * l));
+    }
+}
+
+// This wavefront's reach mask of group g (every Gaussian reaches every wavefront in the GEMM form).
+template <Mode M, int NB>
+__device__ inline uint32_t group_reach(const Stage<M, NB> &S, int buf, int w, int g) {
+    if constexpr (M == Mode::Plain) return __builtin_amdgcn_readfirstlane(uint32_t(S.reach[buf][w][g]));
+    else return 0xffffu;
+}
+
+// Writes one Gaussian into slot `slot` of buffer `buf`. (xc, yc) is the tile centre. `reach`:
+// whether the plain form culls by reach (otherwise every Gaussian reaches every quadrant).
 template <Mode M, int NB, bool Bwd>
 __device__ inline void stage(const GRaw &g, int buf, int slot, float xc, float yc, Stage<M, NB> &S,
-                             StageBwd<NB> *SB) {
+                             StageBwd<NB> *SB, bool reach) {
     // a Gaussian with o < 1/255 never reaches the skip threshold (alpha <= o); stage it inert
     const bool live = g.valid && g.o >= kTauCull;
     const float lo2o = live ? __log2f(g.o) : -INFINITY;
@@ -278,6 +336,9 @@ __device__ inline void stage(const GRaw &g, int buf, int slot, float xc, float y
         S.kc[buf][slot] = k0;
     }
     S.attr[buf][slot] = make_float4(lo2o, g.r, g.g, g.b);
+    if constexpr (M == Mode::Plain)
+        stage_reach<NB>(!reach ? 0xfu : live ? reach_mask(g, lo2o, g.x - xc, g.y - yc) : 0u, buf,
+                        slot, S.reach);
     if constexpr (Bwd) {
         SB->bwd[buf][slot] = make_float4(g.x, g.y, live ? 1.0f / g.o : 0.f, __uint_as_float(g.id));
     }
@@ -379,11 +440,14 @@ __device__ inline void composite(float q, float lo2o, float cr, float cg, float 
 
 // Composites the 16 Gaussians of one group; q(u) gives Gaussian u's exponent for this lane. A
 // Gaussian that some lane takes has its (log2 o, r, g, b) read at one LDS address by every lane.
+// A Gaussian whose bit in `reach` (this wavefront's reach mask of the group) is clear is skipped
+// without evaluating q: no lane would take it.
 template <typename QFn>
-__device__ inline void composite_group(const float4 *attr, int base, FwdState &st,
+__device__ inline void composite_group(const float4 *attr, int base, uint32_t reach, FwdState &st,
                                        QFn q_of) {
 #pragma unroll
     for (int u = 0; u < kGroup; ++u) {
+        if (((reach >> u) & 1u) == 0u) continue;
         const float q = q_of(u);
         if (__builtin_amdgcn_ballot_w64(q >= st.thr) == 0ull) continue;   // no lane takes it
         const float4 a = attr[u];      // one address for every lane: an LDS broadcast
@@ -428,7 +492,7 @@ __device__ inline void fwd_tile(const ViewDesc &v, int64_t tile, Stage<M, NB> &S
     }
     for (int b = 0; b < nb; ++b) {
         const int buf = b & 1;
-        if (L.t < NB) stage<M, NB, false>(nxt, buf, L.t, xc, yc, S, nullptr);
+        if (L.t < NB) stage<M, NB, false>(nxt, buf, L.t, xc, yc, S, nullptr, v.reach != 0);
         // barrier; also counts the pixels still live (the whole block leaves once none is)
         if (__syncthreads_count(st.thr != INFINITY) == 0) break;
         // unconditional: past the last batch these read entry `start` and Gaussian 0, unused
@@ -439,13 +503,15 @@ __device__ inline void fwd_tile(const ViewDesc &v, int64_t tile, Stage<M, NB> &S
                            ? int((len - base + kGroup - 1) / kGroup) : kGroups;
         for (int g = 0; g < ng; ++g) {
             if (__ballot(st.thr != INFINITY) == 0) break;
+            const uint32_t reach = group_reach<M, NB>(S, buf, L.w, g);
+            if (reach == 0u) continue;                 // no Gaussian of the group reaches this wave
             const float4 *attr = &S.attr[buf][g * kGroup];
             if constexpr (M == Mode::Plain) {
-                composite_group(attr, base + g * kGroup, st,
+                composite_group(attr, base + g * kGroup, reach, st,
                                 [&](int u) { return plain_q(S, buf, g * kGroup + u, L); });
             } else {
                 const f16x q = group_q_mfma<M, NB>(S, buf, g, L, bhi, blo);
-                composite_group(attr, base + g * kGroup, st, [&](int u) { return q[u]; });
+                composite_group(attr, base + g * kGroup, reach, st, [&](int u) { return q[u]; });
             }
         }
     }
@@ -913,7 +979,7 @@ __device__ inline void bwd_tile(const ViewDesc &v, int64_t tile, Stage<M, NB> &S
     for (int b = nb - 1; b >= 0; --b) {
         const int buf = b & 1;
         if (L.t < NB) {
-            stage<M, NB, true>(nxt, buf, L.t, xc, yc, S, &SB);
+            stage<M, NB, true>(nxt, buf, L.t, xc, yc, S, &SB, v.reach != 0);
             SB.ids[b % 3][L.t] = nxt.id;
         }
         __syncthreads();
@@ -926,7 +992,10 @@ __device__ inline void bwd_tile(const ViewDesc &v, int64_t tile, Stage<M, NB> &S
                            ? int((len - base + kGroup - 1) / kGroup) : kGroups;
         for (int g = ng - 1; g >= 0; --g) {
             // nothing to do for this wave unless one of its pixels blended past the group start
+            // and a Gaussian of the group can reach it (see reach_mask)
             if (__ballot(st.last > base + g * kGroup) == 0) continue;
+            const uint32_t reach = group_reach<M, NB>(S, buf, L.w, g);
+            if (reach == 0u) continue;
             const float4 *ga = &S.attr[buf][g * kGroup];   // the group's staged values
             const float4 *gb = &SB.bwd[buf][g * kGroup];
             // the group's sums, Gaussian 0 (deterministic: this wavefront's slice)
@@ -953,6 +1022,7 @@ __device__ inline void bwd_tile(const ViewDesc &v, int64_t tile, Stage<M, NB> &S
 #pragma unroll
                         for (int i = 7; i >= 0; --i) {
                             const int u = 8 * h + i;
+                            if (((reach >> u) & 1u) == 0u) continue;
                             if (reverse_pair_mm<false>(q_of(u), true, ga, gb, u, L, st,
                                                        acc + u * kGrad, hit + u, rows[i]))
                                 hmask |= 1u << i;
@@ -961,6 +1031,7 @@ __device__ inline void bwd_tile(const ViewDesc &v, int64_t tile, Stage<M, NB> &S
 #pragma unroll
                         for (int i = 7; i >= 0; --i) {
                             const int u = 8 * h + i;
+                            if (((reach >> u) & 1u) == 0u) continue;
                             if (reverse_pair_mm<true>(q_of(u), u < rel, ga, gb, u, L, st,
                                                       acc + u * kGrad, hit + u, rows[i]))
                                 hmask |= 1u << i;
@@ -971,14 +1042,18 @@ __device__ inline void bwd_tile(const ViewDesc &v, int64_t tile, Stage<M, NB> &S
                 }
             } else if (whole) {
 #pragma unroll
-                for (int u = kGroup - 1; u >= 0; --u)
+                for (int u = kGroup - 1; u >= 0; --u) {
+                    if (((reach >> u) & 1u) == 0u) continue;
                     reverse_pair<false, kDet>(q_of(u), true, ga, gb, u, L, st, acc + u * kGrad,
                                               hit + u);
+                }
             } else {
 #pragma unroll
-                for (int u = kGroup - 1; u >= 0; --u)
+                for (int u = kGroup - 1; u >= 0; --u) {
+                    if (((reach >> u) & 1u) == 0u) continue;
                     reverse_pair<true, kDet>(q_of(u), u < rel, ga, gb, u, L, st, acc + u * kGrad,
                                              hit + u);
+                }
             }
         }
         // Buffers: the next iteration stages into the other stage buffer. The accumulator buffer

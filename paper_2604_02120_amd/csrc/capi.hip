@@ -71,9 +71,16 @@ gsb_status check_blend_common(int32_t W, int32_t H, const uint32_t *ranges,
                 "Gaussian attribute pointers must be non-null");
     GSB_REQUIRE(aligned(means2d, 8), "means2d must be 8-byte aligned");
     GSB_REQUIRE(bg != nullptr, "bg must be a host pointer to 3 floats");
-    GSB_REQUIRE(prec == GSB_FP32_PLAIN || prec == GSB_FP16_GEMM || prec == GSB_BF16_GEMM,
+    const gsb_precision base = prec & ~GSB_FULL_SCAN;
+    GSB_REQUIRE(base == GSB_FP32_PLAIN || base == GSB_FP16_GEMM || base == GSB_BF16_GEMM,
                 "unknown precision %d", int(prec));
     return GSB_OK;
+}
+
+// The precision of a (validated) precision argument, and the view's reach setting from its flag.
+gsb_precision prec_base(gsb_precision prec) { return prec & ~GSB_FULL_SCAN; }
+void set_reach(ViewDesc &v, gsb_precision prec) {
+    v.reach = prec_base(prec) == GSB_FP32_PLAIN && (prec & GSB_FULL_SCAN) == 0 ? 1 : 0;
 }
 
 }  // namespace
@@ -254,7 +261,8 @@ gsb_status gsb_blend_forward(int32_t W, int32_t H, const uint32_t *ranges,
     v.image = image;
     v.final_T = final_T;
     v.last_contrib = last_contrib;
-    return blend_forward(v, prec, kDefaultBatchFwd, static_cast<hipStream_t>(stream));
+    set_reach(v, prec);
+    return blend_forward(v, prec_base(prec), kDefaultBatchFwd, static_cast<hipStream_t>(stream));
 }
 
 gsb_status gsb_blend_backward(int32_t W, int32_t H, const uint32_t *ranges,
@@ -279,7 +287,8 @@ gsb_status gsb_blend_backward(int32_t W, int32_t H, const uint32_t *ranges,
     v.dL_dconics = dL_dconics;
     v.dL_dopacity = dL_dopacity;
     v.dL_dcolors = dL_dcolors;
-    return blend_backward(v, prec, kDefaultBatchBwd, false, static_cast<hipStream_t>(stream));
+    set_reach(v, prec);
+    return blend_backward(v, prec_base(prec), kDefaultBatchBwd, false, static_cast<hipStream_t>(stream));
 }
 
 gsb_status gsb_pack_gaussians(const float *means2d, const float *conics, const float *opacity,
@@ -310,7 +319,8 @@ gsb_status gsb_blend_forward_packed(int32_t W, int32_t H, const uint32_t *ranges
     v.image = image;
     v.final_T = final_T;
     v.last_contrib = last_contrib;
-    return blend_forward_packed(v, prec, static_cast<hipStream_t>(stream));
+    set_reach(v, prec);
+    return blend_forward_packed(v, prec_base(prec), static_cast<hipStream_t>(stream));
 }
 
 gsb_status gsb_blend_backward_packed(int32_t W, int32_t H, const uint32_t *ranges,
@@ -337,7 +347,8 @@ gsb_status gsb_blend_backward_packed(int32_t W, int32_t H, const uint32_t *range
     v.dL_dconics = dL_dconics;
     v.dL_dopacity = dL_dopacity;
     v.dL_dcolors = dL_dcolors;
-    return blend_backward_packed(v, prec, static_cast<hipStream_t>(stream));
+    set_reach(v, prec);
+    return blend_backward_packed(v, prec_base(prec), static_cast<hipStream_t>(stream));
 }
 
 gsb_status gsb_backward_det_workspace_bytes(int64_t n, int64_t pairs, size_t *bytes) {
@@ -377,7 +388,8 @@ gsb_status gsb_blend_backward_deterministic(
     v.dL_dconics = dL_dconics;
     v.dL_dopacity = dL_dopacity;
     v.dL_dcolors = dL_dcolors;
-    return blend_backward_det(v, prec, pairs, ws, static_cast<hipStream_t>(stream));
+    set_reach(v, prec);
+    return blend_backward_det(v, prec_base(prec), pairs, ws, static_cast<hipStream_t>(stream));
 }
 
 gsb_status gsb_plan_create(const gsb_view *views, int32_t n_views, gsb_precision prec,
@@ -387,7 +399,8 @@ gsb_status gsb_plan_create(const gsb_view *views, int32_t n_views, gsb_precision
     *plan = nullptr;
     GSB_REQUIRE(n_views >= 1 && n_views <= kMaxViews, "n_views = %d outside [1, %d]", int(n_views), kMaxViews);
     GSB_REQUIRE(views != nullptr, "views must be non-null");
-    GSB_REQUIRE(prec == GSB_FP32_PLAIN || prec == GSB_FP16_GEMM || prec == GSB_BF16_GEMM,
+    GSB_REQUIRE(prec_base(prec) == GSB_FP32_PLAIN || prec_base(prec) == GSB_FP16_GEMM ||
+                    prec_base(prec) == GSB_BF16_GEMM,
                 "unknown precision %d", int(prec));
     Tuning t{kDefaultBatchFwd, kDefaultBatchBwd, 0, kLaunchPersistent, 0};
     if (tuning) {
@@ -423,11 +436,12 @@ gsb_status gsb_plan_create(const gsb_view *views, int32_t n_views, gsb_precision
         v.dL_dconics = u.dL_dconics;
         v.dL_dopacity = u.dL_dopacity;
         v.dL_dcolors = u.dL_dcolors;
+        set_reach(v, prec);
         vd[size_t(i)] = v;
     }
     GSB_TRY(check_device());
     Plan *p = nullptr;
-    GSB_TRY(plan_create(vd.data(), n_views, prec, t, &p));
+    GSB_TRY(plan_create(vd.data(), n_views, prec_base(prec), t, &p));
     *plan = reinterpret_cast<gsb_plan>(p);
     return GSB_OK;
 }

@@ -109,7 +109,9 @@ gsb_status project(const ProjectArgs &a, int32_t sh_coeffs, hipStream_t s);
 // Everything one tile launch needs about one view (image): geometry, inputs, outputs. Built on the
 // host; passed by value to the single-view kernels and stored in device memory for batches.
 struct ViewDesc {
-    int32_t W, H, gx, pad0;
+    int32_t W, H, gx;
+    int32_t reach;           // plain form, 1: each wavefront skips the staged Gaussians that cannot
+                             // reach its quadrant of the tile (0: every Gaussian is evaluated)
     int64_t n_tiles;
     const uint32_t *ranges;
     const uint32_t *point_list;

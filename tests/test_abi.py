@@ -36,7 +36,7 @@ def test_library_exports_every_declared_symbol():
 
 
 def test_abi_version():
-    assert _lib.gsb_abi_version() == 7
+    assert _lib.gsb_abi_version() == 8
 
 
 def test_project_validation_before_device():
@@ -106,6 +106,13 @@ def test_forward_validation_before_device():
         ((16, 16, ok, ok, 0, ok, ok, ok, 1, (0, 0, 0), 0, ok, ok, ok), "attribute"),
         ((16, 16, ok, ok, ok, ok, ok, ok, 1, None, 0, ok, ok, ok), "bg"),
         ((16, 16, ok, ok, ok, ok, ok, ok, 1, (0, 0, 0), 9, ok, ok, ok), "precision"),
+        ((16, 16, ok, ok, ok, ok, ok, ok, 1, (0, 0, 0), 0x200, ok, ok, ok), "precision"),
+        ((16, 16, ok, ok, ok, ok, ok, ok, 1, (0, 0, 0), 3 | _lib.GSB_FULL_SCAN, ok, ok, ok),
+         "precision"),
+        # the full-scan flag is accepted with every precision (validation reaches the outputs)
+        ((16, 16, ok, ok, ok, ok, ok, ok, 1, (0, 0, 0), _lib.GSB_FULL_SCAN, 0, ok, ok), "output"),
+        ((16, 16, ok, ok, ok, ok, ok, ok, 1, (0, 0, 0), 2 | _lib.GSB_FULL_SCAN, 0, ok, ok),
+         "output"),
         ((16, 16, ok, ok, ok, ok, ok, ok, 1, (0, 0, 0), 1, 0, ok, ok), "output"),
     ]
     for args, frag in cases:

@@ -15,7 +15,7 @@ import gsinputs
 import oracle
 from gpu_util import (GEMM_GRAD, PLAIN_GRAD, check_gemm, check_plain, plain_grad_bound,
                       gpu_forward, normwise, say, upload, upload_bins)
-from paper_2604_02120_amd import api
+from paper_2604_02120_amd import _lib, api
 from paper_2604_02120_amd.autograd import blend
 
 pytestmark = pytest.mark.gpu
@@ -517,3 +517,64 @@ def test_deterministic_backward(gpu, prec, name):
         say(f"  deterministic {name} {prec} {k}: vs oracle {e:.3e}, vs atomic {d:.3e}")
         assert e <= bound, (k, e)
         assert d <= 1e-5, (k, d)
+
+
+# ----------------------------------------------------------------------------- reach culling
+def reach_scene(seed=71, n=3000, W=160, H=96):
+    """Footprints at the edges of the plain form's reach test: axes from 0.05 to 60 px, needles
+    at all angles, half the opacities just above 1/255 (alpha reaches 1/255 only near the
+    centre), a third of the centres on tile and quadrant borders, some off-screen."""
+    rng = np.random.default_rng(seed)
+    s = gsinputs.make_scene("C1", seed=seed, n=n, width=W, height=H)
+    k = n // 4
+    th = rng.uniform(0, np.pi, n)
+    s1 = np.concatenate([rng.uniform(0.05, 0.6, k), rng.uniform(0.3, 1.0, k),
+                         rng.uniform(8.0, 60.0, k), rng.uniform(0.5, 8.0, n - 3 * k)])
+    s2 = np.concatenate([rng.uniform(0.05, 0.6, k), rng.uniform(6.0, 40.0, k),
+                         rng.uniform(8.0, 60.0, k), rng.uniform(0.5, 8.0, n - 3 * k)])
+    s["conics"] = gsinputs.conic_from_axes(th, s1, s2).astype(np.float32)
+    s["radii"] = np.ceil(3.0 * np.maximum(s1, s2)).astype(np.int32)
+    op = rng.uniform(0.05, 0.99, n)
+    op[::2] = rng.uniform(1.0 / 255.0, 3.0 / 255.0, len(op[::2]))
+    s["opacity"] = op.astype(np.float32)
+    m = s["means2d"]
+    idx = rng.choice(n, n // 3, replace=False)
+    m[idx] = (np.round(m[idx] / 8.0) * 8.0 +
+              rng.choice([-0.5, 0.0, 0.5, 7.5], size=(len(idx), 2))).astype(np.float32)
+    m[:40] -= np.float32(30.0)
+    return s
+
+
+@pytest.mark.parametrize("name", ["reach", "needles", "bigrects", "clustered", "ragged"])
+def test_reach_culling_changes_nothing(gpu, name):
+    """The plain form's reach culling (default) against the full scan (GSB_FULL_SCAN): image,
+    final T and last contributor identical bit for bit, the deterministic backward's gradients
+    identical bit for bit; the culled result also within the plain bounds of the oracle. The
+    flag is a no-op for the GEMM forms."""
+    s = reach_scene() if name == "reach" else VIS[name]
+    W, H = s["width"], s["height"]
+    bg = (0.1, 0.3, 0.2)
+    ref = oracle.render(s, bg)
+    sd = upload(s, gpu)
+    pl, rg = upload_bins(ref["point_list"], ref["ranges"], gpu)
+    rec = api.pack_gaussians(sd["means2d"], sd["conics"], sd["opacity"], sd["colors"])
+    gd = torch.from_numpy(gsinputs.make_dloss(W, H, 79)).to(gpu)
+    ws = api.DetWorkspace(rec.shape[0], pl.numel(), device=gpu)
+    for base in ("fp32", "bf16"):
+        outs = {}
+        for prec in (base, api.prec_code(base) | _lib.GSB_FULL_SCAN):
+            f = api.blend_forward_packed(rec, rg, pl, W, H, bg, prec)
+            b = api.blend_backward_deterministic(rec, rg, pl, W, H, f[1], f[2], gd, bg, prec, ws=ws)
+            a = api.blend_forward(sd["means2d"], sd["conics"], sd["opacity"], sd["colors"], rg, pl,
+                                  W, H, bg, prec)
+            torch.cuda.synchronize()
+            outs[prec] = ([x.cpu().numpy() for x in f], [x.cpu().numpy() for x in b],
+                          [x.cpu().numpy() for x in a])
+        (f0, b0, a0), (f1, b1, a1) = outs.values()
+        for x, y in zip(f0 + b0 + a0, f1 + b1 + a1):
+            np.testing.assert_array_equal(x, y)
+        for x, y in zip(f0, a0):       # records and arrays: the same blend
+            np.testing.assert_array_equal(x, y)
+        if base == "fp32":
+            check_plain(ref, *f0, name)
+    say(f"  reach {name}: pairs {pl.numel()}, identical with and without culling")
