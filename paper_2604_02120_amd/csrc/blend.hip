@@ -117,7 +117,7 @@ struct Stage<Mode::Plain, NB> {  // plain form
 
 template <int NB>
 struct StageBwd {
-    float4 bwd[2][NB];         // (x, y, 1/o, index bits)
+    float4 bwd[2][NB];         // (x, y, 0, index bits)
     // The Gaussian index of each slot of batch b, in ids[b % 3]. The flush of batch
     // b + 1 reads other threads' slots while the next batch is staged; three buffers keep that
     // staging out of the ones being read.
@@ -125,6 +125,10 @@ struct StageBwd {
 };
 
 constexpr int kGrad = 9;   // per-Gaussian sums kept per batch
+
+// dL/do from the sum of alpha dL/dalpha over the Gaussian's pairs (alpha = o e^power below the 0.99
+// clamp): that sum over o. A Gaussian with o < 1/255 is never blended (its sum is zero).
+__device__ inline float opacity_grad(float sum, float o) { return o >= kTauCull ? sum / o : 0.f; }
 
 // Per-Gaussian gradient sums of a batch: 9 consecutive words per staged Gaussian, which the
 // flush reads as consecutive words across lanes. Two buffers: batch b sums into buffer b & 1
@@ -340,7 +344,7 @@ __device__ inline void stage(const GRaw &g, int buf, int slot, float xc, float y
         stage_reach<NB>(!reach ? 0xfu : live ? reach_mask(g, lo2o, g.x - xc, g.y - yc) : 0u, buf,
                         slot, S.reach);
     if constexpr (Bwd) {
-        SB->bwd[buf][slot] = make_float4(g.x, g.y, live ? 1.0f / g.o : 0.f, __uint_as_float(g.id));
+        SB->bwd[buf][slot] = make_float4(g.x, g.y, 0.f, __uint_as_float(g.id));
     }
 }
 
@@ -602,8 +606,10 @@ struct BwdState {
 // since 1 / (1 - 0) = 1),
 // the pair's 9 gradient terms are summed over the wavefront, and the totals are added into the
 // Gaussian's LDS accumulator (`acc` points at the word this lane adds when it leads, see
-// sum_word; the flag `hit` is set), which the block flushes to global memory once per batch. Raw sums: S_xx, S_xy, S_yy, S_x, S_y (times dL/dpower), dL/do, and the three colour
-// gradients.
+// sum_word; the flag `hit` is set), which the block flushes to global memory once per batch. Raw
+// sums: S_xx, S_xy, S_yy, S_x, S_y (times dL/dpower), the sum of dL/dpower without the clamp test
+// (o dL/do: the final pass divides it by o, once per Gaussian instead of once per pair), and the
+// three colour gradients.
 // kRanged = false: the caller has checked that the whole group lies before every lane's last
 // contributor, so the skip test alone decides (one compare, whose mask is the ballot).
 // kDet: `acc` points into the wavefront's own slice of the batch's sums, which this Gaussian's
@@ -646,7 +652,7 @@ __device__ inline void reverse_pair(float q, bool in_range, const float4 *ga, co
     const float dg = q > attr.x ? 0.f : da;
     const float dx = bw.x - L.px, dy = bw.y - L.py;
     const float tx = dg * dx, ty = dg * dy;
-    const float s[kGrad] = {tx * dx, tx * dy, ty * dy, tx, ty, da * bw.z,   // dL/do = alpha/o dL/dalpha
+    const float s[kGrad] = {tx * dx, tx * dy, ty * dy, tx, ty, da,   // dL/do = alpha/o dL/dalpha
                             wc * st.gr, wc * st.gg, wc * st.gb};
     float rab, rc;
     wave_sum9(s, L.l, rab, rc);
@@ -717,7 +723,7 @@ __device__ inline bool reverse_pair_mm(float q, bool in_range, const float4 *ga,
     const float lo = (dg - float(hp[0])) * kLoScale;
     const auto pk = __builtin_amdgcn_cvt_pkrtz(dg, lo);
     dgrow[L.l] = __builtin_bit_cast(uint32_t, pk);
-    const float s[4] = {da * bw.z, wc * st.gr, wc * st.gg, wc * st.gb};
+    const float s[4] = {da, wc * st.gr, wc * st.gg, wc * st.gb};
     const float tot = wave_sum4(s);
     if ((L.l & 15) == 0) {
         atomicAdd(acc + 5 + ((L.l >> 4) == 1 ? 2 : (L.l >> 4) == 2 ? 1 : (L.l >> 4)), tot);
@@ -1199,7 +1205,7 @@ __global__ __launch_bounds__(256) void k_det_gather(const float4 *rec, const flo
     dconics[3 * g + 2] = -0.5f * sum[2];
     dmeans[2 * g] = -(A * sum[3] + B * sum[4]);
     dmeans[2 * g + 1] = -(B * sum[3] + C * sum[4]);
-    dopac[g] = sum[5];
+    dopac[g] = opacity_grad(sum[5], r1.y);
     dcolors[3 * g] = sum[6];
     dcolors[3 * g + 1] = sum[7];
     dcolors[3 * g + 2] = sum[8];
@@ -1383,12 +1389,16 @@ __global__ __launch_bounds__(256) void k_bwd_finish(const ViewDesc *views, ViewD
     const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
     if (i >= v.n) return;
     F3 c;
-    if (v.records) {                 // (x, y, A, B), (C, ...): the conic from the packed record
+    float o;
+    if (v.records) {                 // (x, y, A, B), (C, o, ...): conic and opacity from the record
         const float4 r0 = v.records[3 * i], r1 = v.records[3 * i + 1];
         c = F3{r0.z, r0.w, r1.x};
+        o = r1.y;
     } else {
         c = reinterpret_cast<const F3 *>(v.conics)[i];
+        o = v.opacity[i];
     }
+    v.dL_dopacity[i] = opacity_grad(v.dL_dopacity[i], o);
     F3 *dc = reinterpret_cast<F3 *>(v.dL_dconics);
     float2 *dm = reinterpret_cast<float2 *>(v.dL_dmeans2d);
     const F3 s = dc[i];
