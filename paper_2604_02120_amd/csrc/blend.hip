@@ -105,6 +105,7 @@ struct Stage {                 // GEMM form
     vec alo[2][NB];            // v_g lo terms * 2^12
     float kc[2][NB];           // accumulator init: constant term + log2 o (-inf = inert)
     float4 attr[2][NB];        // (log2 o, r, g, b)
+    uint32_t live[2][4];       // forward: whether wavefront w still has a live pixel, per batch
     vec zero;
 };
 template <int NB>
@@ -113,6 +114,7 @@ struct Stage<Mode::Plain, NB> {  // plain form
     float2 geo2[2][NB];        // (C, log2 o)
     float4 attr[2][NB];        // (log2 o, r, g, b)
     uint16_t reach[2][4][NB / kGroup];   // reach masks per quadrant and group (stage_reach)
+    uint32_t live[2][4];       // forward: whether wavefront w still has a live pixel, per batch
 };
 
 template <int NB>
@@ -497,8 +499,16 @@ __device__ inline void fwd_tile(const ViewDesc &v, int64_t tile, Stage<M, NB> &S
     for (int b = 0; b < nb; ++b) {
         const int buf = b & 1;
         if (L.t < NB) stage<M, NB, false>(nxt, buf, L.t, xc, yc, S, nullptr, v.reach != 0);
-        // barrier; also counts the pixels still live (the whole block leaves once none is)
-        if (__syncthreads_count(st.thr != INFINITY) == 0) break;
+        // Barrier. Each wavefront also posts whether it still has a live pixel, and the whole
+        // block leaves once none has (one barrier; the flags are double-buffered with the batch,
+        // so that batch b + 2's post cannot overtake a wavefront still reading batch b's).
+        const bool wave_live = __ballot(st.thr != INFINITY) != 0;   // (the whole wavefront's)
+        if (L.l == 0) S.live[buf][L.w] = wave_live ? 1u : 0u;
+        __syncthreads();
+        {
+            const uint4 f = *reinterpret_cast<const uint4 *>(S.live[buf]);
+            if (__builtin_amdgcn_readfirstlane(f.x | f.y | f.z | f.w) == 0u) break;
+        }
         // unconditional: past the last batch these read entry `start` and Gaussian 0, unused
         nxt = src.fetch(ent.id(), n);
         ent = entry(b + 2);
@@ -874,8 +884,11 @@ __device__ inline void bwd_tile(const ViewDesc &v, int64_t tile, Stage<M, NB> &S
     const uint2 rg = reinterpret_cast<const uint2 *>(v.ranges)[tile];
     const int64_t start = rg.x;
     // positions [0, max last) are the only ones that matter (never more than the list holds)
-    const int64_t len = s_maxlast < int64_t(rg.y) - int64_t(rg.x) ? s_maxlast
-                                                                   : int64_t(rg.y) - int64_t(rg.x);
+    // (the same value in every lane: made wavefront-uniform, so that the batch and group loops
+    // and their index arithmetic run on the scalar unit)
+    const int maxlast = __builtin_amdgcn_readfirstlane(s_maxlast);
+    const int64_t len = maxlast < int64_t(rg.y) - int64_t(rg.x) ? maxlast
+                                                                : int64_t(rg.y) - int64_t(rg.x);
     const int nb = int((len + NB - 1) / NB);
     if constexpr (kDet) {
         // list positions [len, end) are never visited: their sums are zero (positions at or
