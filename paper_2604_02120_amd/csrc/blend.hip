@@ -119,7 +119,7 @@ struct Stage<Mode::Plain, NB> {  // plain form
 
 template <int NB>
 struct StageBwd {
-    float4 bwd[2][NB];         // (x, y, 0, index bits)
+    float2 bwd[2][NB];         // the mean (x, y)
     // The Gaussian index of each slot of batch b, in ids[b % 3]. The flush of batch
     // b + 1 reads other threads' slots while the next batch is staged; three buffers keep that
     // staging out of the ones being read.
@@ -140,7 +140,7 @@ struct BwdAcc {
     float v[2][NB * kGrad];
     // whether a slot received any sum (set by the wavefronts that add into it), and each
     // wavefront's list of its touched slots, built when it flushes
-    uint32_t hit[2][NB];
+    uint8_t hit[2][NB];
     uint16_t list[kBlock / 64][64];
     __device__ float *slot(int ab, int t) { return v[ab] + t * kGrad; }
 };
@@ -346,7 +346,7 @@ __device__ inline void stage(const GRaw &g, int buf, int slot, float xc, float y
         stage_reach<NB>(!reach ? 0xfu : live ? reach_mask(g, lo2o, g.x - xc, g.y - yc) : 0u, buf,
                         slot, S.reach);
     if constexpr (Bwd) {
-        SB->bwd[buf][slot] = make_float4(g.x, g.y, 0.f, __uint_as_float(g.id));
+        SB->bwd[buf][slot] = make_float2(g.x, g.y);
     }
 }
 
@@ -625,9 +625,9 @@ struct BwdState {
 // kDet: `acc` points into the wavefront's own slice of the batch's sums, which this Gaussian's
 // totals are stored into (no other wavefront writes there), so no atomic and no flag.
 template <bool kRanged, bool kDet = false>
-__device__ inline void reverse_pair(float q, bool in_range, const float4 *ga, const float4 *gb,
+__device__ inline void reverse_pair(float q, bool in_range, const float4 *ga, const float2 *gb,
                                     int u, const Lane &L, BwdState &st, float *acc,
-                                    uint32_t *hit) {
+                                    uint8_t *hit) {
     const bool alive = kRanged ? (in_range && q >= kQCull) : (q >= kQCull);
     unsigned long long live;
     if constexpr (kRanged) {
@@ -645,7 +645,7 @@ __device__ inline void reverse_pair(float q, bool in_range, const float4 *ga, co
     }
     if (live == 0ull) return;
     const float4 attr = ga[u];   // one address for every lane: LDS broadcasts
-    const float4 bw = gb[u];
+    const float2 bw = gb[u];
     // a dead lane has q < log2(1/255) or is past its last contributor: it blended nothing here
     const float araw = __builtin_amdgcn_exp2f(fminf(q, attr.x));
     const float a = alive ? fminf(araw, kAlphaMax) : 0.f;
@@ -700,9 +700,9 @@ __device__ inline float wave_sum4(const float (&s)[4]) {
 // transposition row `dgrow`, from which the five geometric sums are formed as a product with the
 // pixel basis (mm_reduce). Returns whether any lane of the wavefront had a live pair.
 template <bool kRanged>
-__device__ inline bool reverse_pair_mm(float q, bool in_range, const float4 *ga, const float4 *gb,
+__device__ inline bool reverse_pair_mm(float q, bool in_range, const float4 *ga, const float2 *gb,
                                        int u, const Lane &L, BwdState &st, float *acc,
-                                       uint32_t *hit, uint32_t *dgrow) {
+                                       uint8_t *hit, uint32_t *dgrow) {
     const bool alive = kRanged ? (in_range && q >= kQCull) : (q >= kQCull);
     unsigned long long live;
     if constexpr (kRanged) {
@@ -716,7 +716,7 @@ __device__ inline bool reverse_pair_mm(float q, bool in_range, const float4 *ga,
     }
     if (live == 0ull) return false;
     const float4 attr = ga[u];
-    const float4 bw = gb[u];
+    const float2 bw = gb[u];
     const float araw = __builtin_amdgcn_exp2f(fminf(q, attr.x));
     const float a = alive ? fminf(araw, kAlphaMax) : 0.f;
     const float r = __builtin_amdgcn_rcpf(1.0f - a);
@@ -772,7 +772,7 @@ __device__ inline void mm_basis(const Lane &L, h8 (&B)[2]) {
 // accumulator. `hmask` has bit i set when Gaussian base + i had a live pair in this wavefront;
 // the rows are left zero.
 __device__ inline void mm_reduce(uint32_t (*rows)[kDgStride], const h8 (&B)[2], unsigned hmask,
-                                 const float4 *gb, float xc, float yc, float *acc, const Lane &L) {
+                                 const float2 *gb, float xc, float yc, float *acc, const Lane &L) {
     __builtin_amdgcn_wave_barrier();
     const int row = L.l & 15, q = L.l >> 4;
     // hi rows take the low halves of the packed words, lo rows the high halves
@@ -814,7 +814,7 @@ __device__ inline void mm_reduce(uint32_t (*rows)[kDgStride], const h8 (&B)[2], 
             const float4 m0 = *reinterpret_cast<const float4 *>(mom + 8 * g);
             const float2 m1 = *reinterpret_cast<const float2 *>(mom + 8 * g + 4);
             const float S1 = m0.x, Sx = m0.y, Sy = m0.z, Sxx = m0.w, Sxy = m1.x, Syy = m1.y;
-            const float4 bw = gb[g];
+            const float2 bw = gb[g];
             const float xh = bw.x - xc, yh = bw.y - yc;
             const float sx = fmaf(xh, S1, Sx), sy = fmaf(yh, S1, Sy);
             float val;
@@ -944,7 +944,7 @@ __device__ inline void bwd_tile(const ViewDesc &v, int64_t tile, Stage<M, NB> &S
         BwdAcc<NB> &s_acc = *acc_;
         constexpr int kPer = NB / (kBlock / 64);   // slots per wavefront, at most 64
         float *acc = s_acc.v[bb & 1];
-        uint32_t *hit = s_acc.hit[bb & 1];
+        uint8_t *hit = s_acc.hit[bb & 1];
         const uint32_t *ids = SB.ids[bb % 3];
         uint16_t *list = s_acc.list[L.w];
         const int s0 = L.w * kPer;
@@ -1016,12 +1016,12 @@ __device__ inline void bwd_tile(const ViewDesc &v, int64_t tile, Stage<M, NB> &S
             const uint32_t reach = group_reach<M, NB>(S, buf, L.w, g);
             if (reach == 0u) continue;
             const float4 *ga = &S.attr[buf][g * kGroup];   // the group's staged values
-            const float4 *gb = &SB.bwd[buf][g * kGroup];
+            const float2 *gb = &SB.bwd[buf][g * kGroup];
             // the group's sums, Gaussian 0 (deterministic: this wavefront's slice)
             float *accw = kDet ? det->v[buf][L.w] + g * kGroup * kGrad
                                : acc_->slot(buf, g * kGroup);
             float *acc = accw + (kMM ? 0 : word);   // this lane's word (VALU reduction)
-            uint32_t *hit = kDet ? nullptr : &acc_->hit[buf][g * kGroup];
+            uint8_t *hit = kDet ? nullptr : &acc_->hit[buf][g * kGroup];
             const int rel = st.last - (base + g * kGroup);   // positions < last are in range
             // the whole group is in range for every lane (the common case once past the lanes'
             // last contributors; never for a partial tile, whose outside lanes have last = 0)
@@ -1107,7 +1107,8 @@ template <bool kMM> __device__ inline BwdMM *mm_ptr(MMTiles<kMM> &t) {
 }
 // Register targets of the one-tile-per-block backward kernels; the matrix-core reduction keeps
 // the product's operands and results live across each half-group and needs more registers
-// (fewer targets spill).
+// (fewer targets spill). (6 wavefronts per SIMD for the GEMM forms fit in LDS, 26.9 KB per block,
+// but at 80 registers a few values spill and the backward is about 1% slower than at 5.)
 template <Mode M, bool kMM> constexpr int waves_bwd_tile() {
     return kMM ? (M == Mode::Plain ? 5 : 4) : (M == Mode::Plain ? 7 : 5);
 }
