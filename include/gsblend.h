@@ -285,7 +285,7 @@ gsb_status gsb_blend_backward_packed(int32_t W, int32_t H, const uint32_t *range
  *          pair count). Entries outside are neither read nor written.
  * records: the packed attributes (gsb_pack_gaussians).
  * ws:      device workspace of ws_bytes >= gsb_backward_det_workspace_bytes(n, pairs) bytes,
- *          256-byte aligned (about 52 bytes per list entry).
+ *          256-byte aligned (about 80 bytes per list entry).
  * Other arguments and the outputs as gsb_blend_backward_packed. Errors: INVALID, UNSUPPORTED, HIP.
  * ------------------------------------------------------------------------------------------- */
 gsb_status gsb_backward_det_workspace_bytes(int64_t n, int64_t pairs, size_t *bytes);

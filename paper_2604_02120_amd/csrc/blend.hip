@@ -127,6 +127,10 @@ struct StageBwd {
 };
 
 constexpr int kGrad = 9;   // per-Gaussian sums kept per batch
+// Deterministic backward: each list position's nine sums sit in a 64-byte row of 16 words (the
+// last seven zero), so that the per-Gaussian gather, which reads the rows of one Gaussian's
+// positions scattered over the whole list, touches one aligned 64-byte segment per position.
+constexpr int kDetStride = 16;
 
 // dL/do from the sum of alpha dL/dalpha over the Gaussian's pairs (alpha = o e^power below the 0.99
 // clamp): that sum over o. A Gaussian with o < 1/255 is never blended (its sum is zero).
@@ -894,8 +898,8 @@ __device__ inline void bwd_tile(const ViewDesc &v, int64_t tile, Stage<M, NB> &S
         // list positions [len, end) are never visited: their sums are zero (positions at or
         // past det_pairs, which an inconsistent range could name, are never written)
         const int64_t end = int64_t(rg.y) < v.det_pairs ? int64_t(rg.y) : v.det_pairs;
-        const int64_t tail = (end - start - len) * kGrad;
-        float *dst = v.det_partial + (start + len) * kGrad;
+        const int64_t tail = (end - start - len) * kDetStride;
+        float *dst = v.det_partial + (start + len) * kDetStride;
         for (int64_t j = L.t; j < tail; j += kBlock) dst[j] = 0.f;
     }
     if (nb == 0) return;
@@ -916,22 +920,25 @@ __device__ inline void bwd_tile(const ViewDesc &v, int64_t tile, Stage<M, NB> &S
     // no lane is spent on the slots without a sum (over half of a 3-sigma list's). Each item is
     // zeroed by the lane that reads it, and each flag by the lane that lists it, ready for batch
     // bb - 2, which reuses the buffers after the next barrier.
-    // Deterministic form: item j of the batch (slot j / 9, sum j % 9) is the four wavefronts'
-    // values added in wavefront order, stored at list position start + bb NB + slot (consecutive
-    // threads, consecutive words) and zeroed in the slices.
+    // Deterministic form: word k < 9 of slot i's row is the four wavefronts' sum k added in
+    // wavefront order (and zeroed in the slices), words 9..15 are zero; the row is stored at list
+    // position start + bb NB + i (consecutive threads, consecutive words).
     const auto flush_det = [&](int bb) {
         const int64_t base = int64_t(bb) * NB;
-        float *dst = v.det_partial + (start + base) * kGrad;
+        float *dst = v.det_partial + (start + base) * kDetStride;
         int64_t last = len - base < NB ? len - base : NB;          // slots of this batch
         if (start + base + last > v.det_pairs) last = v.det_pairs - start - base;
-        const int64_t items = last * kGrad;
-        for (int j = L.t; j < NB * kGrad; j += kBlock) {
+        const int64_t items = last * kDetStride;
+        for (int j = L.t; j < NB * kDetStride; j += kBlock) {
+            const int i = j / kDetStride, k = j % kDetStride;
             float sum = 0.f;
+            if (k < kGrad) {
 #pragma unroll
-            for (int w = 0; w < kBlock / 64; ++w) {
-                float *p = det->v[bb & 1][w] + j;
-                sum += *p;
-                *p = 0.f;
+                for (int w = 0; w < kBlock / 64; ++w) {
+                    float *p = det->v[bb & 1][w] + i * kGrad + k;
+                    sum += *p;
+                    *p = 0.f;
+                }
             }
             if (j < items) dst[j] = sum;
         }
@@ -1207,10 +1214,14 @@ __global__ __launch_bounds__(256) void k_det_gather(const float4 *rec, const flo
     float sum[kGrad];
 #pragma unroll
     for (int k = 0; k < kGrad; ++k) sum[k] = 0.f;
+#pragma unroll 2
     for (uint32_t j = a; j < b; ++j) {
-        const float *p = partial + int64_t(pos[j]) * kGrad;
-#pragma unroll
-        for (int k = 0; k < kGrad; ++k) sum[k] += p[k];
+        const float *p = partial + int64_t(pos[j]) * kDetStride;
+        const float4 p0 = *reinterpret_cast<const float4 *>(p);
+        const float4 p1 = *reinterpret_cast<const float4 *>(p + 4);
+        sum[0] += p0.x; sum[1] += p0.y; sum[2] += p0.z; sum[3] += p0.w;
+        sum[4] += p1.x; sum[5] += p1.y; sum[6] += p1.z; sum[7] += p1.w;
+        sum[8] += p[8];
     }
     const float4 r0 = rec[3 * g], r1 = rec[3 * g + 1];
     const float A = r0.z, B = r0.w, C = r1.x;
@@ -1571,7 +1582,7 @@ DetLayout det_layout(int64_t n, int64_t pairs) {
     const size_t P = size_t(pairs > 0 ? pairs : 1), N = size_t(n > 0 ? n : 1);
     DetLayout L;
     size_t o = 0;
-    L.partial = o; o += al256(sizeof(float) * kGrad * P);
+    L.partial = o; o += al256(sizeof(float) * kDetStride * P);
     L.ka = o;      o += al256(sizeof(uint32_t) * P);
     L.kb = o;      o += al256(sizeof(uint32_t) * P);
     L.va = o;      o += al256(sizeof(uint32_t) * P);
