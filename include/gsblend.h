@@ -279,7 +279,9 @@ gsb_status gsb_blend_backward_packed(int32_t W, int32_t H, const uint32_t *range
  * gsb_blend_backward) with every sum in a fixed order, so that its result is identical bit for bit
  * on every run with the same inputs: per list entry, the wavefronts' sums over the tile's pixels
  * are added in wavefront order and stored at the entry's position; the positions are then grouped
- * by Gaussian with a stable sort and each Gaussian's entries are added in list order.
+ * by Gaussian with a stable sort and each Gaussian's entries are added in a fixed order (lane l of
+ * a wavefront takes entries l, l + 64, ... in list order; the lane sums are combined by a fixed
+ * reduction tree).
  *
  * pairs:   number of entries of point_list; every range must lie in [0, pairs) (the binning's
  *          pair count). Entries outside are neither read nor written.

@@ -1202,38 +1202,58 @@ __global__ __launch_bounds__(256) void k_det_init(const uint32_t *plist, int64_t
     if (i == 0) *count = (unsigned long long)pairs;
 }
 
-// Per Gaussian g: the nine sums of its list positions, added in increasing position order (the
-// order the stable sort left them in), then turned into the gradients as k_bwd_finish does.
+// Per Gaussian g: the nine sums of its list positions in a fixed order, then turned into the
+// gradients as k_bwd_finish does. One wavefront per Gaussian (kGatherPer Gaussians in turn): lane
+// l adds the rows of the Gaussian's positions l, l + 64, ... of its run (in list order, the order
+// the stable sort left them in), and the 64 lane sums are combined by wave_sum9's fixed reduction
+// tree. A thread per Gaussian would leave most lanes of a wavefront idle behind its largest
+// footprint (list runs are heavy-tailed: a few Gaussians cover hundreds of tiles).
+constexpr int kGatherPer = 4;
 __global__ __launch_bounds__(256) void k_det_gather(const float4 *rec, const float *partial,
                                                     const uint32_t *pos, const uint32_t *seg,
                                                     int64_t n, float *dmeans, float *dconics,
                                                     float *dopac, float *dcolors) {
-    const int64_t g = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-    if (g >= n) return;
-    const uint32_t a = seg[2 * g], b = seg[2 * g + 1];
-    float sum[kGrad];
+    const int lane = threadIdx.x & 63;
+    const int64_t wave = (int64_t(blockIdx.x) * blockDim.x + threadIdx.x) >> 6;
+    for (int r = 0; r < kGatherPer; ++r) {
+        const int64_t g = wave * kGatherPer + r;
+        if (g >= n) return;                       // the same in every lane
+        const uint32_t a = seg[2 * g], b = seg[2 * g + 1];
+        float sum[kGrad];
 #pragma unroll
-    for (int k = 0; k < kGrad; ++k) sum[k] = 0.f;
-#pragma unroll 2
-    for (uint32_t j = a; j < b; ++j) {
-        const float *p = partial + int64_t(pos[j]) * kDetStride;
-        const float4 p0 = *reinterpret_cast<const float4 *>(p);
-        const float4 p1 = *reinterpret_cast<const float4 *>(p + 4);
-        sum[0] += p0.x; sum[1] += p0.y; sum[2] += p0.z; sum[3] += p0.w;
-        sum[4] += p1.x; sum[5] += p1.y; sum[6] += p1.z; sum[7] += p1.w;
-        sum[8] += p[8];
+        for (int k = 0; k < kGrad; ++k) sum[k] = 0.f;
+        for (uint32_t j = a + uint32_t(lane); j < b; j += 64) {
+            const float *p = partial + int64_t(pos[j]) * kDetStride;
+            const float4 p0 = *reinterpret_cast<const float4 *>(p);
+            const float4 p1 = *reinterpret_cast<const float4 *>(p + 4);
+            sum[0] += p0.x; sum[1] += p0.y; sum[2] += p0.z; sum[3] += p0.w;
+            sum[4] += p1.x; sum[5] += p1.y; sum[6] += p1.z; sum[7] += p1.w;
+            sum[8] += p[8];
+        }
+        float ab, c;
+        wave_sum9(sum, lane, ab, c);
+        // lane 16r holds sum {0,2,1,3}[r], lane 16r + 8 sum 4 + {0,2,1,3}[r]; lane 0 of c sum 8
+        const auto at = [](float x, int l) {
+            return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(x), l));
+        };
+        float t[kGrad];
+        t[0] = at(ab, 0);  t[2] = at(ab, 16); t[1] = at(ab, 32); t[3] = at(ab, 48);
+        t[4] = at(ab, 8);  t[6] = at(ab, 24); t[5] = at(ab, 40); t[7] = at(ab, 56);
+        t[8] = at(c, 0);
+        if (lane == 0) {
+            const float4 r0 = rec[3 * g], r1 = rec[3 * g + 1];
+            const float A = r0.z, B = r0.w, C = r1.x;
+            dconics[3 * g] = -0.5f * t[0];
+            dconics[3 * g + 1] = -t[1];
+            dconics[3 * g + 2] = -0.5f * t[2];
+            dmeans[2 * g] = -(A * t[3] + B * t[4]);
+            dmeans[2 * g + 1] = -(B * t[3] + C * t[4]);
+            dopac[g] = opacity_grad(t[5], r1.y);
+            dcolors[3 * g] = t[6];
+            dcolors[3 * g + 1] = t[7];
+            dcolors[3 * g + 2] = t[8];
+        }
     }
-    const float4 r0 = rec[3 * g], r1 = rec[3 * g + 1];
-    const float A = r0.z, B = r0.w, C = r1.x;
-    dconics[3 * g] = -0.5f * sum[0];
-    dconics[3 * g + 1] = -sum[1];
-    dconics[3 * g + 2] = -0.5f * sum[2];
-    dmeans[2 * g] = -(A * sum[3] + B * sum[4]);
-    dmeans[2 * g + 1] = -(B * sum[3] + C * sum[4]);
-    dopac[g] = opacity_grad(sum[5], r1.y);
-    dcolors[3 * g] = sum[6];
-    dcolors[3 * g + 1] = sum[7];
-    dcolors[3 * g + 2] = sum[8];
 }
 
 // One record per Gaussian: (x, y, A, B), (C, o, r, g), (b, 0, 0, 0). Consecutive threads write
@@ -1630,7 +1650,7 @@ gsb_status blend_backward_det(const ViewDesc &v0, gsb_precision prec, int64_t pa
         const uint32_t *spos = passes % 2 ? vb : va;
         key_ranges(skeys, count, pairs, seg, s);
         if (v.n > 0)
-            k_det_gather<<<dim3(unsigned((v.n + 255) / 256)), 256, 0, s>>>(
+            k_det_gather<<<dim3(unsigned((v.n + 4 * kGatherPer - 1) / (4 * kGatherPer))), 256, 0, s>>>(
                 v.records, v.det_partial, spos, seg, v.n, v.dL_dmeans2d, v.dL_dconics,
                 v.dL_dopacity, v.dL_dcolors);
     } else if (v.n > 0) {
