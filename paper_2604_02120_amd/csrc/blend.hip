@@ -609,7 +609,11 @@ __device__ inline int sum_word(int l) {
 
 struct BwdState {
     float T;        // transmittance in front of the pairs not yet visited
-    float behind;   // T_final (bg . g) + sum over the visited pairs of alpha T (c . g)
+    // the colour behind them per unit of that transmittance: (T_final (bg . g) + sum over the
+    // visited pairs of alpha T (c . g)) / T. With it dL/dalpha of the next pair (in front) is
+    // T_in (c . g - beta), T_in the transmittance in front of that pair, and beta moves to
+    // beta (1 - alpha) + alpha (c . g): no division by (1 - alpha) beyond the one T needs.
+    float beta;
     float gr, gg, gb;
     int last;
 };
@@ -656,12 +660,12 @@ __device__ inline void reverse_pair(float q, bool in_range, const float4 *ga, co
     const float r = __builtin_amdgcn_rcpf(1.0f - a);  // exactly 1 for a dead lane
     const float Tb = st.T * r;                           // T in front of this Gaussian
     const float gc = st.gr * attr.y + st.gg * attr.z + st.gb * attr.w;
-    const float dLda = Tb * gc - st.behind * r;
-    const float wc = a * Tb;
-    st.behind = fmaf(wc, gc, st.behind);
+    const float wc = a * Tb;                             // the pair's weight alpha T
+    const float gmb = gc - st.beta;                      // dL/dalpha = Tb (c . g - beta)
+    st.beta = fmaf(a, gmb, st.beta);
     st.T = Tb;
     // dL/dpower = alpha * dL/dalpha unless the 0.99 clamp is active
-    const float da = araw < kAlphaMax ? a * dLda : 0.f;
+    const float da = araw < kAlphaMax ? wc * gmb : 0.f;
     // no gradient reaches the geometry through a clamped (positive) power
     const float dg = q > attr.x ? 0.f : da;
     const float dx = bw.x - L.px, dy = bw.y - L.py;
@@ -726,11 +730,11 @@ __device__ inline bool reverse_pair_mm(float q, bool in_range, const float4 *ga,
     const float r = __builtin_amdgcn_rcpf(1.0f - a);
     const float Tb = st.T * r;
     const float gc = st.gr * attr.y + st.gg * attr.z + st.gb * attr.w;
-    const float dLda = Tb * gc - st.behind * r;
     const float wc = a * Tb;
-    st.behind = fmaf(wc, gc, st.behind);
+    const float gmb = gc - st.beta;
+    st.beta = fmaf(a, gmb, st.beta);
     st.T = Tb;
-    const float da = araw < kAlphaMax ? a * dLda : 0.f;
+    const float da = araw < kAlphaMax ? wc * gmb : 0.f;
     const float dg = q > attr.x ? 0.f : da;
     // dg = hi + lo 2^-12 with FP16 hi and lo (truncations; the residual dg - hi is exact in FP32)
     const auto hp = __builtin_amdgcn_cvt_pkrtz(dg, 0.f);
@@ -880,7 +884,7 @@ __device__ inline void bwd_tile(const ViewDesc &v, int64_t tile, Stage<M, NB> &S
         st.T = v.final_T[p];
         st.last = v.last_contrib[p];
         st.gr = v.dL_dimage[p]; st.gg = v.dL_dimage[HW + p]; st.gb = v.dL_dimage[2 * HW + p];
-        st.behind = st.T * (v.bg[0] * st.gr + v.bg[1] * st.gg + v.bg[2] * st.gb);
+        st.beta = v.bg[0] * st.gr + v.bg[1] * st.gg + v.bg[2] * st.gb;   // (T_final (bg . g)) / T_final
     }
     __syncthreads();
     if (st.last > 0) atomicMax(&s_maxlast, st.last);
