@@ -105,7 +105,7 @@ struct Stage {                 // GEMM form
     vec alo[2][NB];            // v_g lo terms * 2^12
     float kc[2][NB];           // accumulator init: constant term + log2 o (-inf = inert)
     float4 attr[2][NB];        // (log2 o, r, g, b)
-    uint32_t live[2][4];       // forward: whether wavefront w still has a live pixel, per batch
+    alignas(16) uint32_t live[2][4];   // forward: whether wavefront w still has a live pixel
     vec zero;
 };
 template <int NB>
@@ -114,7 +114,7 @@ struct Stage<Mode::Plain, NB> {  // plain form
     float2 geo2[2][NB];        // (C, log2 o)
     float4 attr[2][NB];        // (log2 o, r, g, b)
     uint16_t reach[2][4][NB / kGroup];   // reach masks per quadrant and group (stage_reach)
-    uint32_t live[2][4];       // forward: whether wavefront w still has a live pixel, per batch
+    alignas(16) uint32_t live[2][4];   // forward: whether wavefront w still has a live pixel
 };
 
 template <int NB>
