@@ -261,6 +261,43 @@ def c5_sample_tiles(gx, gy, k=40, seed=5):
     return sorted(set(corners) | set(rng.choice(gx * gy, size=k, replace=False).tolist()))
 
 
+def test_c5_4k_full_frame(gpu):
+    """The largest workload (3840x2160, 3M Gaussians, 54.7M pairs) whole, as the benchmark runs
+    it: GPU binning bit-exact against the oracle's, the forward from packed records in every
+    precision against the full-frame oracle image, and the backward's gradients against the
+    oracle's gradient of the whole frame."""
+    s = gsinputs.make_scene("C5")
+    W, H = s["width"], s["height"]
+    say("[c5-full] 3840x2160 n=3e6: oracle binning")
+    pl_ref, rg_ref = oracle.bin_tiles(s["means2d"], s["radii"], s["depths"], W, H)
+    sd = upload(s, gpu)
+    pl, rg = api.bin_tiles(sd["means2d"], sd["radii"], sd["depths"], W, H)
+    np.testing.assert_array_equal(rg.cpu().numpy().astype(np.uint32), rg_ref)
+    np.testing.assert_array_equal(pl.cpu().numpy().astype(np.uint32), pl_ref)
+    say(f"[c5-full] {len(pl_ref)} pairs bit-exact; oracle forward + backward")
+    ref = oracle.forward(W, H, rg_ref, pl_ref, s["means2d"], s["conics"], s["opacity"], s["colors"])
+    g = gsinputs.make_dloss(W, H, 1005)
+    gref = oracle.backward(W, H, rg_ref, pl_ref, s["means2d"], s["conics"], s["opacity"],
+                           s["colors"], g)
+    rec = api.pack_gaussians(sd["means2d"], sd["conics"], sd["opacity"], sd["colors"])
+    gd = torch.from_numpy(g).to(gpu)
+    for prec in PRECS:
+        img, T, last = api.blend_forward_packed(rec, rg, pl, W, H, (0.0, 0.0, 0.0), prec)
+        grads = api.blend_backward_packed(rec, rg, pl, W, H, T, last, gd, (0.0, 0.0, 0.0), prec)
+        torch.cuda.synchronize()
+        img = img.cpu().numpy().astype(np.float64)
+        T, last = T.cpu().numpy().astype(np.float64), last.cpu().numpy()
+        if prec == "fp32":
+            check_plain(ref, img, T, last, "C5 full frame")
+        else:
+            check_gemm(ref, img, T, last, prec, "C5 full frame")
+        bound = plain_grad_bound("C5") if prec == "fp32" else GEMM_GRAD
+        for k, v in zip(("dmeans2d", "dconics", "dopacity", "dcolors"), grads):
+            e = normwise(v.cpu().numpy().astype(np.float64), gref[k])
+            say(f"  C5 full frame bwd {prec} {k}: {e:.3e}")
+            assert e <= bound, (prec, k, e)
+
+
 def test_c5_4k_sampled_tiles(gpu):
     """The largest workload (3840x2160, 3M Gaussians) at full size in the benchmark's launch
     configuration: GPU binning of the whole frame, checked bit-exactly against the oracle's lists of
