@@ -410,7 +410,7 @@ def run_sweeps(dev, steps: int, warmup: int) -> dict:
     """Sensitivity sweeps on the 1080p scene: (1) forward and backward time per LDS batch size
     b (single-view plans with fixed launch shapes), (2) the same scene rendered at 1x, 2x and 3x
     resolution (means and axis lengths scaled), forward + backward blend time, each in the FP16
-    GEMM form and the plain FP32 form."""
+    GEMM form and the plain FP32 form (reach-culled, and as a full scan)."""
     def upload(sc):
         d = {"width": sc["width"], "height": sc["height"]}
         for k in ("means2d", "conics", "opacity", "colors", "depths", "radii"):
@@ -435,7 +435,7 @@ def run_sweeps(dev, steps: int, warmup: int) -> dict:
     base = gsinputs.make_scene("C2")
     view = upload(base)
     g = torch.from_numpy(gsinputs.make_dloss(base["width"], base["height"], 1002)).to(dev)
-    for prec in ("fp16", "fp32"):
+    for prec in ("fp16", "fp32", "fp32_scan"):
         for nb in (64, 128, 256):
             bv = api.BatchedViews([view], prec=prec,
                                   tuning={"batch_fwd": nb, "batch_bwd": nb, "launch": 1})
@@ -448,12 +448,15 @@ def run_sweeps(dev, steps: int, warmup: int) -> dict:
         sc = gsinputs.make_scene("C2", scale=float(scale))
         fr = Frame.from_scene(sc, dev)
         row = {"scale": scale, "width": sc["width"], "height": sc["height"], "pairs": fr.pairs}
-        for prec in ("fp16", "fp32"):
+        for prec in ("fp16", "fp32", "fp32_scan"):
             r = time_path(fr, prec, steps, warmup)
             row[prec] = {"fwd_ms": round(r["fwd_ms"], 4), "bwd_ms": round(r["bwd_ms"], 4),
                          "blend_mpix_s": round(r["blend_mpix_s"], 2)}
-        row["gemm_speedup_fwd"] = round(row["fp32"]["fwd_ms"] / row["fp16"]["fwd_ms"], 3)
-        row["gemm_speedup_blend"] = round(row["fp16"]["blend_mpix_s"] / row["fp32"]["blend_mpix_s"], 3)
+        for plain in ("fp32", "fp32_scan"):
+            sfx = "" if plain == "fp32" else "_vs_full_scan"
+            row["gemm_speedup_fwd" + sfx] = round(row[plain]["fwd_ms"] / row["fp16"]["fwd_ms"], 3)
+            row["gemm_speedup_blend" + sfx] = round(
+                row["fp16"]["blend_mpix_s"] / row[plain]["blend_mpix_s"], 3)
         out["resolution"].append(row)
         del fr
         torch.cuda.empty_cache()
