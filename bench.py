@@ -50,7 +50,7 @@ METRIC = "Mpix/s fwd+bwd blend, GEMM-form vs plain FP32 on 1 MI355X at ≥50 dB 
 # x 2 (packed) x 2.4 GHz). Packed FP32 is disabled in this build, so the reachable rate is half:
 PEAK_FP32_TFLOPS = 157.3
 PEAK_FP32_NONPACKED_TFLOPS = 256 * 4 * 16 * 2 * 2.4e9 / 1e12
-# Algorithmic operations per evaluated pair, the survey's unit counts for the blend:
+# Algorithmic operations per evaluated pair (unit counts of the blend, fixed in advance):
 #   forward : 1 exp + ~11 VALU (GEMM form; the exponent's 12 MFMA flops not counted here) or
 #             1 exp + ~20 VALU (plain form), per evaluation (E)
 #   backward: 1 exp + 1 rcp + ~30 VALU per revisited evaluation (Eb)
@@ -557,7 +557,7 @@ def traffic_entry(config: str, kern: str, src: str = None):
 
 def roofline(res: dict, counts: dict, config: str, prec: str) -> dict:
     """ALU roofline of the dominant blend kernel (the slower of forward / backward): algorithmic
-    operations per launch (the survey's unit counts x the oracle's evaluation counts) / the
+    operations per launch (the unit counts above x the oracle's evaluation counts) / the
     kernel's mean duration from HIP events over the timed steps, against the published FP32 peak.
     The measured HBM traffic is attached when counters of this workload and kernel source exist."""
     kern = "backward" if res["bwd_ms"] >= res["fwd_ms"] else "forward"

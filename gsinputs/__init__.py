@@ -60,7 +60,7 @@ class SceneConfig:
         return self.width * self.height
 
 
-# The five workloads of the spec configs, by size and law.
+# The five benchmark workloads, by size and law.
 CONFIGS = {
     # 64x64, 2000 G, sigma log-uniform [0.5, 8]
     "C1": SceneConfig("C1", 64, 64, 2_000, "loguniform", 0.5, 8.0, "uniform", 1),
