@@ -430,21 +430,25 @@ struct FwdState {
     int last;
 };
 
-// One front-to-back step (Alg. 1 / Alg. 2 inner loop) for this lane's pixel, without branches:
-// a skipped pair or a finished pixel leaves the state unchanged.
+// One front-to-back step (Alg. 1 / Alg. 2 inner loop) for this lane's pixel: a skipped pair or a
+// finished pixel leaves the state unchanged. The kernel is bound by vector-instruction issue, so
+// the lanes that blend update their state under the execution mask rather than through a select
+// per value. (The end of a pixel stays a select: as a scalar branch on a ballot it costs more
+// than it saves, since the branch waits for the compare.)
 __device__ inline void composite(float q, float lo2o, float cr, float cg, float cb, int pos,
                                  FwdState &st) {
     const bool hit = q >= st.thr;
     const float a = fminf(__builtin_amdgcn_exp2f(fminf(q, lo2o)), kAlphaMax);
     const float Tn = st.T * (1.0f - a);
     const bool stop = Tn < kTStop;
-    const bool blend = hit && !stop;
-    const float wgt = blend ? a * st.T : 0.f;
-    st.r = fmaf(wgt, cr, st.r);
-    st.g = fmaf(wgt, cg, st.g);
-    st.b = fmaf(wgt, cb, st.b);
-    st.T = blend ? Tn : st.T;
-    st.last = blend ? pos + 1 : st.last;
+    if (hit && !stop) {
+        const float wgt = a * st.T;
+        st.r = fmaf(wgt, cr, st.r);
+        st.g = fmaf(wgt, cg, st.g);
+        st.b = fmaf(wgt, cb, st.b);
+        st.T = Tn;
+        st.last = pos + 1;
+    }
     st.thr = (hit && stop) ? INFINITY : st.thr;
 }
 
@@ -460,7 +464,10 @@ __device__ inline void composite_group(const float4 *attr, int base, uint32_t re
         if (((reach >> u) & 1u) == 0u) continue;
         const float q = q_of(u);
         if (__builtin_amdgcn_ballot_w64(q >= st.thr) == 0ull) continue;   // no lane takes it
-        const float4 a = attr[u];      // one address for every lane: an LDS broadcast
+        // one address for every lane (an LDS broadcast), read whole: left to itself the compiler
+        // moves the colour reads into the blending lanes' branch, as separate loads
+        f4x a = *reinterpret_cast<const f4x *>(&attr[u]);
+        asm volatile("" : "+v"(a));
         composite(q, a.x, a.y, a.z, a.w, base + u, st);
     }
 }
@@ -664,14 +671,25 @@ __device__ inline void reverse_pair(float q, bool in_range, const float4 *ga, co
     const float gmb = gc - st.beta;                      // dL/dalpha = Tb (c . g - beta)
     st.beta = fmaf(a, gmb, st.beta);
     st.T = Tb;
-    // dL/dpower = alpha * dL/dalpha unless the 0.99 clamp is active
-    const float da = araw < kAlphaMax ? wc * gmb : 0.f;
-    // no gradient reaches the geometry through a clamped (positive) power
-    const float dg = q > attr.x ? 0.f : da;
+    const float da = wc * gmb;                           // dL/dpower = alpha dL/dalpha
     const float dx = bw.x - L.px, dy = bw.y - L.py;
-    const float tx = dg * dx, ty = dg * dy;
-    const float s[kGrad] = {tx * dx, tx * dy, ty * dy, tx, ty, da,   // dL/do = alpha/o dL/dalpha
-                            wc * st.gr, wc * st.gg, wc * st.gb};
+    const float tx = da * dx, ty = da * dy;
+    float s[kGrad] = {tx * dx, tx * dy, ty * dy, tx, ty, da,   // dL/do = alpha/o dL/dalpha
+                      wc * st.gr, wc * st.gg, wc * st.gb};
+    // The clamps are rare, so one scalar test stands for them and the terms of the live lanes they
+    // touch are zeroed in place: with the 0.99 clamp active dL/dpower is 0, and no gradient
+    // reaches the geometry through a clamped (positive) power. (One ballot per compare, kept
+    // apart by the empty asm statements, as above.)
+    unsigned long long m_a = __builtin_amdgcn_ballot_w64(!(araw < kAlphaMax));
+    unsigned long long m_q = __builtin_amdgcn_ballot_w64(q > attr.x);
+    asm volatile("" : "+s"(m_a));
+    asm volatile("" : "+s"(m_q));
+    if (((m_a | m_q) & live) != 0ull) {
+        const bool keep_a = araw < kAlphaMax, keep_g = keep_a && !(q > attr.x);
+#pragma unroll
+        for (int k = 0; k < 5; ++k) s[k] = keep_g ? s[k] : 0.f;
+        s[5] = keep_a ? s[5] : 0.f;
+    }
     float rab, rc;
     wave_sum9(s, L.l, rab, rc);
     if ((L.l & 7) == 0) {
@@ -1026,13 +1044,20 @@ __device__ inline void bwd_tile(const ViewDesc &v, int64_t tile, Stage<M, NB> &S
             if (__ballot(st.last > base + g * kGroup) == 0) continue;
             const uint32_t reach = group_reach<M, NB>(S, buf, L.w, g);
             if (reach == 0u) continue;
-            const float4 *ga = &S.attr[buf][g * kGroup];   // the group's staged values
-            const float2 *gb = &SB.bwd[buf][g * kGroup];
+            // the group's first slot, held in a vector register: each Gaussian's LDS addresses are
+            // then immediate offsets from it (from a scalar base the compiler copies the base
+            // into a vector register again for every Gaussian)
+            int slot0 = g * kGroup;
+            asm volatile("" : "+v"(slot0));
+            const float4 *ga = &S.attr[buf][slot0];   // the group's staged values
+            const float2 *gb = &SB.bwd[buf][slot0];
             // the group's sums, Gaussian 0 (deterministic: this wavefront's slice)
             float *accw = kDet ? det->v[buf][L.w] + g * kGroup * kGrad
                                : acc_->slot(buf, g * kGroup);
             float *acc = accw + (kMM ? 0 : word);   // this lane's word (VALU reduction)
-            uint8_t *hit = kDet ? nullptr : &acc_->hit[buf][g * kGroup];
+            int hslot = buf * NB + slot0;      // (likewise for the flags, written in a branch)
+            asm volatile("" : "+v"(hslot));
+            uint8_t *hit = kDet ? nullptr : reinterpret_cast<uint8_t *>(acc_->hit) + hslot;
             const int rel = st.last - (base + g * kGroup);   // positions < last are in range
             // the whole group is in range for every lane (the common case once past the lanes'
             // last contributors; never for a partial tile, whose outside lanes have last = 0)
@@ -1040,7 +1065,7 @@ __device__ inline void bwd_tile(const ViewDesc &v, int64_t tile, Stage<M, NB> &S
             f16x qm;
             if constexpr (M != Mode::Plain) qm = group_q_mfma<M, NB>(S, buf, g, L, bhi, blo);
             const auto q_of = [&](int u) {
-                if constexpr (M == Mode::Plain) return plain_q(S, buf, g * kGroup + u, L);
+                if constexpr (M == Mode::Plain) return plain_q(S, buf, slot0 + u, L);
                 else return qm[u];
             };
             if constexpr (kMM) {
