@@ -626,9 +626,9 @@ struct BwdState {
 };
 
 // Reverse step for one (Gaussian, pixel) pair. Nothing but a compare and a scalar branch is
-// spent when no lane of the wave has a live pair. Otherwise every lane evaluates the step without
-// branches (a dead lane takes alpha = 0: its terms vanish and its state is unchanged exactly,
-// since 1 / (1 - 0) = 1),
+// spent when no lane of the wave has a live pair. Otherwise every lane evaluates the step, with no
+// branch but a rare one for the clamps (a dead lane takes alpha = 0: its terms vanish and its
+// state is unchanged exactly, since 1 / (1 - 0) = 1),
 // the pair's 9 gradient terms are summed over the wavefront, and the totals are added into the
 // Gaussian's LDS accumulator (`acc` points at the word this lane adds when it leads, see
 // sum_word; the flag `hit` is set), which the block flushes to global memory once per batch. Raw
