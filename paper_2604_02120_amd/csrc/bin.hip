@@ -15,6 +15,7 @@
 #include <hip/hip_runtime.h>
 
 #include <mutex>
+#include <type_traits>
 #include <utility>
 
 #include "gsb_internal.h"
@@ -38,6 +39,21 @@ constexpr int kRadixBits = 8;
 constexpr int kRadix = 1 << kRadixBits;
 
 constexpr int kBigRect = 32;   // mode 0: rectangles with more tiles are emitted by the whole wavefront
+
+// The tile sort's keys are tile ids: 16-bit when the grid has at most 65536 tiles (a 4096 x 4096
+// image), which cuts the bytes of the pair emission, the sort passes and the range pass, and
+// 32-bit otherwise. The pair order is the same either way.
+constexpr int64_t kMaxTiles16 = int64_t(1) << 16;
+
+// Four consecutive keys [idx, idx + 4) with one vector load (idx a multiple of 4; key buffers are
+// 256-byte aligned and padded, so a load that straddles the count stays inside the buffer).
+__device__ inline uint4 load4(const uint32_t *k, int64_t idx) {
+    return *reinterpret_cast<const uint4 *>(k + idx);
+}
+__device__ inline uint4 load4(const uint16_t *k, int64_t idx) {
+    const uint2 v = *reinterpret_cast<const uint2 *>(k + idx);
+    return make_uint4(v.x & 0xffffu, v.x >> 16, v.y & 0xffffu, v.y >> 16);
+}
 
 
 struct BinHeader {
@@ -491,22 +507,25 @@ __device__ inline uint32_t depth_key(float d) {
 // together, one after the other.
 constexpr int kFillStage = 4096;   // pairs staged per block
 
-struct PairSink {
-    uint32_t *keys, *vals;           // global
-    uint32_t *skey, *sval;           // LDS segment, or null
+template <typename K> struct PairSink {
+    K *keys;                         // global
+    uint32_t *vals;
+    K *skey;                         // LDS segment, or null
+    uint32_t *sval;
     unsigned long long seg0, cap;    // first output index of the block, capacity
     __device__ inline void put(unsigned long long o, uint32_t key, uint32_t val) const {
         if (skey) {
             if (o - seg0 >= (unsigned long long)kFillStage) return;   // never for consistent counts
-            skey[o - seg0] = key;
+            skey[o - seg0] = K(key);
             sval[o - seg0] = val;
         } else if (o < cap) {
-            keys[o] = key;
+            keys[o] = K(key);
             vals[o] = val;
         }
     }
 };
 
+template <typename K>
 __global__ __launch_bounds__(256) void k_bin_fill(const float2 *means, const int32_t *radii,
                                                   const float *conics, const float *opac,
                                                   int32_t mode, int32_t W, int32_t H,
@@ -515,9 +534,10 @@ __global__ __launch_bounds__(256) void k_bin_fill(const float2 *means, const int
                                                   const unsigned long long *offs,
                                                   const unsigned long long *counts,
                                                   const unsigned long long *masks, BinHeader *hdr,
-                                                  int64_t cap, uint32_t *keys, uint32_t *vals,
+                                                  int64_t cap, K *keys, uint32_t *vals,
                                                   int32_t *status) {
-    __shared__ uint32_t s_key[kFillStage], s_val[kFillStage];
+    __shared__ K s_key[kFillStage];
+    __shared__ uint32_t s_val[kFillStage];
     const int64_t j = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
     if (j == 0) {
         const unsigned long long total = hdr->total;
@@ -548,7 +568,7 @@ __global__ __launch_bounds__(256) void k_bin_fill(const float2 *means, const int
     const unsigned long long seg1 = offs[jl] + counts[sorted_idx[jl]];
     const unsigned long long ucap = (unsigned long long)cap;
     const bool staged = (seg1 - seg0) <= (unsigned long long)kFillStage && seg1 <= ucap;
-    const PairSink sink{keys, vals, staged ? s_key : nullptr, staged ? s_val : nullptr, seg0, ucap};
+    const PairSink<K> sink{keys, vals, staged ? s_key : nullptr, staged ? s_val : nullptr, seg0, ucap};
 
     const int w = R.tx1 - R.tx0;
     const int area = w * (R.ty1 - R.ty0);
@@ -702,7 +722,8 @@ __global__ __launch_bounds__(kSortThreads) void k_sort_hist(const float *depths,
 
 // Per-block digit histogram of one pass, stored digit-major ([digit][block]) so that one
 // exclusive scan yields every block's output offset per digit.
-__global__ __launch_bounds__(kSortThreads) void k_block_hist(const uint32_t *keys,
+template <typename K>
+__global__ __launch_bounds__(kSortThreads) void k_block_hist(const K *keys,
                                                              const unsigned long long *count,
                                                              int shift, uint32_t *hist,
                                                              int64_t nblk) {
@@ -712,13 +733,12 @@ __global__ __launch_bounds__(kSortThreads) void k_block_hist(const uint32_t *key
     __syncthreads();
     const int64_t P = int64_t(*count);
     const int64_t base = int64_t(blockIdx.x) * kSortTile;
-    // 16-byte loads (order does not matter to a histogram). The key buffers are 256-byte aligned
-    // and padded to 256 bytes, so a load that straddles P stays inside; entries >= P are ignored.
+    // four keys per load (order does not matter to a histogram); entries >= P are ignored
 #pragma unroll
     for (int k = 0; k < kSortItems / 4; ++k) {
         const int64_t idx = base + 4 * (int64_t(k) * kSortThreads + t);
         if (idx < P) {
-            const uint4 v = *reinterpret_cast<const uint4 *>(keys + idx);
+            const uint4 v = load4(keys, idx);
             atomicAdd(&s_h[(v.x >> shift) & (kRadix - 1)], 1u);
             if (idx + 1 < P) atomicAdd(&s_h[(v.y >> shift) & (kRadix - 1)], 1u);
             if (idx + 2 < P) atomicAdd(&s_h[(v.z >> shift) & (kRadix - 1)], 1u);
@@ -741,9 +761,9 @@ __device__ inline uint32_t lb_read(const uint32_t *w) {
 // kChained: the block's tile comes from `ticket` and its digit offsets from the look-back over
 // `lookback` plus the pass's digit counts `ghist`; otherwise tile = blockIdx.x and the offsets are
 // read from `hist_off` ([digit][block], the exclusive scan of the per-block histograms).
-template <bool kChained, bool kRankCounts>
+template <bool kChained, bool kRankCounts, typename K = uint32_t>
 __global__ __launch_bounds__(kSortThreads) void k_radix_pass(
-    const uint32_t *kin, const uint32_t *vin, uint32_t *kout, uint32_t *vout,
+    const K *kin, const uint32_t *vin, K *kout, uint32_t *vout,
     const unsigned long long *count, int shift, const uint32_t *ghist, uint32_t *lookback,
     uint32_t *ticket, int32_t *status, const uint32_t *hist_off, int64_t nblk,
     const unsigned long long *counts_by_idx, unsigned long long *rank_counts) {
@@ -751,7 +771,7 @@ __global__ __launch_bounds__(kSortThreads) void k_radix_pass(
     __shared__ uint32_t s_dstart[kRadix];                     // block-local start of each digit
     __shared__ uint32_t s_gofs[kRadix];                       // global start of each digit
     __shared__ uint32_t s_wave[kSortThreads / 64];
-    __shared__ uint32_t s_key[kSortTile];
+    __shared__ K s_key[kSortTile];
     __shared__ uint32_t s_val[kSortTile];
     __shared__ uint32_t s_tile;
 
@@ -773,7 +793,7 @@ __global__ __launch_bounds__(kSortThreads) void k_radix_pass(
     for (int k = 0; k < kSortItems; ++k) {
         const int64_t idx = base + int64_t(w) * (kSortItems * 64) + k * 64 + lane;
         const bool valid = idx < P;
-        key[k] = valid ? kin[idx] : 0u;
+        key[k] = valid ? uint32_t(kin[idx]) : 0u;
         val[k] = valid ? vin[idx] : 0u;
         const uint32_t d = (key[k] >> shift) & (kRadix - 1);
         // lanes holding the same digit: intersect the ballots of every digit bit
@@ -848,15 +868,15 @@ __global__ __launch_bounds__(kSortThreads) void k_radix_pass(
         if (idx < P) {
             const uint32_t d = (key[k] >> shift) & (kRadix - 1);
             const uint32_t r = s_dstart[d] + s_wcnt[w][d] + loc[k];
-            s_key[r] = key[k];
+            s_key[r] = K(key[k]);
             s_val[r] = val[k];
         }
     }
     __syncthreads();
     const int64_t nvalid = (P - base) < kSortTile ? (P - base) : kSortTile;
     for (int64_t j = t; j < nvalid; j += kSortThreads) {
-        const uint32_t k = s_key[j];
-        const uint32_t d = (k >> shift) & (kRadix - 1);
+        const K k = s_key[j];
+        const uint32_t d = (uint32_t(k) >> shift) & (kRadix - 1);
         const int64_t pos = int64_t(s_gofs[d]) + (j - int64_t(s_dstart[d]));
         kout[pos] = k;
         vout[pos] = s_val[j];
@@ -898,18 +918,20 @@ void sort_depth(const float *depths, uint32_t *ka, uint32_t *kb, uint32_t *va, u
 // histogram, its exclusive scan and the scatter. (With thousands of tiles of keys the chained
 // passes wait on long look-back chains; the three-step pass does not.) The data ends in (ka, va)
 // after an even number of passes, in (kb, vb) after an odd one; returns the number of passes.
-int sort_tiles(uint32_t *ka, uint32_t *kb, uint32_t *va, uint32_t *vb,
-               const unsigned long long *count, int64_t cap, int bits, uint32_t *hist,
-               uint32_t *partial, int32_t *status, hipStream_t s) {
+template <typename K>
+int sort_tiles(K *ka, K *kb, uint32_t *va, uint32_t *vb, const unsigned long long *count,
+               int64_t cap, int bits, uint32_t *hist, uint32_t *partial, int32_t *status,
+               hipStream_t s) {
     const int64_t nblk = sort_blocks(cap);
     const int passes = (bits + kRadixBits - 1) / kRadixBits;
     if (nblk == 0) return passes;
-    uint32_t *kin = ka, *kout = kb, *vin = va, *vout = vb;
+    K *kin = ka, *kout = kb;
+    uint32_t *vin = va, *vout = vb;
     for (int p = 0; p < passes; ++p) {
         const int shift = p * kRadixBits;
         k_block_hist<<<dim3(unsigned(nblk)), kSortThreads, 0, s>>>(kin, count, shift, hist, nblk);
         launch_scan<uint32_t>(hist, int64_t(kRadix) * nblk, partial, nullptr, nullptr, s);
-        k_radix_pass<false, false><<<dim3(unsigned(nblk)), kSortThreads, 0, s>>>(
+        k_radix_pass<false, false, K><<<dim3(unsigned(nblk)), kSortThreads, 0, s>>>(
             kin, vin, kout, vout, count, shift, nullptr, nullptr, nullptr, status, hist, nblk,
             nullptr, nullptr);
         std::swap(kin, kout);
@@ -934,9 +956,10 @@ __global__ __launch_bounds__(256) void k_bin_init(uint32_t *ranges, int64_t m, S
     }
 }
 
-// Tile boundaries in the sorted tile ids: four consecutive pairs per thread (one 16-byte load and
-// the two neighbours outside it). `tiles` is 16-byte aligned.
-__global__ __launch_bounds__(256) void k_ranges(const uint32_t *tiles, const unsigned long long *count,
+// Tile boundaries in the sorted tile ids: four consecutive pairs per thread (one vector load and
+// the two neighbours outside it). `tiles` is 256-byte aligned.
+template <typename K>
+__global__ __launch_bounds__(256) void k_ranges(const K *tiles, const unsigned long long *count,
                                                 uint32_t *ranges) {
     const int64_t P = int64_t(*count);
     const int64_t i0 = 4 * (int64_t(blockIdx.x) * blockDim.x + threadIdx.x);
@@ -944,7 +967,7 @@ __global__ __launch_bounds__(256) void k_ranges(const uint32_t *tiles, const uns
     uint32_t t[6];                       // tiles[i0 - 1 .. i0 + 4]; outside [0, P): no tile
     t[0] = i0 > 0 ? tiles[i0 - 1] : 0xffffffffu;
     if (i0 + 4 <= P) {
-        const uint4 v = *reinterpret_cast<const uint4 *>(tiles + i0);
+        const uint4 v = load4(tiles, i0);
         t[1] = v.x; t[2] = v.y; t[3] = v.z; t[4] = v.w;
     } else {
 #pragma unroll
@@ -1009,7 +1032,6 @@ gsb_status bin_fill(const float *means2d, const int32_t *radii, const float *con
     uint32_t *dka = at<uint32_t>(ws, L.dkey_a), *dkb = at<uint32_t>(ws, L.dkey_b);
     uint32_t *dva = at<uint32_t>(ws, L.dval_a), *dvb = at<uint32_t>(ws, L.dval_b);
     auto *offs = at<unsigned long long>(ws, L.offs);
-    uint32_t *tka = at<uint32_t>(ws, L.tkey_a), *tkb = at<uint32_t>(ws, L.tkey_b);
     uint32_t *vtmp = at<uint32_t>(ws, L.vals_tmp);
     const int32_t gx = int32_t(grid_x(W)), gy = int32_t(grid_y(H));
     const int64_t n_tiles = int64_t(gx) * gy;
@@ -1029,17 +1051,24 @@ gsb_status bin_fill(const float *means2d, const int32_t *radii, const float *con
     // the last pass must land the values in point_list
     uint32_t *v_first = (tp % 2 == 0) ? point_list : vtmp;
     uint32_t *v_second = (tp % 2 == 0) ? vtmp : point_list;
-    k_bin_fill<<<gn, 256, 0, s>>>(reinterpret_cast<const float2 *>(means2d), radii, conics, opacity,
-                                  mode, W, H, sorted_idx, n, gx, gy, offs, counts,
-                                  at<unsigned long long>(ws, L.masks), hdr, cap, tka, v_first,
-                                  status_dev);
-    // 3. stable sort of the pairs on the tile id
-    sort_tiles(tka, tkb, v_first, v_second, &hdr->pairs, cap, tile_bits, sortbuf, partial32,
-               status_dev, s);
-    const uint32_t *tiles_sorted = (tp % 2 == 0) ? tka : tkb;
-    if (cap > 0)
-        k_ranges<<<dim3(unsigned((cap + 1023) / 1024)), 256, 0, s>>>(tiles_sorted, &hdr->pairs,
-                                                                      ranges);
+    // 3. stable sort of the pairs on the tile id; 4. the tiles' ranges
+    const auto emit_sort_range = [&](auto *tka, auto *tkb) {
+        using K = std::remove_pointer_t<decltype(tka)>;
+        k_bin_fill<K><<<gn, 256, 0, s>>>(reinterpret_cast<const float2 *>(means2d), radii, conics,
+                                         opacity, mode, W, H, sorted_idx, n, gx, gy, offs, counts,
+                                         at<unsigned long long>(ws, L.masks), hdr, cap, tka,
+                                         v_first, status_dev);
+        sort_tiles<K>(tka, tkb, v_first, v_second, &hdr->pairs, cap, tile_bits, sortbuf,
+                      partial32, status_dev, s);
+        const K *tiles_sorted = (tp % 2 == 0) ? tka : tkb;
+        if (cap > 0)
+            k_ranges<K><<<dim3(unsigned((cap + 1023) / 1024)), 256, 0, s>>>(tiles_sorted,
+                                                                             &hdr->pairs, ranges);
+    };
+    if (n_tiles <= kMaxTiles16)
+        emit_sort_range(at<uint16_t>(ws, L.tkey_a), at<uint16_t>(ws, L.tkey_b));
+    else
+        emit_sort_range(at<uint32_t>(ws, L.tkey_a), at<uint32_t>(ws, L.tkey_b));
     return check_launch("bin_fill");
 }
 
@@ -1058,13 +1087,14 @@ int pair_sort(uint32_t *ka, uint32_t *kb, uint32_t *va, uint32_t *vb,
     uint32_t *partial = reinterpret_cast<uint32_t *>(
         static_cast<char *>(scratch) +
         align256(sizeof(uint32_t) * kRadix * size_t(sort_blocks(cap > 0 ? cap : 1))));
-    return sort_tiles(ka, kb, va, vb, count, cap, bits, hist, partial, nullptr, s);
+    return sort_tiles<uint32_t>(ka, kb, va, vb, count, cap, bits, hist, partial, nullptr, s);
 }
 
 void key_ranges(const uint32_t *sorted_keys, const unsigned long long *count, int64_t cap,
                 uint32_t *ranges, hipStream_t s) {
     if (cap > 0)
-        k_ranges<<<dim3(unsigned((cap + 1023) / 1024)), 256, 0, s>>>(sorted_keys, count, ranges);
+        k_ranges<uint32_t><<<dim3(unsigned((cap + 1023) / 1024)), 256, 0, s>>>(sorted_keys, count,
+                                                                                ranges);
 }
 
 // ------------------------------------------------------------------------------- no-alloc binning

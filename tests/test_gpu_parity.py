@@ -443,6 +443,34 @@ def test_three_tile_sort_passes(gpu):
             check_plain(ref, img, T, last, "66k tiles")
 
 
+def test_largest_16bit_tile_grid(gpu):
+    """65536 tiles (4096 x 4096 pixels) is the largest grid whose tile ids the binning sorts as
+    16-bit keys; tile 65535 (the bottom-right corner, all 16 bits set) must land in place. Extra
+    Gaussians around that corner and along the last row and column, then both binning modes bit for
+    bit over the whole frame."""
+    cfg = gsinputs.SceneConfig("tiles65536", 4096, 4096, 20000, "loguniform", 0.5, 8.0, "uniform", 48)
+    s = gsinputs.make_scene(cfg)
+    W, H = s["width"], s["height"]
+    gx, gy = oracle.grid(W, H)
+    assert gx * gy == 65536
+    rng = np.random.default_rng(480)
+    k = 2000                       # centres within 40 px of the right or bottom edge
+    edge = rng.uniform(W - 40.0, W + 8.0, k).astype(np.float32)
+    along = rng.uniform(0.0, W, k).astype(np.float32)
+    s["means2d"][:k, 0] = np.where(np.arange(k) % 2 == 0, edge, along)
+    s["means2d"][:k, 1] = np.where(np.arange(k) % 2 == 0, along, edge)
+    s["means2d"][k:k + 50] = np.float32(W - 3.0)
+    say(f"[bin] {W}x{H} ({gx * gy} tiles) n={len(s['radii'])}")
+    sd = upload(s, gpu)
+    for mode, omode in (("rect", oracle.BIN_RECT), ("visible", oracle.BIN_VISIBLE)):
+        pl_ref, rg_ref = oracle.bin_tiles(s["means2d"], s["radii"], s["depths"], W, H,
+                                          s["conics"], s["opacity"], omode)
+        assert rg_ref[65535, 1] > rg_ref[65535, 0]      # the last tile has pairs
+        pl, rg = gpu_bins(sd, mode)
+        np.testing.assert_array_equal(rg.cpu().numpy().astype(np.uint32), rg_ref)
+        np.testing.assert_array_equal(pl.cpu().numpy().astype(np.uint32), pl_ref)
+
+
 # ----------------------------------------------------------------------------- backward reduction
 def plan_grads(sd, prec, g, bg, bwd_reduce, batch_bwd=128):
     """Gradients from a one-view plan (one block per tile) with the given backward reduction."""
