@@ -786,28 +786,38 @@ __global__ __launch_bounds__(kSortThreads) void k_radix_pass(
     if (base >= P) return;   // block-uniform; every later ticket is empty too
 
     // Wave w ranks keys [base + 1024 w, base + 1024 (w + 1)) in 16 steps of 64 consecutive keys,
-    // so rank order within the wave is index order.
-    const unsigned long long lt_mask = (1ull << lane) - 1ull;
+    // so rank order within the wave is index order. All loads are issued first, from an index
+    // clamped into [base, P) (validity applied afterwards), so that they are in flight together.
     uint32_t key[kSortItems], val[kSortItems], loc[kSortItems];
 #pragma unroll
     for (int k = 0; k < kSortItems; ++k) {
         const int64_t idx = base + int64_t(w) * (kSortItems * 64) + k * 64 + lane;
+        const int64_t ci = idx < P ? idx : P - 1;   // P > base here
+        key[k] = uint32_t(kin[ci]);
+        val[k] = vin[ci];
+    }
+#pragma unroll
+    for (int k = 0; k < kSortItems; ++k) {
+        const int64_t idx = base + int64_t(w) * (kSortItems * 64) + k * 64 + lane;
         const bool valid = idx < P;
-        key[k] = valid ? uint32_t(kin[idx]) : 0u;
-        val[k] = valid ? vin[idx] : 0u;
         const uint32_t d = (key[k] >> shift) & (kRadix - 1);
-        // lanes holding the same digit: intersect the ballots of every digit bit
-        unsigned long long peers = __ballot(valid);
+        // lanes holding the same digit: intersect, over the digit's bits, the lanes whose bit
+        // equals this lane's (the ballot of the set bits, flipped where this lane's bit is clear),
+        // on the two 32-bit halves of the mask
+        const unsigned long long vmask = __builtin_amdgcn_ballot_w64(valid);
+        uint32_t plo = uint32_t(vmask), phi = uint32_t(vmask >> 32);
+        const uint32_t nd = ~d;
 #pragma unroll
         for (int b = 0; b < kRadixBits; ++b) {
-            const bool bit = (d >> b) & 1u;
-            const unsigned long long vote = __ballot(bit);
-            peers &= bit ? vote : ~vote;
+            const uint32_t flip = uint32_t(int32_t(nd << (31 - b)) >> 31);  // ones if bit b clear
+            const unsigned long long vote = __builtin_amdgcn_ballot_w64(flip == 0u);
+            plo &= uint32_t(vote) ^ flip;
+            phi &= uint32_t(vote >> 32) ^ flip;
         }
-        const uint32_t rank = __popcll(peers & lt_mask);
+        const uint32_t rank = __builtin_amdgcn_mbcnt_hi(phi, __builtin_amdgcn_mbcnt_lo(plo, 0u));
         uint32_t prior = 0;
         if (valid) prior = s_wcnt[w][d];
-        if (valid && rank == 0) s_wcnt[w][d] = prior + uint32_t(__popcll(peers));
+        if (valid && rank == 0) s_wcnt[w][d] = prior + uint32_t(__popc(plo) + __popc(phi));
         loc[k] = prior + rank;
     }
     __syncthreads();
