@@ -76,9 +76,9 @@ size_t align256(size_t b) { return (b + 255) & ~size_t(255); }
 
 struct Layout {
     // bin_count's part (depends on n only)
-    size_t hdr, counts, masks, partials;
+    size_t hdr, counts, masks, recs, partials;
     // bin_fill's part
-    size_t sorts, dkey_a, dkey_b, dval_a, dval_b, offs, tkey_a, tkey_b, vals_tmp, sortbuf, end;
+    size_t sorts, dkey_a, dkey_b, dval_a, dval_b, offs, rects, tkey_a, tkey_b, vals_tmp, sortbuf, end;
 };
 
 int64_t sort_blocks(int64_t m) { return (m + kSortTile - 1) / kSortTile; }
@@ -90,6 +90,7 @@ Layout layout(int64_t n, int64_t cap) {
     L.hdr = o;       o += align256(sizeof(BinHeader));
     L.counts = o;    o += align256(sizeof(unsigned long long) * nn);
     L.masks = o;     o += align256(sizeof(unsigned long long) * nn);
+    L.recs = o;      o += align256(sizeof(uint4) * nn);
     L.partials = o;  o += align256(sizeof(unsigned long long) * kScanMaxBlocks);
     L.sorts = o;     o += align256(sizeof(SortState));
     L.dkey_a = o;    o += align256(sizeof(uint32_t) * nn);
@@ -97,6 +98,7 @@ Layout layout(int64_t n, int64_t cap) {
     L.dval_a = o;    o += align256(sizeof(uint32_t) * nn);
     L.dval_b = o;    o += align256(sizeof(uint32_t) * nn);
     L.offs = o;      o += align256(sizeof(unsigned long long) * nn);
+    L.rects = o;     o += align256(sizeof(unsigned long long) * nn);
     L.tkey_a = o;    o += align256(sizeof(uint32_t) * cc);
     L.tkey_b = o;    o += align256(sizeof(uint32_t) * cc);
     L.vals_tmp = o;  o += align256(sizeof(uint32_t) * cc);
@@ -436,19 +438,35 @@ __device__ inline unsigned long long owner_run(uint32_t excl, uint32_t area, uin
 // Pair counts per Gaussian. Mode 0: the rectangle's area. Mode 1: its visible candidates, with
 // the candidates of each wavefront balanced over its lanes; a Gaussian with at most kMaskBits
 // candidates also records which ones are visible (masks).
+// A Gaussian's pair count and emission rectangle in one 16-byte record, stored by Gaussian index:
+// the depth sort's last pass gathers both with one load and lays them out in rank order, so that
+// the pair emission reads them in order instead of gathering means and radii by rank. Tile
+// coordinates are at most 4096 and fit 16 bits.
+__device__ inline uint4 count_rect(unsigned long long cnt, const Rect &R) {
+    return make_uint4(uint32_t(cnt), uint32_t(cnt >> 32), uint32_t(R.tx0) | (uint32_t(R.tx1) << 16),
+                      uint32_t(R.ty0) | (uint32_t(R.ty1) << 16));
+}
+__device__ inline Rect unpack_rect(unsigned long long p) {
+    const uint32_t x = uint32_t(p), y = uint32_t(p >> 32);
+    return Rect{int32_t(x & 0xffffu), int32_t(x >> 16), int32_t(y & 0xffffu), int32_t(y >> 16)};
+}
+
 __global__ __launch_bounds__(256) void k_bin_count(const float2 *means, const int32_t *radii,
                                                    const float *conics, const float *opac,
                                                    int32_t mode, int64_t n, int32_t gx,
                                                    int32_t gy, int32_t W, int32_t H,
                                                    unsigned long long *counts,
-                                                   unsigned long long *masks) {
+                                                   unsigned long long *masks, uint4 *recs) {
     __shared__ GaussVis s_vis[256];
     const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
     if (mode == 0) {
         if (i >= n) return;
         const float2 m = means[i];
         const Rect R = tile_rect(m.x, m.y, radii[i], gx, gy);
-        counts[i] = (unsigned long long)(R.tx1 - R.tx0) * (unsigned long long)(R.ty1 - R.ty0);
+        const unsigned long long cnt =
+            (unsigned long long)(R.tx1 - R.tx0) * (unsigned long long)(R.ty1 - R.ty0);
+        counts[i] = cnt;
+        recs[i] = count_rect(cnt, R);
         return;
     }
     if (int64_t(blockIdx.x) * blockDim.x >= n) return;   // block-uniform
@@ -490,6 +508,7 @@ __global__ __launch_bounds__(256) void k_bin_count(const float2 *means, const in
     if (valid) {
         counts[i] = cnt;
         masks[i] = mask;
+        recs[i] = count_rect(cnt, CR);
     }
 }
 
@@ -526,16 +545,17 @@ template <typename K> struct PairSink {
 };
 
 template <typename K>
-__global__ __launch_bounds__(256) void k_bin_fill(const float2 *means, const int32_t *radii,
-                                                  const float *conics, const float *opac,
+__global__ __launch_bounds__(256) void k_bin_fill(const float2 *means, const float *conics,
+                                                  const float *opac,
                                                   int32_t mode, int32_t W, int32_t H,
                                                   const uint32_t *sorted_idx, int64_t n,
                                                   int32_t gx, int32_t gy,
                                                   const unsigned long long *offs,
                                                   const unsigned long long *counts,
-                                                  const unsigned long long *masks, BinHeader *hdr,
-                                                  int64_t cap, K *keys, uint32_t *vals,
-                                                  int32_t *status) {
+                                                  const unsigned long long *masks,
+                                                  const unsigned long long *rank_rects,
+                                                  BinHeader *hdr, int64_t cap, K *keys,
+                                                  uint32_t *vals, int32_t *status) {
     __shared__ K s_key[kFillStage];
     __shared__ uint32_t s_val[kFillStage];
     const int64_t j = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
@@ -548,17 +568,16 @@ __global__ __launch_bounds__(256) void k_bin_fill(const float2 *means, const int
     if (j0 >= n) return;   // block-uniform (only the single block of an empty launch)
     const bool valid = j < n;
     const uint32_t i = valid ? sorted_idx[j] : 0u;
-    // the rectangle to emit from: mode 0 the 3-sigma one, mode 1 the candidates (cand_rect)
+    // the rectangle to emit from (laid out in rank order by the depth sort): mode 0 the 3-sigma
+    // one, mode 1 the candidates (cand_rect)
     Rect R{0, 0, 0, 0};
     GaussVis g{};
     unsigned long long base = 0, vmask = 0;
     if (valid) {
-        const float2 m = means[i];
-        R = tile_rect(m.x, m.y, radii[i], gx, gy);
+        R = unpack_rect(rank_rects[j]);
         base = offs[j];
         if (mode != 0) {
-            g = vis_setup(m, conics + 3 * int64_t(i), opac[i]);
-            R = cand_rect(g, R);
+            g = vis_setup(means[i], conics + 3 * int64_t(i), opac[i]);
             vmask = masks[i];
         }
     }
@@ -757,7 +776,8 @@ __device__ inline uint32_t lb_read(const uint32_t *w) {
 }
 
 // kRankCounts (last pass of the depth sort): also writes, at each Gaussian's rank, the number of
-// pairs it emits (counts_by_idx[value]) into rank_counts.
+// pairs it emits and its emission rectangle (from the record recs_by_idx[value]) into
+// rank_counts and rank_rects.
 // kChained: the block's tile comes from `ticket` and its digit offsets from the look-back over
 // `lookback` plus the pass's digit counts `ghist`; otherwise tile = blockIdx.x and the offsets are
 // read from `hist_off` ([digit][block], the exclusive scan of the per-block histograms).
@@ -766,7 +786,7 @@ __global__ __launch_bounds__(kSortThreads) void k_radix_pass(
     const K *kin, const uint32_t *vin, K *kout, uint32_t *vout,
     const unsigned long long *count, int shift, const uint32_t *ghist, uint32_t *lookback,
     uint32_t *ticket, int32_t *status, const uint32_t *hist_off, int64_t nblk,
-    const unsigned long long *counts_by_idx, unsigned long long *rank_counts) {
+    const uint4 *recs_by_idx, unsigned long long *rank_counts, unsigned long long *rank_rects) {
     __shared__ uint32_t s_wcnt[kSortThreads / 64][kRadix];  // per-wave digit counts, then prefixes
     __shared__ uint32_t s_dstart[kRadix];                     // block-local start of each digit
     __shared__ uint32_t s_gofs[kRadix];                       // global start of each digit
@@ -890,7 +910,11 @@ __global__ __launch_bounds__(kSortThreads) void k_radix_pass(
         const int64_t pos = int64_t(s_gofs[d]) + (j - int64_t(s_dstart[d]));
         kout[pos] = k;
         vout[pos] = s_val[j];
-        if constexpr (kRankCounts) rank_counts[pos] = counts_by_idx[s_val[j]];
+        if constexpr (kRankCounts) {
+            const uint4 r = recs_by_idx[s_val[j]];
+            rank_counts[pos] = (static_cast<unsigned long long>(r.y) << 32) | r.x;
+            rank_rects[pos] = (static_cast<unsigned long long>(r.w) << 32) | r.z;
+        }
     }
 }
 
@@ -899,8 +923,8 @@ __global__ __launch_bounds__(kSortThreads) void k_radix_pass(
 // (rank_counts). The sorted indices end in va (4 passes, an even number).
 void sort_depth(const float *depths, uint32_t *ka, uint32_t *kb, uint32_t *va, uint32_t *vb,
                 const unsigned long long *count, int64_t n, SortState *st, uint32_t *lookback,
-                int32_t *status, const unsigned long long *counts_by_idx,
-                unsigned long long *rank_counts, hipStream_t s) {
+                int32_t *status, const uint4 *recs_by_idx, unsigned long long *rank_counts,
+                unsigned long long *rank_rects, hipStream_t s) {
     constexpr int passes = 32 / kRadixBits;
     const int64_t nblk = sort_blocks(n);
     if (nblk == 0) return;
@@ -914,11 +938,11 @@ void sort_depth(const float *depths, uint32_t *ka, uint32_t *kb, uint32_t *va, u
         if (p == passes - 1)
             k_radix_pass<true, true><<<dim3(unsigned(nblk)), kSortThreads, 0, s>>>(
                 kin, vin, kout, vout, count, shift, st->hist[p], lb, &st->ticket[p], status,
-                nullptr, nblk, counts_by_idx, rank_counts);
+                nullptr, nblk, recs_by_idx, rank_counts, rank_rects);
         else
             k_radix_pass<true, false><<<dim3(unsigned(nblk)), kSortThreads, 0, s>>>(
                 kin, vin, kout, vout, count, shift, st->hist[p], lb, &st->ticket[p], status,
-                nullptr, nblk, nullptr, nullptr);
+                nullptr, nblk, nullptr, nullptr, nullptr);
         std::swap(kin, kout);
         std::swap(vin, vout);
     }
@@ -943,7 +967,7 @@ int sort_tiles(K *ka, K *kb, uint32_t *va, uint32_t *vb, const unsigned long lon
         launch_scan<uint32_t>(hist, int64_t(kRadix) * nblk, partial, nullptr, nullptr, s);
         k_radix_pass<false, false, K><<<dim3(unsigned(nblk)), kSortThreads, 0, s>>>(
             kin, vin, kout, vout, count, shift, nullptr, nullptr, nullptr, status, hist, nblk,
-            nullptr, nullptr);
+            nullptr, nullptr, nullptr);
         std::swap(kin, kout);
         std::swap(vin, vout);
     }
@@ -1021,7 +1045,7 @@ gsb_status bin_count(const float *means2d, const int32_t *radii, const float *co
     if (n > 0)
         k_bin_count<<<dim3(unsigned((n + 255) / 256)), 256, 0, s>>>(
             reinterpret_cast<const float2 *>(means2d), radii, conics, opacity, mode, n, gx, gy, W,
-            H, counts, at<unsigned long long>(ws, L.masks));
+            H, counts, at<unsigned long long>(ws, L.masks), at<uint4>(ws, L.recs));
     // the total only: offsets are formed in depth order by bin_fill
     launch_scan<unsigned long long>(counts, n, partial, &hdr->total,
                                     reinterpret_cast<long long *>(n_pairs_dev), s, false);
@@ -1050,9 +1074,9 @@ gsb_status bin_fill(const float *means2d, const int32_t *radii, const float *con
     k_bin_init<<<dim3(unsigned((2 * n_tiles + 255) / 256)), 256, 0, s>>>(ranges, 2 * n_tiles,
                                                                        sorts, hdr, n, status_dev);
     // 1. Gaussians by depth (ties by index: the sort is stable over index order); the last pass
-    //    also lays out each Gaussian's pair count in rank order
+    //    also lays out each Gaussian's pair count and emission rectangle in rank order
     sort_depth(depths, dka, dkb, dva, dvb, &hdr->gaussians, n, sorts, sortbuf, status_dev,
-               counts, offs, s);
+               at<uint4>(ws, L.recs), offs, at<unsigned long long>(ws, L.rects), s);
     const uint32_t *sorted_idx = dva;
     // 2. offsets in rank order; pairs emitted in rank order
     launch_scan<unsigned long long>(offs, n, partial64, nullptr, nullptr, s);
@@ -1064,9 +1088,10 @@ gsb_status bin_fill(const float *means2d, const int32_t *radii, const float *con
     // 3. stable sort of the pairs on the tile id; 4. the tiles' ranges
     const auto emit_sort_range = [&](auto *tka, auto *tkb) {
         using K = std::remove_pointer_t<decltype(tka)>;
-        k_bin_fill<K><<<gn, 256, 0, s>>>(reinterpret_cast<const float2 *>(means2d), radii, conics,
+        k_bin_fill<K><<<gn, 256, 0, s>>>(reinterpret_cast<const float2 *>(means2d), conics,
                                          opacity, mode, W, H, sorted_idx, n, gx, gy, offs, counts,
-                                         at<unsigned long long>(ws, L.masks), hdr, cap, tka,
+                                         at<unsigned long long>(ws, L.masks),
+                                         at<unsigned long long>(ws, L.rects), hdr, cap, tka,
                                          v_first, status_dev);
         sort_tiles<K>(tka, tkb, v_first, v_second, &hdr->pairs, cap, tile_bits, sortbuf,
                       partial32, status_dev, s);
