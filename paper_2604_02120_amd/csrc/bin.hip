@@ -752,12 +752,19 @@ __global__ __launch_bounds__(kSortThreads) void k_block_hist(const K *keys,
     __syncthreads();
     const int64_t P = int64_t(*count);
     const int64_t base = int64_t(blockIdx.x) * kSortTile;
-    // four keys per load (order does not matter to a histogram); entries >= P are ignored
+    // four keys per load (order does not matter to a histogram), all loads issued before any is
+    // counted (from index 0 where past P: entries >= P are ignored)
+    uint4 q[kSortItems / 4];
+#pragma unroll
+    for (int k = 0; k < kSortItems / 4; ++k) {
+        const int64_t idx = base + 4 * (int64_t(k) * kSortThreads + t);
+        q[k] = load4(keys, idx < P ? idx : 0);
+    }
 #pragma unroll
     for (int k = 0; k < kSortItems / 4; ++k) {
         const int64_t idx = base + 4 * (int64_t(k) * kSortThreads + t);
         if (idx < P) {
-            const uint4 v = load4(keys, idx);
+            const uint4 v = q[k];
             atomicAdd(&s_h[(v.x >> shift) & (kRadix - 1)], 1u);
             if (idx + 1 < P) atomicAdd(&s_h[(v.y >> shift) & (kRadix - 1)], 1u);
             if (idx + 2 < P) atomicAdd(&s_h[(v.z >> shift) & (kRadix - 1)], 1u);
