@@ -58,6 +58,12 @@ constexpr float kLog2e = 0x1.715476p+0f;    // log2(e) rounded to FP32
 constexpr float kQCull = -0x1.ffa37cp+2f;   // log2(fp32(1/255)) rounded to FP32
 constexpr float kTauCull = 1.0f / 255.0f;
 constexpr float kAlphaMax = 0.99f;
+// The 0.99 clamp applied before the exponential: v_exp_f32 is monotonic near log2(0.99) and
+// returns exactly 0.99f for every input from -0x1.db1f6ep-7 to -0x1.db1eb8p-7 (checked over every
+// FP32 input in [-0.03, -0.014]), so min(2^x, 0.99f) = 2^min(x, kQAlphaMax) bit for bit, one
+// three-way min instead of two mins; 2^x >= 0.99f exactly when x >= kQAlphaMaxLo.
+constexpr float kQAlphaMax = -0x1.db1f16p-7f;     // log2f(0.99f)
+constexpr float kQAlphaMaxLo = -0x1.db1f6ep-7f;
 constexpr float kTStop = 1e-4f;
 constexpr float kLoScale = 4096.0f;         // 2^12
 constexpr float kLoScaleInv = 1.0f / 4096.0f;
@@ -438,7 +444,7 @@ struct FwdState {
 __device__ inline void composite(float q, float lo2o, float cr, float cg, float cb, int pos,
                                  FwdState &st) {
     const bool hit = q >= st.thr;
-    const float a = fminf(__builtin_amdgcn_exp2f(fminf(q, lo2o)), kAlphaMax);
+    const float a = __builtin_amdgcn_exp2f(fminf(fminf(q, lo2o), kQAlphaMax));   // <= 0.99
     const float Tn = st.T * (1.0f - a);
     const bool stop = Tn < kTStop;
     if (hit && !stop) {
@@ -662,8 +668,7 @@ __device__ inline void reverse_pair(float q, bool in_range, const float4 *ga, co
     const float4 attr = ga[u];   // one address for every lane: LDS broadcasts
     const float2 bw = gb[u];
     // a dead lane has q < log2(1/255) or is past its last contributor: it blended nothing here
-    const float araw = __builtin_amdgcn_exp2f(fminf(q, attr.x));
-    const float a = alive ? fminf(araw, kAlphaMax) : 0.f;
+    const float a = alive ? __builtin_amdgcn_exp2f(fminf(fminf(q, attr.x), kQAlphaMax)) : 0.f;
     const float r = __builtin_amdgcn_rcpf(1.0f - a);  // exactly 1 for a dead lane
     const float Tb = st.T * r;                           // T in front of this Gaussian
     const float gc = st.gr * attr.y + st.gg * attr.z + st.gb * attr.w;
@@ -680,12 +685,15 @@ __device__ inline void reverse_pair(float q, bool in_range, const float4 *ga, co
     // touch are zeroed in place: with the 0.99 clamp active dL/dpower is 0, and no gradient
     // reaches the geometry through a clamped (positive) power. (One ballot per compare, kept
     // apart by the empty asm statements, as above.)
-    unsigned long long m_a = __builtin_amdgcn_ballot_w64(!(araw < kAlphaMax));
+    // (The 0.99 clamp is active where min(q, log2 o) >= kQAlphaMaxLo, so only where q is too.)
+    unsigned long long m_a = __builtin_amdgcn_ballot_w64(q >= kQAlphaMaxLo);
     unsigned long long m_q = __builtin_amdgcn_ballot_w64(q > attr.x);
     asm volatile("" : "+s"(m_a));
     asm volatile("" : "+s"(m_q));
     if (((m_a | m_q) & live) != 0ull) {
-        const bool keep_a = araw < kAlphaMax, keep_g = keep_a && !(q > attr.x);
+        // (min(q, log2 o) >= kQAlphaMaxLo, as two compares: the step above keeps its three-way min)
+        const bool keep_a = !(q >= kQAlphaMaxLo && attr.x >= kQAlphaMaxLo);
+        const bool keep_g = keep_a && !(q > attr.x);
 #pragma unroll
         for (int k = 0; k < 5; ++k) s[k] = keep_g ? s[k] : 0.f;
         s[5] = keep_a ? s[5] : 0.f;

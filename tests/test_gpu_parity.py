@@ -218,6 +218,41 @@ def test_backward_parity(gpu, prec, name):
 
 
 @pytest.mark.parametrize("prec", PRECS)
+def test_alpha_clamp(gpu, prec):
+    """The 0.99 clamp of alpha (Eq. (alpha)): the kernels apply it to the exponent's argument,
+    min(2^x, 0.99) = 2^min(x, log2f(0.99f)), which is exact only because the exp2 instruction
+    returns exactly 0.99f there. An opaque Gaussian centred on a pixel must leave exactly
+    1 - 0.99f at it; then a scene of opacities 0.97 to 1 (the clamp active around most centres)
+    against the oracle, image and gradients."""
+    s1 = gsinputs.stack_scene(1, 1.0, at=(8.0, 8.0))
+    sd1 = upload(s1, gpu)
+    pl1, rg1 = api.bin_tiles(sd1["means2d"], sd1["radii"], sd1["depths"], 16, 16)
+    _, T1, last1 = gpu_forward(sd1, pl1, rg1, prec)
+    assert last1[8, 8] == 1
+    assert T1[8, 8] == float(np.float32(1.0) - np.float32(0.99)), T1[8, 8]
+    s = dict(SCENES["C1"])
+    rng = np.random.default_rng(99)
+    s["opacity"] = rng.uniform(0.97, 1.0, len(s["opacity"])).astype(np.float32)
+    W, H = s["width"], s["height"]
+    say(f"[clamp] C1 with opacities in [0.97, 1] {prec}")
+    pl_ref, rg_ref = oracle.bin_tiles(s["means2d"], s["radii"], s["depths"], W, H)
+    ref = oracle.forward(W, H, rg_ref, pl_ref, s["means2d"], s["conics"], s["opacity"], s["colors"])
+    sd = upload(s, gpu)
+    pl, rg = upload_bins(pl_ref, rg_ref, gpu)
+    img, T, last = gpu_forward(sd, pl, rg, prec)
+    if prec == "fp32":
+        check_plain(ref, img, T, last, "clamp")
+    else:
+        check_gemm(ref, img, T, last, prec, "clamp")
+    got, gref = backward_case(s, gpu, prec)
+    bound = PLAIN_GRAD if prec == "fp32" else GEMM_GRAD
+    for k in gref:
+        e = normwise(got[k], gref[k])
+        say(f"  {k}: normwise rel err {e:.3e}")
+        assert e <= bound, (k, e)
+
+
+@pytest.mark.parametrize("prec", PRECS)
 def test_autograd_matches_oracle_on_fd_subscene(gpu, prec):
     """The 32x32, 200-Gaussian subscene whose oracle gradient is pinned to finite differences."""
     s = gsinputs.fd_subscene(33)
