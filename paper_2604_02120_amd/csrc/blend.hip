@@ -445,7 +445,7 @@ __device__ inline void composite(float q, float lo2o, float cr, float cg, float 
                                  FwdState &st) {
     const bool hit = q >= st.thr;
     const float a = __builtin_amdgcn_exp2f(fminf(fminf(q, lo2o), kQAlphaMax));   // <= 0.99
-    const float Tn = st.T * (1.0f - a);
+    const float Tn = fmaf(-a, st.T, st.T);   // T (1 - alpha), rounded once
     const bool stop = Tn < kTStop;
     if (hit && !stop) {
         const float wgt = a * st.T;
