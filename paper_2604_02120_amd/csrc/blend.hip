@@ -671,9 +671,9 @@ __device__ inline void reverse_pair(float q, bool in_range, const float4 *ga, co
     const float a = alive ? __builtin_amdgcn_exp2f(fminf(fminf(q, attr.x), kQAlphaMax)) : 0.f;
     const float r = __builtin_amdgcn_rcpf(1.0f - a);  // exactly 1 for a dead lane
     const float Tb = st.T * r;                           // T in front of this Gaussian
-    const float gc = st.gr * attr.y + st.gg * attr.z + st.gb * attr.w;
     const float wc = a * Tb;                             // the pair's weight alpha T
-    const float gmb = gc - st.beta;                      // dL/dalpha = Tb (c . g - beta)
+    // c . g - beta as one fma chain from -beta: dL/dalpha = Tb (c . g - beta)
+    const float gmb = fmaf(st.gb, attr.w, fmaf(st.gg, attr.z, fmaf(st.gr, attr.y, -st.beta)));
     st.beta = fmaf(a, gmb, st.beta);
     st.T = Tb;
     const float da = wc * gmb;                           // dL/dpower = alpha dL/dalpha
@@ -755,9 +755,8 @@ __device__ inline bool reverse_pair_mm(float q, bool in_range, const float4 *ga,
     const float a = alive ? fminf(araw, kAlphaMax) : 0.f;
     const float r = __builtin_amdgcn_rcpf(1.0f - a);
     const float Tb = st.T * r;
-    const float gc = st.gr * attr.y + st.gg * attr.z + st.gb * attr.w;
     const float wc = a * Tb;
-    const float gmb = gc - st.beta;
+    const float gmb = fmaf(st.gb, attr.w, fmaf(st.gg, attr.z, fmaf(st.gr, attr.y, -st.beta)));
     st.beta = fmaf(a, gmb, st.beta);
     st.T = Tb;
     const float da = araw < kAlphaMax ? wc * gmb : 0.f;
