@@ -6,10 +6,11 @@
 // produced without ever sorting 64-bit tile|depth keys:
 //   1. the Gaussians themselves are sorted by depth (stable LSD radix sort of N 32-bit keys, so
 //      equal depths keep increasing index): this fixes every Gaussian's rank in (depth, index);
-//   2. pairs are emitted in rank order, each with its tile id as a 32-bit key;
+//   2. pairs are emitted in rank order, each with its tile id as key (16-bit when the grid has at
+//      most 65536 tiles, else 32-bit);
 //   3. a stable LSD radix sort of the pairs on the tile id alone (ceil(log2 tiles / 8) passes, 2
 //      up to 65536 tiles) then leaves each tile's pairs in rank order, i.e. (depth, index) order.
-// Against sorting (tile << 32 | depth) pairs directly this moves ~48 instead of ~200 bytes per
+// Against sorting (tile << 32 | depth) pairs directly this moves ~40 instead of ~200 bytes per
 // pair. Everything is integer work and bit-exact: the covered-tile rectangle is evaluated in
 // integer arithmetic (floor((x - r)/16) == (floor(x) - r) >> 4 for integer r).
 #include <hip/hip_runtime.h>
@@ -659,17 +660,20 @@ __global__ __launch_bounds__(256) void k_bin_fill(const float2 *means, const flo
 }
 
 // ------------------------------------------------------------------------------- radix sort
-// Stable LSD radix sort of (u32 key, u32 value) on 8-bit digits, one kernel per pass plus one
-// histogram kernel per sort (a "onesweep" organisation with decoupled look-back):
+// Stable LSD radix sort of (key, u32 value) on 8-bit digits. The depth sort (u32 keys) takes one
+// kernel per pass plus one histogram kernel per sort (a "onesweep" organisation with decoupled
+// look-back):
 //   * k_sort_hist reads the keys once and accumulates the global digit counts of every pass (at
 //     most 256 blocks, so few blocks add into each global count); it also clears the look-back
 //     words of every pass.
-//   * k_onesweep, one launch per pass: each block draws the index of its tile of 4096 keys from
+//   * k_radix_pass<chained>, one launch per pass: each block draws the index of its tile of 4096 keys from
 //     a ticket counter (so a block only ever waits on tiles whose blocks are already running),
 //     ranks its keys stably in LDS, publishes its per-digit counts, and walks back over the
 //     preceding tiles' published words (16 per step) until it meets an inclusive prefix. A digit's global
 //     start is the exclusive scan of the pass's digit counts plus that prefix. Keys are then
 //     written out in digit order (contiguous runs, so the global writes coalesce).
+// The tile sort (u16 or u32 keys, see sort_tiles) runs each pass as a per-block histogram, its
+// scan and k_radix_pass<unchained>, which reads its digit offsets instead of looking back.
 // A look-back word is flag << 30 | value: flag 1 = the tile's own count, 2 = inclusive prefix.
 // Every wait is bounded; an expired wait reports GSB_ERR_INTERNAL in the status word instead of
 // hanging. The element count is read from device memory (*count).
