@@ -700,17 +700,18 @@ __device__ inline void reverse_pair(float q, bool in_range, const float4 *ga, co
     }
     float rab, rc;
     wave_sum9(s, L.l, rab, rc);
-    if ((L.l & 7) == 0) {
-        // acc is this lane's word of the Gaussian's sums (see sum_word); lane 0's is word 0
-        if constexpr (kDet) {
+    if constexpr (kDet) {
+        if ((L.l & 7) == 0) {
+            // acc is this lane's word of the Gaussian's sums (see sum_word); lane 0's is word 0
             *acc = rab;
             if (L.l == 0) acc[8] = rc;
-        } else {
-            atomicAdd(acc, rab);
-            if (L.l == 0) {
-                atomicAdd(acc + 8, rc);
-                *hit = 1u;
-            }
+        }
+    } else {
+        // one LDS atomic for all nine sums: lane 1 adds s8 (its acc points at word 8)
+        const float val = L.l == 1 ? rc : rab;
+        if ((L.l & 7) == 0 || L.l == 1) {
+            atomicAdd(acc, val);
+            if (L.l == 0) *hit = 1u;
         }
     }
 }
@@ -1061,7 +1062,8 @@ __device__ inline void bwd_tile(const ViewDesc &v, int64_t tile, Stage<M, NB> &S
             // the group's sums, Gaussian 0 (deterministic: this wavefront's slice)
             float *accw = kDet ? det->v[buf][L.w] + g * kGroup * kGrad
                                : acc_->slot(buf, g * kGroup);
-            float *acc = accw + (kMM ? 0 : word);   // this lane's word (VALU reduction)
+            // this lane's word (VALU reduction; with atomics lane 1 adds word 8)
+            float *acc = accw + (kMM ? 0 : !kDet && L.l == 1 ? 8 : word);
             int hslot = buf * NB + slot0;      // (likewise for the flags, written in a branch)
             asm volatile("" : "+v"(hslot));
             uint8_t *hit = kDet ? nullptr : reinterpret_cast<uint8_t *>(acc_->hit) + hslot;
