@@ -148,9 +148,7 @@ __device__ inline float opacity_grad(float sum, float o) { return o >= kTauCull 
 template <int NB>
 struct BwdAcc {
     float v[2][NB * kGrad];
-    // whether a slot received any sum (set by the wavefronts that add into it), and each
-    // wavefront's list of its touched slots, built when it flushes
-    uint8_t hit[2][NB];
+    // each wavefront's list of the slots with a nonzero sum, built when it flushes
     uint16_t list[kBlock / 64][64];
     __device__ float *slot(int ab, int t) { return v[ab] + t * kGrad; }
 };
@@ -637,18 +635,17 @@ struct BwdState {
 // state is unchanged exactly, since 1 / (1 - 0) = 1),
 // the pair's 9 gradient terms are summed over the wavefront, and the totals are added into the
 // Gaussian's LDS accumulator (`acc` points at the word this lane adds when it leads, see
-// sum_word; the flag `hit` is set), which the block flushes to global memory once per batch. Raw
+// sum_word), which the block flushes to global memory once per batch. Raw
 // sums: S_xx, S_xy, S_yy, S_x, S_y (times dL/dpower), the sum of dL/dpower without the clamp test
 // (o dL/do: the final pass divides it by o, once per Gaussian instead of once per pair), and the
 // three colour gradients.
 // kRanged = false: the caller has checked that the whole group lies before every lane's last
 // contributor, so the skip test alone decides (one compare, whose mask is the ballot).
 // kDet: `acc` points into the wavefront's own slice of the batch's sums, which this Gaussian's
-// totals are stored into (no other wavefront writes there), so no atomic and no flag.
+// totals are stored into (no other wavefront writes there), so no atomic.
 template <bool kRanged, bool kDet = false>
 __device__ inline void reverse_pair(float q, bool in_range, const float4 *ga, const float2 *gb,
-                                    int u, const Lane &L, BwdState &st, float *acc,
-                                    uint8_t *hit) {
+                                    int u, const Lane &L, BwdState &st, float *acc) {
     const bool alive = kRanged ? (in_range && q >= kQCull) : (q >= kQCull);
     unsigned long long live;
     if constexpr (kRanged) {
@@ -709,10 +706,7 @@ __device__ inline void reverse_pair(float q, bool in_range, const float4 *ga, co
     } else {
         // one LDS atomic for all nine sums: lane 1 adds s8 (its acc points at word 8)
         const float val = L.l == 1 ? rc : rab;
-        if ((L.l & 7) == 0 || L.l == 1) {
-            atomicAdd(acc, val);
-            if (L.l == 0) *hit = 1u;
-        }
+        if ((L.l & 7) == 0 || L.l == 1) atomicAdd(acc, val);
     }
 }
 
@@ -737,7 +731,7 @@ __device__ inline float wave_sum4(const float (&s)[4]) {
 template <bool kRanged>
 __device__ inline bool reverse_pair_mm(float q, bool in_range, const float4 *ga, const float2 *gb,
                                        int u, const Lane &L, BwdState &st, float *acc,
-                                       uint8_t *hit, uint32_t *dgrow) {
+                                       uint32_t *dgrow) {
     const bool alive = kRanged ? (in_range && q >= kQCull) : (q >= kQCull);
     unsigned long long live;
     if constexpr (kRanged) {
@@ -769,10 +763,8 @@ __device__ inline bool reverse_pair_mm(float q, bool in_range, const float4 *ga,
     dgrow[L.l] = __builtin_bit_cast(uint32_t, pk);
     const float s[4] = {da, wc * st.gr, wc * st.gg, wc * st.gb};
     const float tot = wave_sum4(s);
-    if ((L.l & 15) == 0) {
+    if ((L.l & 15) == 0)
         atomicAdd(acc + 5 + ((L.l >> 4) == 1 ? 2 : (L.l >> 4) == 2 ? 1 : (L.l >> 4)), tot);
-        if (L.l == 0) *hit = 1u;
-    }
     return true;
 }
 
@@ -944,12 +936,12 @@ __device__ inline void bwd_tile(const ViewDesc &v, int64_t tile, Stage<M, NB> &S
         return load_entry(plist, start + o, bb >= 0 && L.t < NB && o < len, start);
     };
     // Wavefront w flushes slots [w NB/4, (w + 1) NB/4). It lists the slots that
-    // received a sum, in slot order, and then spreads their nine sums over its lanes, item j the
-    // sum j % 9 of listed slot j / 9, so that consecutive lanes add consecutive words of one
-    // Gaussian (a wavefront's atomic instruction reaches about 30 cache lines instead of 64) and
-    // no lane is spent on the slots without a sum (over half of a 3-sigma list's). Each item is
-    // zeroed by the lane that reads it, and each flag by the lane that lists it, ready for batch
-    // bb - 2, which reuses the buffers after the next barrier.
+    // received a nonzero sum, in slot order, and then spreads their nine sums over its lanes,
+    // item j the sum j % 9 of listed slot j / 9, so that consecutive lanes add consecutive words
+    // of one Gaussian (a wavefront's atomic instruction reaches about 30 cache lines instead of
+    // 64) and no lane is spent on the slots without a sum (over half of a 3-sigma list's). Each
+    // item is zeroed by the lane that reads it (an unlisted slot's sums are all +-0 already),
+    // ready for batch bb - 2, which reuses the buffers after the next barrier.
     // Deterministic form: word k < 9 of slot i's row is the four wavefronts' sum k added in
     // wavefront order (and zeroed in the slices), words 9..15 are zero; the row is stored at list
     // position start + bb NB + i (consecutive threads, consecutive words).
@@ -981,14 +973,18 @@ __device__ inline void bwd_tile(const ViewDesc &v, int64_t tile, Stage<M, NB> &S
         BwdAcc<NB> &s_acc = *acc_;
         constexpr int kPer = NB / (kBlock / 64);   // slots per wavefront, at most 64
         float *acc = s_acc.v[bb & 1];
-        uint8_t *hit = s_acc.hit[bb & 1];
         const uint32_t *ids = SB.ids[bb % 3];
         uint16_t *list = s_acc.list[L.w];
         const int s0 = L.w * kPer;
+        // a slot is listed if any of its nine sums is nonzero (NaN included); one whose sums
+        // are all +-0 adds nothing to the gradients, whether or not a pair reached it
         bool touched = false;
         if (L.l < kPer) {
-            touched = hit[s0 + L.l] != 0u;
-            hit[s0 + L.l] = 0u;
+            const float *p = acc + (s0 + L.l) * kGrad;
+            uint32_t bits = 0u;
+#pragma unroll
+            for (int k = 0; k < kGrad; ++k) bits |= __float_as_uint(p[k]) & 0x7fffffffu;
+            touched = bits != 0u;
         }
         const unsigned long long m = __ballot(touched);
         if (touched) list[__popcll(m & ((1ull << L.l) - 1ull))] = uint16_t(s0 + L.l);
@@ -1027,10 +1023,6 @@ __device__ inline void bwd_tile(const ViewDesc &v, int64_t tile, Stage<M, NB> &S
             acc_->v[0][e] = 0.f;
             acc_->v[1][e] = 0.f;
         }
-        if (L.t < NB) {
-            acc_->hit[0][L.t] = 0u;
-            acc_->hit[1][L.t] = 0u;
-        }
     }
     for (int b = nb - 1; b >= 0; --b) {
         const int buf = b & 1;
@@ -1064,9 +1056,6 @@ __device__ inline void bwd_tile(const ViewDesc &v, int64_t tile, Stage<M, NB> &S
                                : acc_->slot(buf, g * kGroup);
             // this lane's word (VALU reduction; with atomics lane 1 adds word 8)
             float *acc = accw + (kMM ? 0 : !kDet && L.l == 1 ? 8 : word);
-            int hslot = buf * NB + slot0;      // (likewise for the flags, written in a branch)
-            asm volatile("" : "+v"(hslot));
-            uint8_t *hit = kDet ? nullptr : reinterpret_cast<uint8_t *>(acc_->hit) + hslot;
             const int rel = st.last - (base + g * kGroup);   // positions < last are in range
             // the whole group is in range for every lane (the common case once past the lanes'
             // last contributors; never for a partial tile, whose outside lanes have last = 0)
@@ -1088,7 +1077,7 @@ __device__ inline void bwd_tile(const ViewDesc &v, int64_t tile, Stage<M, NB> &S
                             const int u = 8 * h + i;
                             if (((reach >> u) & 1u) == 0u) continue;
                             if (reverse_pair_mm<false>(q_of(u), true, ga, gb, u, L, st,
-                                                       acc + u * kGrad, hit + u, rows[i]))
+                                                       acc + u * kGrad, rows[i]))
                                 hmask |= 1u << i;
                         }
                     } else {
@@ -1097,7 +1086,7 @@ __device__ inline void bwd_tile(const ViewDesc &v, int64_t tile, Stage<M, NB> &S
                             const int u = 8 * h + i;
                             if (((reach >> u) & 1u) == 0u) continue;
                             if (reverse_pair_mm<true>(q_of(u), u < rel, ga, gb, u, L, st,
-                                                      acc + u * kGrad, hit + u, rows[i]))
+                                                      acc + u * kGrad, rows[i]))
                                 hmask |= 1u << i;
                         }
                     }
@@ -1108,15 +1097,13 @@ __device__ inline void bwd_tile(const ViewDesc &v, int64_t tile, Stage<M, NB> &S
 #pragma unroll
                 for (int u = kGroup - 1; u >= 0; --u) {
                     if (((reach >> u) & 1u) == 0u) continue;
-                    reverse_pair<false, kDet>(q_of(u), true, ga, gb, u, L, st, acc + u * kGrad,
-                                              hit + u);
+                    reverse_pair<false, kDet>(q_of(u), true, ga, gb, u, L, st, acc + u * kGrad);
                 }
             } else {
 #pragma unroll
                 for (int u = kGroup - 1; u >= 0; --u) {
                     if (((reach >> u) & 1u) == 0u) continue;
-                    reverse_pair<true, kDet>(q_of(u), u < rel, ga, gb, u, L, st, acc + u * kGrad,
-                                             hit + u);
+                    reverse_pair<true, kDet>(q_of(u), u < rel, ga, gb, u, L, st, acc + u * kGrad);
                 }
             }
         }
