@@ -218,6 +218,54 @@ def test_backward_parity(gpu, prec, name):
 
 
 @pytest.mark.parametrize("prec", PRECS)
+def test_backward_sparse_and_zero_upstream_gradient(gpu, prec):
+    """The block flushes a Gaussian's per-batch sums only if one of them is nonzero. An upstream
+    gradient on three pixels leaves almost every reached Gaussian with sums of exactly zero: the
+    gradients must still match the oracle's (normwise) and be exactly zero for every Gaussian
+    listed in none of the three pixels' tiles; a zero upstream gradient must give exactly zero
+    gradients, also when the output buffers hold an earlier call's values."""
+    s = SCENES["lognormal"]
+    W, H = s["width"], s["height"]
+    bg = (0.1, 0.3, 0.2)
+    say(f"[bwd sparse] lognormal {prec}")
+    pl_ref, rg_ref = oracle.bin_tiles(s["means2d"], s["radii"], s["depths"], W, H)
+    g = np.zeros((3, H, W), np.float32)
+    # Gaussians listed in none of the three pixels' tiles cannot reach them on any path
+    untouched = np.ones(s["opacity"].shape[0], bool)
+    gx = (W + 15) // 16
+    for (y, x, c, v) in [(3, 5, 0, 1.0), (H // 2, W // 2, 1, -2.0), (H - 1, W - 1, 2, 0.5)]:
+        g[c, y, x] = v
+        t = (y // 16) * gx + x // 16
+        untouched[pl_ref[int(rg_ref[t][0]):int(rg_ref[t][1])]] = False
+    ref = oracle.backward(W, H, rg_ref, pl_ref, s["means2d"], s["conics"], s["opacity"],
+                          s["colors"], g, bg)
+    sd = upload(s, gpu)
+    pl, rg = upload_bins(pl_ref, rg_ref, gpu)
+    img, T, last = api.blend_forward(sd["means2d"], sd["conics"], sd["opacity"], sd["colors"], rg,
+                                     pl, W, H, bg, prec)
+    out = api.blend_backward(sd["means2d"], sd["conics"], sd["opacity"], sd["colors"], rg, pl, W,
+                             H, T, last, torch.from_numpy(g).to(gpu), bg, prec)
+    torch.cuda.synchronize()
+    bound = plain_grad_bound("lognormal") if prec == "fp32" else GEMM_GRAD
+    names = ["dmeans2d", "dconics", "dopacity", "dcolors"]
+    for k, v in zip(names, out):
+        got = v.cpu().numpy().astype(np.float64)
+        e = normwise(got, ref[k])
+        say(f"  {k}: normwise rel err {e:.3e}")
+        assert e <= bound, (k, e)
+    assert untouched.sum() > 0.5 * len(untouched)
+    for k, v in zip(names, out):
+        got = v.cpu().numpy().reshape(len(untouched), -1)
+        assert np.all(got[untouched] == 0.0), k
+    zero = torch.zeros((3, H, W), dtype=torch.float32, device=gpu)
+    out2 = api.blend_backward(sd["means2d"], sd["conics"], sd["opacity"], sd["colors"], rg, pl, W,
+                              H, T, last, zero, bg, prec, out=out)
+    torch.cuda.synchronize()
+    for k, v in zip(names, out2):
+        assert torch.count_nonzero(v).item() == 0, k
+
+
+@pytest.mark.parametrize("prec", PRECS)
 def test_alpha_clamp(gpu, prec):
     """The 0.99 clamp of alpha (Eq. (alpha)): the kernels apply it to the exponent's argument,
     min(2^x, 0.99) = 2^min(x, log2f(0.99f)), which is exact only because the exp2 instruction
