@@ -689,8 +689,12 @@ __device__ inline void reverse_pair(float q, bool in_range, const float4 *ga, co
     asm volatile("" : "+s"(m_q));
     if (((m_a | m_q) & live) != 0ull) {
         // (min(q, log2 o) >= kQAlphaMaxLo, as two compares: the step above keeps its three-way min)
-        const bool keep_a = !(q >= kQAlphaMaxLo && attr.x >= kQAlphaMaxLo);
-        const bool keep_g = keep_a && !(q > attr.x);
+        // The lane predicates are read back from the two masks: recomparing q would make the
+        // compiler keep each compare's result beside its ballot, a scalar copy per live pair.
+        const bool clamp_a = ((m_a >> L.l) & 1ull) != 0ull;
+        const bool clamp_q = ((m_q >> L.l) & 1ull) != 0ull;
+        const bool keep_a = !(clamp_a && attr.x >= kQAlphaMaxLo);
+        const bool keep_g = keep_a && !clamp_q;
 #pragma unroll
         for (int k = 0; k < 5; ++k) s[k] = keep_g ? s[k] : 0.f;
         s[5] = keep_a ? s[5] : 0.f;
