@@ -646,19 +646,23 @@ struct BwdState {
 template <bool kRanged, bool kDet = false>
 __device__ inline void reverse_pair(float q, bool in_range, const float4 *ga, const float2 *gb,
                                     int u, const Lane &L, BwdState &st, float *acc) {
-    const bool alive = kRanged ? (in_range && q >= kQCull) : (q >= kQCull);
+    bool alive;
     unsigned long long live;
     if constexpr (kRanged) {
         // one ballot per compare (each is just that compare's lane mask), combined and tested in
         // scalar registers: a ballot of the combined condition is copied through a vector
         // register, two more vector instructions for every Gaussian of a ranged group. The empty
-        // asm statements keep the compiler from merging the two ballots back into one.
+        // asm statements keep the compiler from merging the two ballots back into one, and the
+        // lane's own condition is read back from the combined mask (with the compares reused,
+        // each mask is copied beside its ballot: two scalar moves per visit).
         unsigned long long m_range = __builtin_amdgcn_ballot_w64(in_range);
         unsigned long long m_cull = __builtin_amdgcn_ballot_w64(q >= kQCull);
         asm volatile("" : "+s"(m_range));
         asm volatile("" : "+s"(m_cull));
         live = m_range & m_cull;
+        alive = __builtin_amdgcn_inverse_ballot_w64(live);
     } else {
+        alive = q >= kQCull;
         live = __builtin_amdgcn_ballot_w64(alive);
     }
     if (live == 0ull) return;
@@ -691,8 +695,8 @@ __device__ inline void reverse_pair(float q, bool in_range, const float4 *ga, co
         // (min(q, log2 o) >= kQAlphaMaxLo, as two compares: the step above keeps its three-way min)
         // The lane predicates are read back from the two masks: recomparing q would make the
         // compiler keep each compare's result beside its ballot, a scalar copy per live pair.
-        const bool clamp_a = ((m_a >> L.l) & 1ull) != 0ull;
-        const bool clamp_q = ((m_q >> L.l) & 1ull) != 0ull;
+        const bool clamp_a = __builtin_amdgcn_inverse_ballot_w64(m_a);
+        const bool clamp_q = __builtin_amdgcn_inverse_ballot_w64(m_q);
         const bool keep_a = !(clamp_a && attr.x >= kQAlphaMaxLo);
         const bool keep_g = keep_a && !clamp_q;
 #pragma unroll
@@ -736,7 +740,7 @@ template <bool kRanged>
 __device__ inline bool reverse_pair_mm(float q, bool in_range, const float4 *ga, const float2 *gb,
                                        int u, const Lane &L, BwdState &st, float *acc,
                                        uint32_t *dgrow) {
-    const bool alive = kRanged ? (in_range && q >= kQCull) : (q >= kQCull);
+    bool alive;
     unsigned long long live;
     if constexpr (kRanged) {
         unsigned long long m_range = __builtin_amdgcn_ballot_w64(in_range);
@@ -744,7 +748,9 @@ __device__ inline bool reverse_pair_mm(float q, bool in_range, const float4 *ga,
         asm volatile("" : "+s"(m_range));
         asm volatile("" : "+s"(m_cull));
         live = m_range & m_cull;
+        alive = __builtin_amdgcn_inverse_ballot_w64(live);
     } else {
+        alive = q >= kQCull;
         live = __builtin_amdgcn_ballot_w64(alive);
     }
     if (live == 0ull) return false;
