@@ -43,6 +43,7 @@
 #include <math.h>
 
 #include <algorithm>
+#include <cstddef>
 #include <type_traits>
 #include <vector>
 
@@ -108,11 +109,12 @@ template <Mode M, int NB>
 struct Stage {                 // GEMM form
     typedef typename Op<M>::vec vec;
     vec ahi[2][NB];            // v_g hi terms, 5 used of 8
+    vec zero_hi;               // zeros: the A operand of the lanes off the block diagonal
     vec alo[2][NB];            // v_g lo terms * 2^12
+    vec zero_lo;               // zeros, as far from zero_hi as alo[b][i] is from ahi[b][i]
     float kc[2][NB];           // accumulator init: constant term + log2 o (-inf = inert)
     float4 attr[2][NB];        // (log2 o, r, g, b)
     alignas(16) uint32_t live[2][4];   // forward: whether wavefront w still has a live pixel
-    vec zero;
 };
 template <int NB>
 struct Stage<Mode::Plain, NB> {  // plain form
@@ -399,7 +401,10 @@ __device__ inline void pixel_basis(const Lane &L, typename Op<M>::vec &bhi, type
 }
 
 // q for 16 consecutive staged Gaussians (group g of buffer buf): one value per register.
-template <Mode M, int NB>
+// kOnePtr: address the A operands through one per-lane pointer (below); otherwise through a
+// select per operand, which holds fewer registers (the forward's 64 keep it at 8 wavefronts per
+// SIMD, the one-pointer form's 70 would not).
+template <Mode M, int NB, bool kOnePtr>
 __device__ inline f16x group_q_mfma(const Stage<M, NB> &S, int buf, int g, const Lane &L,
                                     const typename Op<M>::vec &bhi,
                                     const typename Op<M>::vec &blo) {
@@ -410,9 +415,27 @@ __device__ inline f16x group_q_mfma(const Stage<M, NB> &S, int buf, int g, const
         const float4 k = kc4[j];
         acc[4 * j + 0] = k.x; acc[4 * j + 1] = k.y; acc[4 * j + 2] = k.z; acc[4 * j + 3] = k.w;
     }
-    const typename Op<M>::vec *ph = L.a_valid ? &S.ahi[buf][g * kGroup + L.a_g] : &S.zero;
-    const typename Op<M>::vec *pl = L.a_valid ? &S.alo[buf][g * kGroup + L.a_g] : &S.zero;
-    const typename Op<M>::vec ah = *ph, al = *pl;
+    typedef typename Op<M>::vec vec;
+    vec ah, al;
+    if constexpr (kOnePtr) {
+        // One address per lane: a lane off the diagonal reads zero_hi and zero_lo whatever buf
+        // and g are (its steps are 0), and every lane's lo operand lies at one fixed offset from
+        // its hi operand, so the lo read takes no address arithmetic of its own (the selects
+        // depend on the lane only and leave the loops): one vector instruction per group instead
+        // of five.
+        const vec *base = L.a_valid ? &S.ahi[0][L.a_g] : &S.zero_hi;
+        const int bstep = L.a_valid ? NB : 0, gstep = L.a_valid ? kGroup : 0;
+        const vec *ph = base + buf * bstep + g * gstep;
+        typedef Stage<M, NB> St;
+        constexpr size_t kLoOff = offsetof(St, alo) - offsetof(St, ahi);
+        static_assert(offsetof(St, zero_lo) - offsetof(St, zero_hi) == kLoOff,
+                      "zero_lo must mirror zero_hi");
+        ah = *ph;
+        al = *reinterpret_cast<const vec *>(reinterpret_cast<const char *>(ph) + kLoOff);
+    } else {
+        ah = *(L.a_valid ? &S.ahi[buf][g * kGroup + L.a_g] : &S.zero_hi);
+        al = *(L.a_valid ? &S.alo[buf][g * kGroup + L.a_g] : &S.zero_hi);
+    }
     acc = Op<M>::mfma(ah, bhi, acc);
     acc = Op<M>::mfma(al, blo, acc);
     return acc;
@@ -491,7 +514,7 @@ __device__ inline void fwd_tile(const ViewDesc &v, int64_t tile, Stage<M, NB> &S
     pixel_basis<M>(L, bhi, blo);
     if (L.t == 0) {
         float z[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
-        if constexpr (M != Mode::Plain) S.zero = Op<M>::cvt(z);
+        if constexpr (M != Mode::Plain) S.zero_hi = S.zero_lo = Op<M>::cvt(z);
     }
     const uint2 rg = reinterpret_cast<const uint2 *>(v.ranges)[tile];
     // without Gaussians every list entry would be invalid: the tile shows the background
@@ -539,7 +562,7 @@ __device__ inline void fwd_tile(const ViewDesc &v, int64_t tile, Stage<M, NB> &S
                 composite_group(attr, base + g * kGroup, reach, st,
                                 [&](int u) { return plain_q(S, buf, g * kGroup + u, L); });
             } else {
-                const f16x q = group_q_mfma<M, NB>(S, buf, g, L, bhi, blo);
+                const f16x q = group_q_mfma<M, NB, false>(S, buf, g, L, bhi, blo);
                 composite_group(attr, base + g * kGroup, reach, st, [&](int u) { return q[u]; });
             }
         }
@@ -892,7 +915,7 @@ __device__ inline void bwd_tile(const ViewDesc &v, int64_t tile, Stage<M, NB> &S
     pixel_basis<M>(L, bhi, blo);
     if (L.t == 0) {
         float z[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
-        if constexpr (M != Mode::Plain) S.zero = Op<M>::cvt(z);
+        if constexpr (M != Mode::Plain) S.zero_hi = S.zero_lo = Op<M>::cvt(z);
         s_maxlast = 0;
     }
     h8 mmB[2];
@@ -1071,7 +1094,7 @@ __device__ inline void bwd_tile(const ViewDesc &v, int64_t tile, Stage<M, NB> &S
             // last contributors; never for a partial tile, whose outside lanes have last = 0)
             const bool whole = __builtin_amdgcn_ballot_w64(rel < kGroup) == 0ull;
             f16x qm;
-            if constexpr (M != Mode::Plain) qm = group_q_mfma<M, NB>(S, buf, g, L, bhi, blo);
+            if constexpr (M != Mode::Plain) qm = group_q_mfma<M, NB, true>(S, buf, g, L, bhi, blo);
             const auto q_of = [&](int u) {
                 if constexpr (M == Mode::Plain) return plain_q(S, buf, slot0 + u, L);
                 else return qm[u];
